@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched quadrotor environment step on one MI355X.
+
+One bench step = one whole rollout of the headline workload: 65536
+domain-randomised envs x 1000 env steps (observation, actor MLP, RK4,
+reward, termination, in-kernel reset) in the autotuned fused kernel, inputs
+resident in HBM.  value = env-steps/s.  Also reported: the plain five-kernel
+per-step path on the same batch, the fused kernel launched once per step, the
+roofline fraction of the dominant kernel (HIP events on the launch stream),
+and the FP64 oracle timed on the host cores over a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+METRIC = "env-steps/s @65536 envs (fused vs plain) + fwd+bwd steps/s; err vs FP64 oracle"
+
+# Algorithmic work per env step of the forward path: actor MACs
+# (146*64 + 64*64 + 64*4 = 13696, i.e. 27392 FLOP) plus ~1.1 kFLOP for
+# observation, action map, four dynamics evaluations, RK4 combination,
+# renormalisation and reward.
+FLOP_PER_ENV_STEP = 28_500
+PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fwd65536_dr")
+    ap.add_argument("--plain-steps", type=int, default=100,
+                    help="env steps per timed plain-path rollout")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plain / per-step comparison legs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu"],
+                    help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
+                         "per rollout (used for profiling so only timed launches appear)")
+    return ap.parse_args()
+
+
+def time_rollouts(torch, sim, actor, T, K, W):
+    """W warm-up rollouts, then K timed rollouts bracketed by synchronisation;
+    HIP events on the launch stream give the device time."""
+    for _ in range(W):
+        sim.rollout(actor, T, rewards=False, dones=False)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(K):
+        sim.rollout(actor, T, rewards=False, dones=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    _, launches = sim.last_rollout_timing()
+    return wall, dev_ms, launches
+
+
+def cpu_baseline(cfg, W, seconds):
+    """FP64 oracle on a bounded sample of the same workload (env ids spread
+    over the batch), all host threads."""
+    import oracle
+    oracle.build(force=False)
+    nthreads = min(os.cpu_count() or 1, 64)
+    N = cfg["n_envs"]
+    probe_ids = np.linspace(0, N - 1, nthreads * 4).astype(np.uint32)
+    b = oracle.Batch.init(cfg, len(probe_ids), ids=probe_ids)
+    t0 = time.perf_counter()
+    b.rollout(W, 20, nthreads=nthreads)
+    rate = len(probe_ids) * 20 / max(time.perf_counter() - t0, 1e-6)
+    steps = 200
+    n = int(max(nthreads, min(N, rate * seconds / steps)))
+    ids = np.linspace(0, N - 1, n).astype(np.uint32)
+    b = oracle.Batch.init(cfg, n, ids=ids)
+    t0 = time.perf_counter()
+    b.rollout(W, steps, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "env-steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} of {N} envs x {steps} steps (same config, seeds, env ids), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the environment batch is one GPU's share and "
+              "this build has no multi-GPU path (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2311_13081_amd as pkg
+
+    name = args.workload
+    cfg = wl.workload_config(name)
+    T = wl.workload_steps(name)
+    N = cfg["n_envs"]
+    W = wl.xavier_actor(0)
+
+    sim = pkg.QuadSim(cfg)
+    actor = sim.actor_tensor(W)
+    if args.variant == "auto":
+        sim.autotune(actor, T)
+    else:
+        sim.set_variant(pkg.SIM_V_FUSED_MFMA if args.variant == "mfma" else pkg.SIM_V_FUSED_VALU,
+                        0, True)
+    v, spl, graph = sim.get_variant()
+    wall, dev_ms, launches = time_rollouts(torch, sim, actor, T, args.steps, args.warmup)
+    env_steps = N * T * args.steps
+    value = env_steps / wall
+    ms_per_step = wall * 1e3 / args.steps
+    kernel_ms = dev_ms / (args.steps * launches)
+    flop_per_launch = FLOP_PER_ENV_STEP * N * (T / launches)
+    achieved = flop_per_launch / (kernel_ms * 1e-3)
+    vname = {1: "plain", 2: "fused_valu", 3: "fused_mfma"}[v]
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "n_envs": N, "rollout_steps": T, "dr": bool(cfg["dr_enable"]),
+                   "terminate_autoreset": True, "variant": vname, "steps_per_launch": spl,
+                   "hipgraph": bool(graph), "launches_per_step": launches},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "kernel": f"k_fused<{'MFMA' if v == 3 else 'VALU'}>",
+                     "kernel_ms": kernel_ms, "flop_per_env_step": FLOP_PER_ENV_STEP},
+    }
+    if not args.no_extras:
+        extras = {}
+        # plain five-kernel step, graph-captured and eager, on the same batch
+        for label, use_graph in (("plain_graph", True), ("plain_eager", False)):
+            s2 = pkg.QuadSim(cfg)
+            s2.set_variant(pkg.SIM_V_PLAIN, 0, use_graph)
+            w2, d2, _ = time_rollouts(torch, s2, actor, args.plain_steps, 2, 1)
+            extras[label] = {"env_steps_per_s": N * args.plain_steps * 2 / w2,
+                             "ms_per_env_step": w2 * 1e3 / (2 * args.plain_steps)}
+            s2.close()
+        # fused kernel launched once per env step
+        s3 = pkg.QuadSim(cfg)
+        s3.set_variant(pkg.SIM_V_FUSED_MFMA, 1, True)
+        w3, _, _ = time_rollouts(torch, s3, actor, args.plain_steps, 2, 1)
+        extras["fused_per_step_launch"] = {"env_steps_per_s": N * args.plain_steps * 2 / w3,
+                                           "ms_per_env_step": w3 * 1e3 / (2 * args.plain_steps)}
+        s3.close()
+        extras["fused_vs_plain_speedup"] = value / extras["plain_graph"]["env_steps_per_s"]
+        res["comparison"] = extras
+    sim.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(cfg, W, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * quadsim.h -- C ABI of the MI355X batched quadrotor environment.
+ *
+ * The library advances N independent quadrotors.  Each one is the Markov
+ * decision process of "Learning to Fly in Seconds" (Eschmann, Albani,
+ * Loianno, IEEE RA-L 2024), Sec. IV (Methodology):
+ *   state s = {p, q, v, w, w_m} (17 floats: position, unit quaternion
+ *     (w,x,y,z), linear velocity, body angular velocity, 4 rotor speeds in
+ *     RPM), integrated with classical RK4 at the configured dt (100 Hz in
+ *     Sec. V, Simulation);
+ *   actor observation {p, R(q) row-major, v, w, H} with H the last 32 actions
+ *     oldest first, 18 + 4*32 = 146 inputs (Sec. IV);
+ *   actor MLP 146-64-64-4, ReLU, ReLU, tanh; action a in (-1,1)^4 mapped to
+ *     RPM set points u = rpm_min + (a+1)/2 (rpm_max - rpm_min) (Sec. IV);
+ *   rotors: thrust c0 + c1 w + c2 w^2, first-order lag with time constant T_m
+ *     (Sec. IV and the taxonomy of Sec. II, levels 4.3 and 5.1);
+ *   reward r = -C_rp|p|^2 - C_rq(1-q_w^2) - C_rv|v|^2 - C_rw|w|^2
+ *              - C_ra|a - C_rab|^2 + C_rs on the post-step state (Sec. IV);
+ *   termination when any |p_i| > pos_limit, any |v_i| > vel_limit or the state
+ *     is not finite (the box around the origin of Sec. V, Training);
+ *     truncation at max_episode_steps; optional in-kernel reset.
+ *
+ * Conventions for every call:
+ *   - Pointers named "dev" are device pointers on the handle's device; all
+ *     device buffers use struct-of-arrays layouts: element (k, env) of a
+ *     [K][N] array is at k*N + env.
+ *   - The caller owns every pointer it passes; the library never frees them
+ *     and keeps none after the call returns.  The handle owns all internal
+ *     device memory (state, history, parameters, tape, scratch).
+ *   - Every call returns SIM_OK (0) or a negative sim_status and never throws.
+ *     Argument errors are detected before any work is queued.  Device errors
+ *     (including asynchronous ones from earlier work) map to SIM_E_DEVICE.
+ *     sim_last_error() gives a message for the calling thread's last error.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *     All work is queued on it and calls return without synchronising, except
+ *     sim_create, sim_destroy and sim_autotune, which synchronise.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef QUADSIM_H
+#define QUADSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SIM_NSTATE = 17,   /* p(3) q(4) v(3) w(3) w_m(4)                                  */
+  SIM_NHIST = 32,    /* action history length N_H                                   */
+  SIM_NACT = 4,      /* normalised actions / RPM set points                         */
+  SIM_NOBS = 146,    /* 18 + 4 * N_H                                                */
+  SIM_NHID = 64,     /* hidden width                                                */
+  SIM_NPARAM = 8,    /* m, Jxx, Jyy, Jzz, c0, c1, c2, T_m                            */
+  SIM_NACTOR = 13828 /* [W1 64x146 | b1 64 | W2 64x64 | b2 64 | W3 4x64 | b3 4]      */
+};
+
+typedef enum sim_status {
+  SIM_OK = 0,
+  SIM_E_INVAL = -1,       /* bad argument                                        */
+  SIM_E_NOMEM = -2,       /* device allocation failed                            */
+  SIM_E_DEVICE = -3,      /* HIP error, no device, or a launch failed            */
+  SIM_E_STATE = -4,       /* call not valid in the handle's current state        */
+  SIM_E_UNSUPPORTED = -5  /* option not available in this build                  */
+} sim_status;
+
+enum {
+  SIM_F_TERMINATE = 1,  /* end episodes that leave the box or become non-finite */
+  SIM_F_AUTORESET = 2,  /* reset ended episodes inside the step                  */
+  SIM_F_RENORM_Q = 4    /* renormalise the quaternion after each step           */
+};
+
+/* Execution variants of the forward step. */
+enum {
+  SIM_V_AUTO = 0,        /* the autotuned choice (fused MFMA until tuned)         */
+  SIM_V_PLAIN = 1,       /* five kernels per step, intermediates through HBM      */
+  SIM_V_FUSED_VALU = 2,  /* one fused kernel, actor on the vector ALUs            */
+  SIM_V_FUSED_MFMA = 3   /* one fused kernel, actor on fp32 matrix cores          */
+};
+
+typedef struct sim_config {
+  int32_t n_envs;            /* N >= 1                                               */
+  int32_t max_episode_steps; /* truncation cap (0 = none)                            */
+  int32_t flags;             /* SIM_F_*                                              */
+  int32_t dr_enable;         /* 1: per-env parameters = nominal * U(dr_lo, dr_hi)    */
+  int32_t max_tape_horizon;  /* longest differentiable rollout (0 = none)            */
+  int32_t ckpt_every;        /* checkpoint interval K of the tape (>= 1)             */
+  int32_t reserved0, reserved1;
+  double dt, g, arm, k_m, rpm_min, rpm_max; /* s, m/s^2, m, m (yaw moment / thrust), RPM */
+  double nominal[SIM_NPARAM];   /* m, Jxx, Jyy, Jzz, c0, c1, c2, T_m                  */
+  double dr_lo[SIM_NPARAM], dr_hi[SIM_NPARAM]; /* randomisation factor ranges          */
+  double pos_limit, vel_limit;  /* termination box (per axis)                          */
+  double init_pos, init_angle, init_vel, init_angvel; /* reset ranges                  */
+  double C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;   /* reward constants              */
+  uint64_t seed;             /* reset-state seed                                     */
+  uint64_t dr_seed;          /* domain-randomisation seed                            */
+} sim_config;
+
+typedef struct sim_handle sim_handle;
+
+/* Creates a simulator for cfg->n_envs envs on HIP device `device`, allocates
+ * all device memory (including the tape for max_tape_horizon steps), draws the
+ * per-env parameters from dr_seed and resets every env to episode 0 from
+ * cfg->seed.  Synchronises.  *out is NULL on failure. */
+int sim_create(const sim_config* cfg, int device, sim_handle** out);
+
+/* Frees everything the handle owns.  Synchronises.  NULL is allowed. */
+int sim_destroy(sim_handle* h);
+
+/* Resets every env to episode 0 with reset seed `seed` (Sec. IV initial-state
+ * distribution): p ~ U(-init_pos, init_pos)^3, attitude rotated by an angle
+ * U(0, init_angle) about a uniformly random axis, v, w uniform in their
+ * ranges, rotors at the hover speed of the env's parameters, history filled
+ * with the hover action, episode counters zero. */
+int sim_reset(sim_handle* h, uint64_t seed, void* stream);
+
+/* One step of every env.  actor: dev [13828] weights; if NULL, actions
+ * (dev [4][N], values in [-1,1]) are applied instead of the policy.
+ * reward: dev [N] or NULL; done: dev [N] or NULL, bit0 terminated, bit1
+ * truncated.  Reward and done describe the transition; with SIM_F_AUTORESET
+ * the state left behind for a finished env is its next episode's start. */
+int sim_step(sim_handle* h, const float* actor, const float* actions, float* reward,
+             uint8_t* done, void* stream);
+
+/* T >= 1 steps of every env under the actor (dev [13828], required).
+ * Optional outputs (NULL to skip): rewards dev [T][N], dones dev [T][N],
+ * states dev [T+1][17][N] with states[0] the start state.
+ * record_tape != 0 stores checkpoints for sim_backward; it requires
+ * T <= max_tape_horizon and flags without TERMINATE and AUTORESET, else
+ * SIM_E_STATE / SIM_E_INVAL. */
+int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
+                float* states, int32_t record_tape, void* stream);
+
+/* Vector-Jacobian product of the last taped rollout (discrete adjoint through
+ * the observation, actor, action map, RK4 stages, quaternion normalisation and
+ * history shift).  Cotangents: d_rewards dev [T][N] (NULL = all ones),
+ * d_states dev [T+1][17][N] (NULL = zeros).  Outputs: grad_actor dev [13828]
+ * (summed over envs and steps, reduced in a fixed order), grad_params dev
+ * [8][N] (per env).  Either output may be NULL.  The start state of the
+ * rollout is held fixed.  Must use the same actor as the taped rollout.
+ * SIM_E_STATE if no tape is recorded. */
+int sim_backward(sim_handle* h, const float* actor, const float* d_rewards,
+                 const float* d_states, float* grad_actor, float* grad_params, void* stream);
+
+/* Snapshot of the per-env state: state dev [17][N], hist dev [32][4][N]
+ * (oldest first), t_ep dev [N], episode dev [N].  Any pointer may be NULL. */
+int sim_get_state(sim_handle* h, float* state, float* hist, int32_t* t_ep, int32_t* episode,
+                  void* stream);
+
+/* Restores a snapshot (same layouts).  NULL pointers leave that part as is.
+ * Invalidates the tape. */
+int sim_set_state(sim_handle* h, const float* state, const float* hist, const int32_t* t_ep,
+                  const int32_t* episode, void* stream);
+
+/* Per-env dynamics parameters theta dev [8][N] (m, Jxx, Jyy, Jzz, c0, c1, c2,
+ * T_m).  set: values must be finite with m, J, T_m > 0 and c2 >= 0 (checked
+ * on the device at the next step: offending envs produce non-finite states). */
+int sim_get_params(sim_handle* h, float* theta, void* stream);
+int sim_set_params(sim_handle* h, const float* theta, void* stream);
+
+/* Chooses the forward variant (SIM_V_*), steps per launch for the fused
+ * variants (0 = whole rollout in one launch) and whether multi-launch
+ * rollouts are replayed from a captured hipGraph (use_graph != 0). */
+int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph);
+int sim_get_variant(const sim_handle* h, int* variant, int* steps_per_launch, int* use_graph);
+
+/* Times every variant and launch shape on a T-step rollout with HIP events,
+ * keeps the fastest (ties go to the earlier candidate), restores the env state
+ * afterwards.  Writes the chosen variant and its time to *variant_out and
+ * *ms_out (either may be NULL).  Synchronises. */
+int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int* variant_out,
+                 float* ms_out);
+
+/* Average duration (ms) of the dominant kernel over the last sim_rollout call,
+ * from HIP events recorded on the call's stream, and the number of launches
+ * it made.  Valid after the stream has completed the rollout. */
+int sim_last_rollout_timing(sim_handle* h, float* ms_per_launch, int* launches);
+
+int sim_n_envs(const sim_handle* h);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QUADSIM_H */

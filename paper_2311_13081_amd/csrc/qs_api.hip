@@ -1,0 +1,550 @@
+// Host runtime of the C ABI declared in include/quadsim.h: argument checks,
+// device memory owned by the handle, variant dispatch, hipGraph replay of
+// multi-launch rollouts, HIP-event timing and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/quadsim.h"
+#include "qs_backward.h"
+#include "qs_forward.h"
+
+using namespace qs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SIM_E_NOMEM : SIM_E_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct GraphKey {
+  int variant = -1, spl = 0, T = 0, tape = 0;
+  const void *W = nullptr, *rew = nullptr, *done = nullptr, *states = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return variant == o.variant && spl == o.spl && T == o.T && tape == o.tape && W == o.W &&
+           rew == o.rew && done == o.done && states == o.states;
+  }
+};
+
+}  // namespace
+
+struct sim_handle {
+  sim_config cfg{};
+  DevCfg dc{};
+  int device = 0, N = 0;
+  SimBufs b{};
+  PlainBufs p{};
+  float* tape = nullptr;     // [max_tape_horizon/K + 1][145][N]
+  int tape_ckpts = 0;
+  int tape_T = 0;            // horizon of the recorded tape (0 = none)
+  BwdBufs bw{};
+  int variant = SIM_V_AUTO, spl = 0, use_graph = 1;
+  int tuned_variant = SIM_V_FUSED_MFMA, tuned_spl = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int last_launches = 0;
+  bool timing_valid = false;
+};
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+int check_config(const sim_config* c) {
+  if (!c) return fail(SIM_E_INVAL, "config is NULL");
+  if (c->n_envs < 1 || c->n_envs > (1 << 24)) return fail(SIM_E_INVAL, "n_envs %d out of range", c->n_envs);
+  if (c->max_episode_steps < 0) return fail(SIM_E_INVAL, "max_episode_steps < 0");
+  if (c->flags & ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q))
+    return fail(SIM_E_INVAL, "unknown flags 0x%x", c->flags);
+  if (c->max_tape_horizon < 0 || c->max_tape_horizon > (1 << 20))
+    return fail(SIM_E_INVAL, "max_tape_horizon out of range");
+  if (c->ckpt_every < 1 || c->ckpt_every > 4096) return fail(SIM_E_INVAL, "ckpt_every must be in [1, 4096]");
+  if (!finite_pos(c->dt) || !finite_pos(c->g) || !finite_pos(c->arm) || !std::isfinite(c->k_m))
+    return fail(SIM_E_INVAL, "dt, g, arm must be finite and positive");
+  if (!std::isfinite(c->rpm_min) || !std::isfinite(c->rpm_max) || !(c->rpm_max > c->rpm_min))
+    return fail(SIM_E_INVAL, "need rpm_max > rpm_min");
+  const double* nom = c->nominal;
+  if (!finite_pos(nom[0]) || !finite_pos(nom[1]) || !finite_pos(nom[2]) || !finite_pos(nom[3]) ||
+      !finite_pos(nom[7]))
+    return fail(SIM_E_INVAL, "mass, inertia and motor time constant must be positive");
+  if (!(nom[6] >= 0) || !std::isfinite(nom[4]) || !std::isfinite(nom[5]) || !std::isfinite(nom[6]))
+    return fail(SIM_E_INVAL, "thrust coefficients must be finite with c2 >= 0");
+  for (int i = 0; i < SIM_NPARAM; ++i)
+    if (c->dr_enable && !(c->dr_lo[i] > 0 && c->dr_hi[i] >= c->dr_lo[i] && std::isfinite(c->dr_hi[i])))
+      return fail(SIM_E_INVAL, "dr range %d invalid", i);
+  if (!finite_pos(c->pos_limit) || !finite_pos(c->vel_limit))
+    return fail(SIM_E_INVAL, "limits must be positive");
+  const double need = nom[0] * c->g / 4 - nom[4];
+  if (!(need > 0) || (nom[6] == 0 && !(nom[5] > 0)))
+    return fail(SIM_E_INVAL, "thrust curve cannot hover the nominal body");
+  return SIM_OK;
+}
+
+DevCfg make_devcfg(const sim_config& c, uint64_t seed) {
+  DevCfg d{};
+  d.n_envs = c.n_envs;
+  d.max_steps = c.max_episode_steps;
+  d.flags = c.flags;
+  d.dr_enable = c.dr_enable;
+  d.dt = (float)c.dt;
+  d.g = (float)c.g;
+  d.arm = (float)c.arm;
+  d.km = (float)c.k_m;
+  d.rpm_min = (float)c.rpm_min;
+  d.rpm_half_range = (float)(0.5 * (c.rpm_max - c.rpm_min));
+  d.pos_limit = (float)c.pos_limit;
+  d.vel_limit = (float)c.vel_limit;
+  d.init_pos = (float)c.init_pos;
+  d.init_angle = (float)c.init_angle;
+  d.init_vel = (float)c.init_vel;
+  d.init_angvel = (float)c.init_angvel;
+  d.C_rp = (float)c.C_rp;
+  d.C_rq = (float)c.C_rq;
+  d.C_rv = (float)c.C_rv;
+  d.C_rw = (float)c.C_rw;
+  d.C_ra = (float)c.C_ra;
+  d.C_rab = (float)c.C_rab;
+  d.C_rs = (float)c.C_rs;
+  for (int i = 0; i < NP; ++i) {
+    d.nominal[i] = (float)c.nominal[i];
+    d.dr_lo[i] = (float)c.dr_lo[i];
+    d.dr_hi[i] = (float)c.dr_hi[i];
+  }
+  d.seed_lo = (uint32_t)seed;
+  d.seed_hi = (uint32_t)(seed >> 32);
+  d.dr_seed_lo = (uint32_t)c.dr_seed;
+  d.dr_seed_hi = (uint32_t)(c.dr_seed >> 32);
+  return d;
+}
+
+// Error left by earlier asynchronous work on this device, if any.
+int sticky_error() {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SIM_E_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+  }
+  return SIM_OK;
+}
+
+int effective_variant(const sim_handle* h) {
+  return h->variant == SIM_V_AUTO ? h->tuned_variant : h->variant;
+}
+int effective_spl(const sim_handle* h) { return h->variant == SIM_V_AUTO ? h->tuned_spl : h->spl; }
+
+void drop_graph(sim_handle* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->gkey = GraphKey{};
+}
+
+// Queues the launches of a T-step rollout on st.
+int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, float* rew,
+                    uint8_t* done, float* states, float* tape, hipStream_t st, int* launches) {
+  const int N = h->N;
+  const int K = h->cfg.ckpt_every;
+  int nl = 0;
+  if (variant == SIM_V_PLAIN) {
+    if (states) HIP_TRY(launch_copy_state(h->b, N, states, st));
+    for (int t = 0; t < T; ++t) {
+      if (tape && t % K == 0) {
+        float* ck = tape + (size_t)(t / K) * (NS + NH * NA) * N;
+        HIP_TRY(launch_get_state(h->b, N, ck, ck + (size_t)NS * N, nullptr, nullptr, st));
+      }
+      HIP_TRY(launch_plain_step(h->dc, h->b, h->p, W, nullptr, rew ? rew + (size_t)t * N : nullptr,
+                                done ? done + (size_t)t * N : nullptr,
+                                states ? states + (size_t)(t + 1) * NS * N : nullptr, st));
+      ++nl;
+    }
+  } else {
+    const bool mfma = variant == SIM_V_FUSED_MFMA;
+    const int chunk = (spl <= 0 || spl > T) ? T : spl;
+    for (int t0 = 0; t0 < T; t0 += chunk) {
+      const int n = (T - t0) < chunk ? (T - t0) : chunk;
+      HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, tape, K, st));
+      ++nl;
+    }
+  }
+  *launches = nl;
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+int sim_n_envs(const sim_handle* h) { return h ? h->N : 0; }
+
+int sim_create(const sim_config* cfg, int device, sim_handle** out) {
+  if (!out) return fail(SIM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(SIM_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(SIM_E_INVAL, "device %d not in [0, %d)", device, ndev);
+  DeviceGuard g(device);
+  if (!g.ok) return fail(SIM_E_DEVICE, "hipSetDevice(%d) failed", device);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SIM_E_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+
+  sim_handle* h = new sim_handle();
+  h->cfg = *cfg;
+  h->device = device;
+  h->N = cfg->n_envs;
+  h->dc = make_devcfg(*cfg, cfg->seed);
+  const size_t N = (size_t)h->N;
+  auto alloc = [&](void** p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? SIM_E_NOMEM : SIM_E_DEVICE, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    return SIM_OK;
+  };
+  rc = SIM_OK;
+  rc = rc ? rc : alloc((void**)&h->b.state, N * NS * 4);
+  rc = rc ? rc : alloc((void**)&h->b.ring, N * NH * NA * 4);
+  rc = rc ? rc : alloc((void**)&h->b.head, N * 4);
+  rc = rc ? rc : alloc((void**)&h->b.t_ep, N * 4);
+  rc = rc ? rc : alloc((void**)&h->b.ep, N * 4);
+  rc = rc ? rc : alloc((void**)&h->b.theta, N * NP * 4);
+  rc = rc ? rc : alloc((void**)&h->p.obs, N * NO * 4);
+  rc = rc ? rc : alloc((void**)&h->p.h1, N * NHID * 4);
+  rc = rc ? rc : alloc((void**)&h->p.h2, N * NHID * 4);
+  rc = rc ? rc : alloc((void**)&h->p.act, N * NA * 4);
+  if (!rc && cfg->max_tape_horizon > 0) {
+    h->tape_ckpts = (cfg->max_tape_horizon + cfg->ckpt_every - 1) / cfg->ckpt_every + 1;
+    rc = alloc((void**)&h->tape, (size_t)h->tape_ckpts * (NS + NH * NA) * N * 4);
+    if (!rc) rc = bwd_alloc(h->bw, h->N, cfg->ckpt_every, cfg->max_tape_horizon) == hipSuccess
+                      ? SIM_OK
+                      : fail(SIM_E_NOMEM, "backward scratch allocation failed");
+  }
+  if (!rc && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(SIM_E_DEVICE, "stream creation failed");
+  if (!rc && (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess))
+    rc = fail(SIM_E_DEVICE, "event creation failed");
+  if (!rc) {
+    hipError_t e = launch_init(h->dc, h->b, 1, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = fail(SIM_E_DEVICE, "init: %s", hipGetErrorString(e));
+  }
+  if (rc) {
+    sim_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SIM_OK;
+}
+
+int sim_destroy(sim_handle* h) {
+  if (!h) return SIM_OK;
+  DeviceGuard g(h->device);
+  (void)hipDeviceSynchronize();
+  drop_graph(h);
+  void* ptrs[] = {h->b.state, h->b.ring, h->b.head, h->b.t_ep, h->b.ep, h->b.theta,
+                  h->p.obs,   h->p.h1,   h->p.h2,   h->p.act,  h->tape};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  bwd_free(h->bw);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+  return SIM_OK;
+}
+
+int sim_reset(sim_handle* h, uint64_t seed, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  h->cfg.seed = seed;
+  h->dc = make_devcfg(h->cfg, seed);
+  h->tape_T = 0;
+  drop_graph(h);
+  HIP_TRY(launch_init(h->dc, h->b, 0, (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_step(sim_handle* h, const float* actor, const float* actions, float* reward, uint8_t* done,
+             void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actor && !actions) return fail(SIM_E_INVAL, "need actor weights or actions");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  h->tape_T = 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int v = effective_variant(h);
+  if (v == SIM_V_PLAIN) {
+    HIP_TRY(launch_plain_step(h->dc, h->b, h->p, actor, actor ? nullptr : actions, reward, done,
+                              nullptr, st));
+  } else {
+    HIP_TRY(launch_fused(v == SIM_V_FUSED_MFMA, h->dc, h->b, actor, actor ? nullptr : actions, 1, 0,
+                         reward, done, nullptr, nullptr, h->cfg.ckpt_every, st));
+  }
+  return SIM_OK;
+}
+
+int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
+                float* states, int32_t record_tape, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actor) return fail(SIM_E_INVAL, "actor is NULL");
+  if (T < 1) return fail(SIM_E_INVAL, "T = %d < 1", T);
+  if (record_tape) {
+    if (h->cfg.max_tape_horizon <= 0 || T > h->cfg.max_tape_horizon)
+      return fail(SIM_E_INVAL, "T = %d exceeds max_tape_horizon = %d", T, h->cfg.max_tape_horizon);
+    if (h->cfg.flags & (SIM_F_TERMINATE | SIM_F_AUTORESET))
+      return fail(SIM_E_STATE, "differentiable rollouts need TERMINATE and AUTORESET off");
+  }
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int v = effective_variant(h);
+  const int spl = effective_spl(h);
+  float* tape = record_tape ? h->tape : nullptr;
+  h->tape_T = 0;
+  int launches = 0;
+  const bool multi = (v == SIM_V_PLAIN) || (spl > 0 && spl < T);
+  if (h->use_graph && multi) {
+    GraphKey key;
+    key.variant = v;
+    key.spl = spl;
+    key.T = T;
+    key.tape = record_tape ? 1 : 0;
+    key.W = actor;
+    key.rew = rewards;
+    key.done = dones;
+    key.states = states;
+    if (!(h->gexec && h->gkey == key)) {
+      drop_graph(h);
+      HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc2 = enqueue_rollout(h, v, spl, actor, T, rewards, dones, states, tape, h->cap_stream,
+                                &launches);
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(h->cap_stream, &gr);
+      if (rc2) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc2;
+      }
+      if (e != hipSuccess) return fail(SIM_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+      h->graph = gr;
+      e = hipGraphInstantiate(&h->gexec, gr, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        drop_graph(h);
+        return fail(SIM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+      }
+      h->gkey = key;
+    }
+    launches = v == SIM_V_PLAIN ? T : (T + spl - 1) / spl;
+    HIP_TRY(hipEventRecord(h->ev0, st));
+    HIP_TRY(hipGraphLaunch(h->gexec, st));
+    HIP_TRY(hipEventRecord(h->ev1, st));
+  } else {
+    HIP_TRY(hipEventRecord(h->ev0, st));
+    rc = enqueue_rollout(h, v, spl, actor, T, rewards, dones, states, tape, st, &launches);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(h->ev1, st));
+  }
+  h->last_launches = launches;
+  h->timing_valid = true;
+  if (record_tape) h->tape_T = T;
+  return SIM_OK;
+}
+
+int sim_last_rollout_timing(sim_handle* h, float* ms_per_launch, int* launches) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!h->timing_valid) return fail(SIM_E_STATE, "no rollout timed yet");
+  DeviceGuard g(h->device);
+  float ms = 0;
+  HIP_TRY(hipEventSynchronize(h->ev1));
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (ms_per_launch) *ms_per_launch = h->last_launches ? ms / h->last_launches : ms;
+  if (launches) *launches = h->last_launches;
+  return SIM_OK;
+}
+
+int sim_backward(sim_handle* h, const float* actor, const float* d_rewards, const float* d_states,
+                 float* grad_actor, float* grad_params, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actor) return fail(SIM_E_INVAL, "actor is NULL");
+  if (h->tape_T <= 0) return fail(SIM_E_STATE, "no taped rollout to differentiate");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  HIP_TRY(run_backward(h->dc, h->b, h->bw, actor, h->tape, h->cfg.ckpt_every, h->tape_T, d_rewards,
+                       d_states, grad_actor, grad_params, (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_get_state(sim_handle* h, float* state, float* hist, int32_t* t_ep, int32_t* episode,
+                  void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  HIP_TRY(launch_get_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_set_state(sim_handle* h, const float* state, const float* hist, const int32_t* t_ep,
+                  const int32_t* episode, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  h->tape_T = 0;
+  HIP_TRY(launch_set_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_get_params(sim_handle* h, float* theta, void* stream) {
+  if (!h || !theta) return fail(SIM_E_INVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(theta, h->b.theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_set_params(sim_handle* h, const float* theta, void* stream) {
+  if (!h || !theta) return fail(SIM_E_INVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  h->tape_T = 0;
+  HIP_TRY(hipMemcpyAsync(h->b.theta, theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_MFMA) return fail(SIM_E_INVAL, "unknown variant %d", variant);
+  if (steps_per_launch < 0) return fail(SIM_E_INVAL, "steps_per_launch < 0");
+  h->variant = variant;
+  h->spl = steps_per_launch;
+  h->use_graph = use_graph ? 1 : 0;
+  DeviceGuard g(h->device);
+  drop_graph(h);
+  return SIM_OK;
+}
+
+int sim_get_variant(const sim_handle* h, int* variant, int* steps_per_launch, int* use_graph) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (variant) *variant = effective_variant(h);
+  if (steps_per_launch) *steps_per_launch = effective_spl(h);
+  if (use_graph) *use_graph = h->use_graph;
+  return SIM_OK;
+}
+
+int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int* variant_out,
+                 float* ms_out) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actor || T < 1) return fail(SIM_E_INVAL, "need actor and T >= 1");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)h->N;
+  // Snapshot so every candidate starts from the same state and the caller's
+  // state is restored afterwards.
+  float *s_state = nullptr, *s_hist = nullptr;
+  int32_t *s_tep = nullptr, *s_ep = nullptr;
+  HIP_TRY(hipMalloc(&s_state, N * NS * 4));
+  HIP_TRY(hipMalloc(&s_hist, N * NH * NA * 4));
+  HIP_TRY(hipMalloc(&s_tep, N * 4));
+  HIP_TRY(hipMalloc(&s_ep, N * 4));
+  HIP_TRY(launch_get_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
+  struct Cand { int v, spl; };
+  std::vector<Cand> cands = {{SIM_V_FUSED_MFMA, 0}, {SIM_V_FUSED_MFMA, 100}, {SIM_V_FUSED_VALU, 0},
+                             {SIM_V_PLAIN, 0}};
+  const int save_v = h->variant, save_spl = h->spl;
+  float best = 1e30f;
+  Cand bestc = cands[0];
+  for (const Cand& cd : cands) {
+    if (cd.spl >= T) continue;
+    h->variant = cd.v;
+    h->spl = cd.spl;
+    drop_graph(h);
+    float acc = 0;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRY(launch_set_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
+      rc = sim_rollout(h, actor, T, nullptr, nullptr, nullptr, 0, stream);
+      if (rc) break;
+      HIP_TRY(hipEventSynchronize(h->ev1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      if (rep > 0) acc += ms;  // first run warms up (and captures the graph)
+    }
+    if (rc) break;
+    const float ms = acc / 2;
+    if (ms < best) {
+      best = ms;
+      bestc = cd;
+    }
+  }
+  h->variant = save_v;
+  h->spl = save_spl;
+  drop_graph(h);
+  if (!rc) {
+    h->tuned_variant = bestc.v;
+    h->tuned_spl = bestc.spl;
+    (void)launch_set_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st);
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(s_state);
+  (void)hipFree(s_hist);
+  (void)hipFree(s_tep);
+  (void)hipFree(s_ep);
+  h->tape_T = 0;
+  if (rc) return rc;
+  if (variant_out) *variant_out = bestc.v;
+  if (ms_out) *ms_out = best;
+  return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Device-side pieces shared by every kernel of the library: the per-launch
+// configuration, the counter RNG, the reset distribution, the quadrotor
+// dynamics, RK4, reward and termination.  One env is one lane; everything here
+// is scalar per env.  Equations: "Learning to Fly in Seconds", Sec. IV.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+constexpr int NS = 17, NH = 32, NA = 4, NO = 146, NHID = 64, NP = 8, NW = 13828;
+constexpr int OFF_W1 = 0, OFF_B1 = NHID * NO, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
+              OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NA * NHID;
+constexpr int F_TERMINATE = 1, F_AUTORESET = 2, F_RENORM_Q = 4;
+constexpr uint32_t STREAM_RESET = 0, STREAM_DR = 1;
+
+// Everything a kernel needs from the configuration, in single precision,
+// passed by value.
+struct DevCfg {
+  int n_envs, max_steps, flags, dr_enable;
+  float dt, g, arm, km, rpm_min, rpm_half_range;
+  float pos_limit, vel_limit, init_pos, init_angle, init_vel, init_angvel;
+  float C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;
+  float nominal[NP], dr_lo[NP], dr_hi[NP];
+  uint32_t seed_lo, seed_hi, dr_seed_lo, dr_seed_hi;
+};
+
+// Device state of the batch, struct-of-arrays, N = n_envs.
+struct SimBufs {
+  float* state;    // [17][N]
+  float* ring;     // [32][4][N] action history ring; logical slot s at (head+s)&31
+  int32_t* head;   // [N]
+  int32_t* t_ep;   // [N] steps in the current episode
+  int32_t* ep;     // [N] episode index
+  float* theta;    // [8][N] m, Jxx, Jyy, Jzz, c0, c1, c2, Tm
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 counter RNG (Salmon et al., SC'11).  Counter (env, episode,
+// block, stream), key = 64-bit seed.  Uniform u = (2k+1) 2^-24, k the top 23
+// bits, exact in float.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ inline void uniforms4(uint32_t klo, uint32_t khi, uint32_t env, uint32_t episode,
+                                 uint32_t block, uint32_t stream, float u[4]) {
+  uint32_t c[4] = {env, episode, block, stream};
+  philox4x32_10(c, klo, khi);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = ((float)(c[i] >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// Per-env parameters: nominal times U(lo, hi) factors when randomised.
+__device__ inline void env_params(const DevCfg& c, uint32_t env, float th[NP]) {
+  float u[8];
+  uniforms4(c.dr_seed_lo, c.dr_seed_hi, env, 0, 0, STREAM_DR, u);
+  uniforms4(c.dr_seed_lo, c.dr_seed_hi, env, 0, 1, STREAM_DR, u + 4);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const float f = c.dr_enable ? c.dr_lo[i] + (c.dr_hi[i] - c.dr_lo[i]) * u[i] : 1.0f;
+    th[i] = c.nominal[i] * f;
+  }
+}
+
+// Hover rotor speed: positive root of c2 w^2 + c1 w + c0 = m g / 4, in the
+// cancellation-free form 2 need / (c1 + sqrt(c1^2 + 4 c2 need)).
+__device__ inline float hover_rpm(const DevCfg& c, float m, float c0, float c1, float c2) {
+  const float need = m * c.g * 0.25f - c0;
+  return 2.0f * need / (c1 + sqrtf(c1 * c1 + 4.0f * c2 * need));
+}
+
+__device__ inline float rpm_to_action(const DevCfg& c, float w) {
+  return (w - c.rpm_min) / c.rpm_half_range - 1.0f;
+}
+
+// Episode-start state for (env, episode): p, attitude (angle about a uniform
+// axis), v, w uniform in their ranges, rotors at hover.  Returns the hover
+// action used to fill the history.
+__device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t episode, float m,
+                                    float c0, float c1, float c2, float s[NS]) {
+  float u[12];
+  uniforms4(c.seed_lo, c.seed_hi, env, episode, 0, STREAM_RESET, u);
+  uniforms4(c.seed_lo, c.seed_hi, env, episode, 1, STREAM_RESET, u + 4);
+  uniforms4(c.seed_lo, c.seed_hi, env, episode, 2, STREAM_RESET, u + 8);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s[i] = c.init_pos * (2.0f * u[i] - 1.0f);
+  const float z = 2.0f * u[3] - 1.0f;
+  const float phi = 6.283185307179586f * u[4];
+  const float half = 0.5f * c.init_angle * u[5];
+  const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+  float sp, cp, sa, ca;
+  sincosf(phi, &sp, &cp);
+  sincosf(half, &sa, &ca);
+  s[3] = ca;
+  s[4] = sa * r * cp;
+  s[5] = sa * r * sp;
+  s[6] = sa * z;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s[7 + i] = c.init_vel * (2.0f * u[6 + i] - 1.0f);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s[10 + i] = c.init_angvel * (2.0f * u[9 + i] - 1.0f);
+  const float wh = hover_rpm(c, m, c0, c1, c2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s[13 + i] = wh;
+  return rpm_to_action(c, wh);
+}
+
+// ---------------------------------------------------------------------------
+// Dynamics, templated on the arithmetic type R of the integrator.
+// Rotor i sits at (sx_i l, sy_i l, 0) with spin sign d_i:
+//   sx = (+,-,-,+), sy = (-,-,+,+), d = (-,+,-,+).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Body {
+  R inv_m, Jx, Jy, Jz, inv_Jx, inv_Jy, inv_Jz, c0, c1, c2, inv_Tm;
+};
+
+template <typename R>
+__device__ inline Body<R> make_body(const float th[NP]) {
+  Body<R> b;
+  b.inv_m = R(1) / R(th[0]);
+  b.Jx = R(th[1]);
+  b.Jy = R(th[2]);
+  b.Jz = R(th[3]);
+  b.inv_Jx = R(1) / b.Jx;
+  b.inv_Jy = R(1) / b.Jy;
+  b.inv_Jz = R(1) / b.Jz;
+  b.c0 = R(th[4]);
+  b.c1 = R(th[5]);
+  b.c2 = R(th[6]);
+  b.inv_Tm = R(1) / R(th[7]);
+  return b;
+}
+
+__device__ inline float rsqrt_r(float x) { return __frsqrt_rn(x); }
+__device__ inline double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+
+// dx = f(x, u) for the 17-state (Newton-Euler with motor lag, z up).
+template <typename R>
+__device__ inline void deriv(const Body<R>& B, R arm, R km, R g, const R x[NS], const R u[4],
+                             R dx[NS]) {
+  const R w0 = x[13], w1 = x[14], w2 = x[15], w3 = x[16];
+  const R T0 = B.c0 + w0 * (B.c1 + B.c2 * w0);
+  const R T1 = B.c0 + w1 * (B.c1 + B.c2 * w1);
+  const R T2 = B.c0 + w2 * (B.c1 + B.c2 * w2);
+  const R T3 = B.c0 + w3 * (B.c1 + B.c2 * w3);
+  const R F = (T0 + T1) + (T2 + T3);
+  const R tx = arm * ((T2 + T3) - (T0 + T1));
+  const R ty = arm * ((T1 + T2) - (T0 + T3));
+  const R tz = km * ((T1 + T3) - (T0 + T2));
+  const R qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  // third column of R(q/|q|) times F/m: (2(xz+wy), 2(yz-wx), 1-2(x^2+y^2)) / |q|^2
+  const R n2 = qw * qw + qx * qx + qy * qy + qz * qz;
+  const R s = F * B.inv_m / n2;
+  dx[0] = x[7];
+  dx[1] = x[8];
+  dx[2] = x[9];
+  const R ox = x[10], oy = x[11], oz = x[12];
+  dx[3] = R(-0.5) * (qx * ox + qy * oy + qz * oz);
+  dx[4] = R(0.5) * (qw * ox + qy * oz - qz * oy);
+  dx[5] = R(0.5) * (qw * oy + qz * ox - qx * oz);
+  dx[6] = R(0.5) * (qw * oz + qx * oy - qy * ox);
+  dx[7] = R(2) * (qx * qz + qw * qy) * s;
+  dx[8] = R(2) * (qy * qz - qw * qx) * s;
+  dx[9] = (n2 - R(2) * (qx * qx + qy * qy)) * s - g;
+  // Euler: J wdot = tau - w x (J w)
+  dx[10] = (tx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
+  dx[11] = (ty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
+  dx[12] = (tz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
+  dx[13] = (u[0] - w0) * B.inv_Tm;
+  dx[14] = (u[1] - w1) * B.inv_Tm;
+  dx[15] = (u[2] - w2) * B.inv_Tm;
+  dx[16] = (u[3] - w3) * B.inv_Tm;
+}
+
+// One classical RK4 step, set points held.  Optional renormalisation of q.
+template <typename R>
+__device__ inline void rk4_step(const Body<R>& B, R arm, R km, R g, R h, bool renorm, R x[NS],
+                                const R u[4]) {
+  R k[NS], acc[NS], t[NS];
+  deriv<R>(B, arm, km, g, x, u, k);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] = k[i];
+    t[i] = x[i] + R(0.5) * h * k[i];
+  }
+  deriv<R>(B, arm, km, g, t, u, k);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] += R(2) * k[i];
+    t[i] = x[i] + R(0.5) * h * k[i];
+  }
+  deriv<R>(B, arm, km, g, t, u, k);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] += R(2) * k[i];
+    t[i] = x[i] + h * k[i];
+  }
+  deriv<R>(B, arm, km, g, t, u, k);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = x[i] + (h / R(6)) * (acc[i] + k[i]);
+  if (renorm) {
+    const R r = rsqrt_r(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+    x[3] *= r;
+    x[4] *= r;
+    x[5] *= r;
+    x[6] *= r;
+  }
+}
+
+// Row-major rotation matrix of q/|q| (Hamilton, body to world).
+__device__ inline void rotmat(const float q[4], float Rm[9]) {
+  const float n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  const float s = 2.0f / n2;
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  Rm[0] = 1.0f - s * (y * y + z * z);
+  Rm[1] = s * (x * y - w * z);
+  Rm[2] = s * (x * z + w * y);
+  Rm[3] = s * (x * y + w * z);
+  Rm[4] = 1.0f - s * (x * x + z * z);
+  Rm[5] = s * (y * z - w * x);
+  Rm[6] = s * (x * z - w * y);
+  Rm[7] = s * (y * z + w * x);
+  Rm[8] = 1.0f - s * (x * x + y * y);
+}
+
+__device__ inline float reward(const DevCfg& c, const float s[NS], const float a[NA]) {
+  const float pp = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+  const float vv = s[7] * s[7] + s[8] * s[8] + s[9] * s[9];
+  const float ww = s[10] * s[10] + s[11] * s[11] + s[12] * s[12];
+  float aa = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) aa += (a[i] - c.C_rab) * (a[i] - c.C_rab);
+  return -c.C_rp * pp - c.C_rq * (1.0f - s[3] * s[3]) - c.C_rv * vv - c.C_rw * ww - c.C_ra * aa +
+         c.C_rs;
+}
+
+// bit0: terminated (box or non-finite, if enabled); bit1: truncated.
+__device__ inline uint32_t episode_end(const DevCfg& c, const float s[NS], int t_ep) {
+  uint32_t term = 0;
+  if (c.flags & F_TERMINATE) {
+    bool out = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out |= fabsf(s[i]) > c.pos_limit;
+      out |= fabsf(s[7 + i]) > c.vel_limit;
+    }
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) finite &= isfinite(s[i]);
+    term = (out || !finite) ? 1u : 0u;
+  }
+  const uint32_t trunc = (!term && c.max_steps > 0 && t_ep >= c.max_steps) ? 2u : 0u;
+  return term | trunc;
+}
+
+// Returns v unchanged but hides its value from the optimiser.  Loop bodies
+// index SoA rows as row*N + opaque(e): the row part stays scalar and the
+// per-lane part is one register, instead of the compiler hoisting one live
+// 64-bit address per row out of the loop.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+
+__device__ inline float action_to_rpm(const DevCfg& c, float a) {
+  return c.rpm_min + (a + 1.0f) * c.rpm_half_range;
+}
+
+}  // namespace qs

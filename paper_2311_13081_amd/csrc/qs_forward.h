@@ -1,0 +1,29 @@
+// Launchers of the forward kernels (qs_forward.hip) and the backward kernels
+// (qs_backward.hip), called by the host runtime (qs_api.hip).
+#pragma once
+#include "qs_device.h"
+
+namespace qs {
+
+// Intermediates of the plain five-kernel step, [K][N] each.
+struct PlainBufs {
+  float* obs;  // [146][N]
+  float* h1;   // [64][N]
+  float* h2;   // [64][N]
+  float* act;  // [4][N]
+};
+
+hipError_t launch_init(const DevCfg& c, const SimBufs& b, int params, hipStream_t st);
+hipError_t launch_get_state(const SimBufs& b, int N, float* state, float* hist, int32_t* t_ep,
+                            int32_t* ep, hipStream_t st);
+hipError_t launch_set_state(const SimBufs& b, int N, const float* state, const float* hist,
+                            const int32_t* t_ep, const int32_t* ep, hipStream_t st);
+hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs& p,
+                             const float* W, const float* ext_act, float* reward, uint8_t* done,
+                             float* state_out, hipStream_t st);
+hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st);
+hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
+                        const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
+                        float* states, float* tape, int ckpt_every, hipStream_t st);
+
+}  // namespace qs

@@ -1,0 +1,571 @@
+// Forward kernels of the batched quadrotor step: initialisation and reset,
+// snapshots, the plain five-kernel step, and the fused multi-step kernel with
+// the actor either on the vector ALUs or on fp32 matrix cores (MFMA).
+//
+// Layout: one env per lane, struct-of-arrays in HBM ([K][N]) so every global
+// access of a wave is a contiguous 256-byte segment.  Actor weights are staged
+// in LDS once per workgroup.
+#include "qs_forward.h"
+
+namespace qs {
+
+// ---------------------------------------------------------------------------
+// Init / reset / snapshots
+// ---------------------------------------------------------------------------
+
+// Draws per-env parameters (when params != 0) and episode-0 start states.
+__global__ void k_init(DevCfg c, SimBufs b, int params) {
+  const int N = c.n_envs;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float th[NP];
+  if (params) {
+    env_params(c, (uint32_t)e, th);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) b.theta[i * N + e] = th[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) th[i] = b.theta[i * N + e];
+  }
+  float s[NS];
+  const float ah = reset_state(c, (uint32_t)e, 0u, th[0], th[4], th[5], th[6], s);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) b.state[i * N + e] = s[i];
+  for (int i = 0; i < NH * NA; ++i) b.ring[i * N + e] = ah;
+  b.head[e] = 0;
+  b.t_ep[e] = 0;
+  b.ep[e] = 0;
+}
+
+__global__ void k_get_state(SimBufs b, int N, float* state, float* hist, int32_t* t_ep,
+                            int32_t* ep) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  if (state)
+    for (int i = 0; i < NS; ++i) state[i * N + e] = b.state[i * N + e];
+  if (hist) {
+    const int h = b.head[e];
+    for (int s = 0; s < NH; ++s) {
+      const int slot = (h + s) & (NH - 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) hist[(s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+    }
+  }
+  if (t_ep) t_ep[e] = b.t_ep[e];
+  if (ep) ep[e] = b.ep[e];
+}
+
+__global__ void k_set_state(SimBufs b, int N, const float* state, const float* hist,
+                            const int32_t* t_ep, const int32_t* ep) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  if (state)
+    for (int i = 0; i < NS; ++i) b.state[i * N + e] = state[i * N + e];
+  if (hist) {
+    for (int i = 0; i < NH * NA; ++i) b.ring[i * N + e] = hist[i * N + e];
+    b.head[e] = 0;
+  }
+  if (t_ep) b.t_ep[e] = t_ep[e];
+  if (ep) b.ep[e] = ep[e];
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: five kernels per step, every intermediate through HBM.
+// ---------------------------------------------------------------------------
+
+// obs[146][N] = {p, R(q), v, w, H oldest..newest}
+__global__ void __launch_bounds__(256) k_plain_obs(SimBufs b, int N, float* __restrict__ obs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float q[4], Rm[9];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = b.state[(3 + i) * N + e];
+  rotmat(q, Rm);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) obs[i * N + e] = b.state[i * N + e];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) obs[(3 + i) * N + e] = Rm[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) obs[(12 + i) * N + e] = b.state[(7 + i) * N + e];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) obs[(15 + i) * N + e] = b.state[(10 + i) * N + e];
+  const int h = b.head[e];
+  for (int s = 0; s < NH; ++s) {
+    const int slot = (h + s) & (NH - 1);
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+      obs[(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+  }
+}
+
+// out[NOUT][N] = act(Wl in[NIN][N] + bl), act = ReLU or tanh.  Weights are
+// staged transposed in LDS so every lane reads the same address (broadcast).
+template <int NIN, int NOUT, bool TANH>
+__global__ void __launch_bounds__(256) k_plain_dense(int N, const float* __restrict__ Wl,
+                                                     const float* __restrict__ bl,
+                                                     const float* __restrict__ in,
+                                                     float* __restrict__ out) {
+  __shared__ float sW[NIN * NOUT];
+  __shared__ float sb[NOUT];
+  for (int i = threadIdx.x; i < NIN * NOUT; i += blockDim.x) {
+    const int k = i / NOUT, n = i % NOUT;
+    sW[i] = Wl[n * NIN + k];
+  }
+  for (int i = threadIdx.x; i < NOUT; i += blockDim.x) sb[i] = bl[i];
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float acc[NOUT];
+#pragma unroll
+  for (int n = 0; n < NOUT; ++n) acc[n] = sb[n];
+  for (int k = 0; k < NIN; ++k) {
+    const float x = in[k * N + e];
+#pragma unroll
+    for (int n = 0; n < NOUT; ++n) acc[n] = fmaf(sW[k * NOUT + n], x, acc[n]);
+  }
+#pragma unroll
+  for (int n = 0; n < NOUT; ++n) out[n * N + e] = TANH ? tanhf(acc[n]) : fmaxf(acc[n], 0.0f);
+}
+
+// Dynamics, reward, history push, episode bookkeeping and reset.
+__global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
+                                                   const float* __restrict__ act,
+                                                   float* __restrict__ reward_out,
+                                                   uint8_t* __restrict__ done_out,
+                                                   float* __restrict__ state_out) {
+  const int N = c.n_envs;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float th[NP], x[NS], a[NA], u[NA];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) th[i] = b.theta[i * N + e];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    a[i] = act[i * N + e];
+    u[i] = action_to_rpm(c, a[i]);
+  }
+  const Body<float> B = make_body<float>(th);
+  rk4_step<float>(B, c.arm, c.km, c.g, c.dt, (c.flags & F_RENORM_Q) != 0, x, u);
+  const float r = reward(c, x, a);
+  int h = b.head[e];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) b.ring[(h * NA + i) * N + e] = a[i];
+  h = (h + 1) & (NH - 1);
+  int t_ep = b.t_ep[e] + 1;
+  const uint32_t d = episode_end(c, x, t_ep);
+  if (d && (c.flags & F_AUTORESET)) {
+    const int ep = b.ep[e] + 1;
+    b.ep[e] = ep;
+    t_ep = 0;
+    const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
+    for (int i = 0; i < NH * NA; ++i) b.ring[i * N + e] = ah;
+    h = 0;
+  }
+  b.head[e] = h;
+  b.t_ep[e] = t_ep;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) b.state[i * N + e] = x[i];
+  if (reward_out) reward_out[e] = r;
+  if (done_out) done_out[e] = (uint8_t)d;
+  if (state_out)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) state_out[i * N + e] = x[i];
+}
+
+// Copies the state to a [17][N] slice (start state of a recorded rollout).
+__global__ void k_copy_state(SimBufs b, int N, float* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) out[i * N + e] = b.state[i * N + e];
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-step kernel
+// ---------------------------------------------------------------------------
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16 __attribute__((ext_vector_type(16)));
+
+// LDS layouts (floats).
+// MFMA: W1 row-major [64][148] (k padded), b1, W2 [64][68], b2, W3 [16][68]
+// (rows 4..15 zero), b3.  Row pitches keep 16-byte alignment and spread the
+// 16 rows one 16-lane group reads over distinct banks.
+constexpr int M_W1_LD = 148, M_W2_LD = 68;
+constexpr int M_W1 = 0, M_B1 = M_W1 + NHID * M_W1_LD, M_W2 = M_B1 + NHID,
+              M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + 16 * M_W2_LD,
+              M_TOTAL = M_B3 + 4;
+// VALU: transposed weights so consecutive outputs are consecutive floats.
+constexpr int V_W1T = 0, V_B1 = V_W1T + NO * NHID, V_W2T = V_B1 + NHID,
+              V_B2 = V_W2T + NHID * NHID, V_W3T = V_B2 + NHID, V_B3 = V_W3T + NHID * NA,
+              V_TOTAL = V_B3 + NA;
+constexpr int LDS_FLOATS = M_TOTAL > V_TOTAL ? M_TOTAL : V_TOTAL;
+
+template <bool MFMA>
+__device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (MFMA) {
+    for (int i = tid; i < NHID * M_W1_LD; i += nt) {
+      const int r = i / M_W1_LD, k = i % M_W1_LD;
+      lds[M_W1 + i] = k < NO ? W[OFF_W1 + r * NO + k] : 0.0f;
+    }
+    for (int i = tid; i < NHID * M_W2_LD; i += nt) {
+      const int r = i / M_W2_LD, k = i % M_W2_LD;
+      lds[M_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
+    }
+    for (int i = tid; i < 16 * M_W2_LD; i += nt) {
+      const int r = i / M_W2_LD, k = i % M_W2_LD;
+      lds[M_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
+    }
+    for (int i = tid; i < NHID; i += nt) {
+      lds[M_B1 + i] = W[OFF_B1 + i];
+      lds[M_B2 + i] = W[OFF_B2 + i];
+    }
+    for (int i = tid; i < 4; i += nt) lds[M_B3 + i] = W[OFF_B3 + i];
+  } else {
+    for (int i = tid; i < NO * NHID; i += nt) {
+      const int k = i / NHID, n = i % NHID;
+      lds[V_W1T + i] = W[OFF_W1 + n * NO + k];
+    }
+    for (int i = tid; i < NHID * NHID; i += nt) {
+      const int k = i / NHID, n = i % NHID;
+      lds[V_W2T + i] = W[OFF_W2 + n * NHID + k];
+    }
+    for (int i = tid; i < NHID * NA; i += nt) {
+      const int k = i / NA, n = i % NA;
+      lds[V_W3T + i] = W[OFF_W3 + n * NHID + k];
+    }
+    for (int i = tid; i < NHID; i += nt) {
+      lds[V_B1 + i] = W[OFF_B1 + i];
+      lds[V_B2 + i] = W[OFF_B2 + i];
+    }
+    for (int i = tid; i < NA; i += nt) lds[V_B3 + i] = W[OFF_B3 + i];
+  }
+}
+
+// Observation feature k of this lane's env (compile-time k after unrolling).
+#define QS_FEAT(k)                                                                  \
+  ((k) < 3 ? s[(k)] : (k) < 12 ? Rm[(k)-3] : (k) < 15 ? s[(k)-12 + 7] : (k) < 18 ? \
+   s[(k)-15 + 10] : H[(k)-18])
+
+// Actor on matrix cores.  Each wave evaluates its 64 envs together:
+//  layer 1: 146 rank-1 updates per 16-neuron tile with the 4-block
+//           16x16x1 fp32 MFMA; B = feature k of the 64 envs (one per lane,
+//           4 blocks of 16 envs), A = weights of 16 neurons broadcast to the
+//           4 blocks.  The result registers hold (neuron, env) tiles.
+//  layer 2/3: 16x16x4 fp32 MFMA.  A result register of the previous layer is
+//           directly a B operand whose K-chunk is 4 neurons {4g+v}; the
+//           weights are read in the matching order.  Layer 3 uses 4 of 16
+//           rows.
+//  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
+__device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
+                                  const float H[NH * NA], float z3out[NA]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  f16 acc1[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc1[n][r] = lds[M_B1 + 16 * n + 4 * lg + (r & 3)];
+#pragma unroll
+  for (int kc = 0; kc < (NO + 3) / 4; ++kc) {
+    f4 w[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      w[n] = *reinterpret_cast<const f4*>(&lds[M_W1 + (16 * n + li) * M_W1_LD + 4 * kc]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kc + kk;
+      if (k < NO) {
+        const float x = QS_FEAT(k);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], x, acc1[n], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
+
+  f4 acc2[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = lds[M_B2 + 16 * n2 + 4 * lg + r];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const f4 w =
+          *reinterpret_cast<const f4*>(&lds[M_W2 + (16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          acc2[n2][bb] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][4 * bb + v], acc2[n2][bb], 0, 0, 0);
+    }
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = fmaxf(acc2[n2][bb][r], 0.0f);
+
+  f4 acc3[4];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc3[bb][r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + li * M_W2_LD + 16 * n2 + 4 * lg]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][bb][v], acc3[bb], 0, 0, 0);
+  }
+  // lanes 0..15 of block bb hold z3[o] of env 16 bb + lane in register o.
+  const int src = li << 2;
+#pragma unroll
+  for (int o = 0; o < NA; ++o) {
+    float v[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+      v[bb] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[bb][o])));
+    z3out[o] = lg == 0 ? v[0] : lg == 1 ? v[1] : lg == 2 ? v[2] : v[3];
+  }
+}
+
+// Actor on the vector ALUs, one env per lane, weights broadcast from LDS.
+__device__ inline void actor_valu(const float* lds, const float s[NS], const float Rm[9],
+                                  const float H[NH * NA], float z3out[NA]) {
+  float z1[NHID];
+#pragma unroll
+  for (int n = 0; n < NHID; ++n) z1[n] = lds[V_B1 + n];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const float x = QS_FEAT(k);
+#pragma unroll
+    for (int nc = 0; nc < NHID / 4; ++nc) {
+      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W1T + k * NHID + 4 * nc]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z1[4 * nc + j] = fmaf(w[j], x, z1[4 * nc + j]);
+    }
+  }
+  float z2[NHID];
+#pragma unroll
+  for (int n = 0; n < NHID; ++n) z2[n] = lds[V_B2 + n];
+#pragma unroll
+  for (int k = 0; k < NHID; ++k) {
+    const float x = fmaxf(z1[k], 0.0f);
+#pragma unroll
+    for (int nc = 0; nc < NHID / 4; ++nc) {
+      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W2T + k * NHID + 4 * nc]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z2[4 * nc + j] = fmaf(w[j], x, z2[4 * nc + j]);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NA; ++n) z3out[n] = lds[V_B3 + n];
+#pragma unroll
+  for (int k = 0; k < NHID; ++k) {
+    const float x = fmaxf(z2[k], 0.0f);
+    const f4 w = *reinterpret_cast<const f4*>(&lds[V_W3T + k * NA]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z3out[j] = fmaf(w[j], x, z3out[j]);
+  }
+}
+
+// T steps of the whole step (observation, actor, action map, RK4, reward,
+// history push, termination, truncation, reset) with state and history kept
+// in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
+// the actor when non-NULL.  Inactive lanes of the last wave shadow the wave's
+// first env (read only) so every MFMA operand is finite.
+template <bool MFMA>
+__global__ void __launch_bounds__(256)
+k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
+        int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
+        float* __restrict__ states, float* __restrict__ tape, int ckpt_every) {
+  __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+  const int N = c.n_envs;
+  if (ext_act == nullptr) stage_actor<MFMA>(W, lds);
+  __syncthreads();
+  const int env = blockIdx.x * blockDim.x + threadIdx.x;
+  const int first = env - (threadIdx.x & 63);
+  if (first >= N) return;  // whole wave past the end
+  const bool active = env < N;
+  const int e = active ? env : first;
+
+  float th[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) th[i] = b.theta[i * N + e];
+  const Body<float> B = make_body<float>(th);
+  const bool renorm = (c.flags & F_RENORM_Q) != 0;
+
+  float x[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+  float H[NH * NA];
+  const int head0 = b.head[e];
+#pragma unroll
+  for (int sl = 0; sl < NH; ++sl) {
+    const int slot = (head0 + sl) & (NH - 1);
+#pragma unroll
+    for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
+  }
+  int t_ep = b.t_ep[e], ep = b.ep[e];
+  bool was_reset = false;
+
+  if (states && t_base == 0 && active)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) states[i * N + e] = x[i];
+
+  for (int t = 0; t < T; ++t) {
+    // Keeps the weight reads inside the step: hoisting them out of the time
+    // loop would pin thousands of loop-invariant values in registers.
+    __asm__ volatile("" ::: "memory");
+    const uint32_t eo = opaque((uint32_t)e);
+    const int gt = t_base + t;
+    if (tape && (gt % ckpt_every) == 0 && active) {
+      float* ck = tape + (size_t)(gt / ckpt_every) * (NS + NH * NA) * N;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) ck[(size_t)i * N + eo] = x[i];
+#pragma unroll
+      for (int i = 0; i < NH * NA; ++i) ck[(size_t)(NS + i) * N + eo] = H[i];
+    }
+    float a[NA];
+    if (ext_act) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) a[i] = ext_act[((size_t)t * NA + i) * N + eo];
+    } else {
+      float Rm[9];
+      rotmat(x + 3, Rm);
+      const float* s = x;
+      float z3[NA];
+      if (MFMA)
+        actor_mfma(lds, s, Rm, H, z3);
+      else
+        actor_valu(lds, s, Rm, H, z3);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
+    }
+    float u[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
+    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    const float r = reward(c, x, a);
+#pragma unroll
+    for (int i = 0; i < (NH - 1) * NA; ++i) H[i] = H[i + NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) H[(NH - 1) * NA + i] = a[i];
+    ++t_ep;
+    const uint32_t d = episode_end(c, x, t_ep);
+    if (d && (c.flags & F_AUTORESET)) {
+      ++ep;
+      t_ep = 0;
+      was_reset = true;
+      const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
+#pragma unroll
+      for (int i = 0; i < NH * NA; ++i) H[i] = ah;
+    }
+    if (active) {
+      if (rewards) rewards[(size_t)gt * N + eo] = r;
+      if (dones) dones[(size_t)gt * N + eo] = (uint8_t)d;
+      if (states)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
+    }
+  }
+  if (!active) return;
+  const uint32_t ef = opaque((uint32_t)e);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + ef] = x[i];
+  // The ring keeps slots older than this launch in place; only the T newest
+  // logical slots (all 32 after a reset) are written.
+  const int head1 = (head0 + T) & (NH - 1);
+#pragma unroll
+  for (int sl = 0; sl < NH; ++sl) {
+    if (was_reset || sl >= NH - T) {
+      const int slot = (head1 + sl) & (NH - 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) b.ring[(size_t)(slot * NA + a) * N + ef] = H[sl * NA + a];
+    }
+  }
+  b.head[ef] = head1;
+  b.t_ep[ef] = t_ep;
+  b.ep[ef] = ep;
+}
+#undef QS_FEAT
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(int n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_init(const DevCfg& c, const SimBufs& b, int params, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, params);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const SimBufs& b, int N, float* state, float* hist, int32_t* t_ep,
+                            int32_t* ep, hipStream_t st) {
+  hipLaunchKernelGGL(k_get_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, state, hist, t_ep,
+                     ep);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const SimBufs& b, int N, const float* state, const float* hist,
+                            const int32_t* t_ep, const int32_t* ep, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, state, hist, t_ep,
+                     ep);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs& p,
+                             const float* W, const float* ext_act, float* reward, uint8_t* done,
+                             float* state_out, hipStream_t st) {
+  const int N = c.n_envs;
+  const dim3 g(nblk(N, 256)), blk(256);
+  const float* act = ext_act;
+  if (!ext_act) {
+    hipLaunchKernelGGL(k_plain_obs, g, blk, 0, st, b, N, p.obs);
+    hipLaunchKernelGGL((k_plain_dense<NO, NHID, false>), g, blk, 0, st, N, W + OFF_W1, W + OFF_B1,
+                       p.obs, p.h1);
+    hipLaunchKernelGGL((k_plain_dense<NHID, NHID, false>), g, blk, 0, st, N, W + OFF_W2,
+                       W + OFF_B2, p.h1, p.h2);
+    hipLaunchKernelGGL((k_plain_dense<NHID, NA, true>), g, blk, 0, st, N, W + OFF_W3, W + OFF_B3,
+                       p.h2, p.act);
+    act = p.act;
+  }
+  hipLaunchKernelGGL(k_plain_dyn, g, blk, 0, st, c, b, act, reward, done, state_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
+                        const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
+                        float* states, float* tape, int ckpt_every, hipStream_t st) {
+  const dim3 g(nblk(c.n_envs, 256)), blk(256);
+  if (mfma)
+    hipLaunchKernelGGL(k_fused<true>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
+                       states, tape, ckpt_every);
+  else
+    hipLaunchKernelGGL(k_fused<false>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
+                       states, tape, ckpt_every);
+  return hipGetLastError();
+}
+
+}  // namespace qs

@@ -1,0 +1,147 @@
+"""QuadSim: Python handle over the C ABI.  Tensors are passed by device pointer
+with torch's current HIP stream; torch only supplies memory and streams."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class QuadSim:
+    """N quadrotor envs on one GPU.  cfg: dict with the sim_config fields (see
+    workloads.crazyflie_config)."""
+
+    def __init__(self, cfg: dict, device: int = 0):
+        self.L = _lib.load()
+        self.cfg = dict(cfg)
+        self.N = int(cfg["n_envs"])
+        self.device = torch.device("cuda", device)
+        c = _lib.make_config(cfg)
+        h = ctypes.c_void_p()
+        check(self.L.sim_create(ctypes.byref(c), device, ctypes.byref(h)), "sim_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(self.L.sim_destroy(self.h), "sim_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ------------------------------------------------------------
+    def _f32(self, *shape):
+        return torch.empty(*shape, dtype=torch.float32, device=self.device)
+
+    def actor_tensor(self, w) -> torch.Tensor:
+        t = torch.as_tensor(w, dtype=torch.float32).to(self.device).contiguous()
+        if t.numel() != _lib.SIM_NACTOR:
+            raise ValueError(f"actor must have {_lib.SIM_NACTOR} parameters")
+        return t
+
+    # -- calls ----------------------------------------------------------------
+    def reset(self, seed: int | None = None):
+        s = self.cfg["seed"] if seed is None else seed
+        check(self.L.sim_reset(self.h, ctypes.c_uint64(s), _stream()), "sim_reset")
+
+    def step(self, actor: torch.Tensor | None = None, actions: torch.Tensor | None = None):
+        """One step; returns (reward [N], done [N] uint8)."""
+        r = self._f32(self.N)
+        d = torch.empty(self.N, dtype=torch.uint8, device=self.device)
+        check(self.L.sim_step(self.h, _ptr(actor), _ptr(actions), _ptr(r), _ptr(d), _stream()),
+              "sim_step")
+        return r, d
+
+    def rollout(self, actor: torch.Tensor, T: int, rewards=True, dones=True, states=False,
+                record_tape=False, out=None):
+        """T steps.  Returns dict with rewards [T][N], dones [T][N], states
+        [T+1][17][N] (each only when requested).  out= reuses tensors."""
+        out = {} if out is None else out
+        if rewards and "rewards" not in out:
+            out["rewards"] = self._f32(T, self.N)
+        if dones and "dones" not in out:
+            out["dones"] = torch.empty(T, self.N, dtype=torch.uint8, device=self.device)
+        if states and "states" not in out:
+            out["states"] = self._f32(T + 1, 17, self.N)
+        check(self.L.sim_rollout(self.h, _ptr(actor), T, _ptr(out.get("rewards")),
+                                 _ptr(out.get("dones")), _ptr(out.get("states")),
+                                 1 if record_tape else 0, _stream()), "sim_rollout")
+        return out
+
+    def backward(self, actor: torch.Tensor, d_rewards=None, d_states=None, want_actor=True,
+                 want_params=True):
+        ga = torch.empty(_lib.SIM_NACTOR, dtype=torch.float32, device=self.device) if want_actor else None
+        gp = self._f32(8, self.N) if want_params else None
+        check(self.L.sim_backward(self.h, _ptr(actor), _ptr(d_rewards), _ptr(d_states), _ptr(ga),
+                                  _ptr(gp), _stream()), "sim_backward")
+        return ga, gp
+
+    def get_state(self):
+        s = self._f32(17, self.N)
+        hist = self._f32(32, 4, self.N)
+        t = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        e = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        check(self.L.sim_get_state(self.h, _ptr(s), _ptr(hist), _ptr(t), _ptr(e), _stream()),
+              "sim_get_state")
+        return dict(state=s, hist=hist, t_ep=t, episode=e)
+
+    def set_state(self, state=None, hist=None, t_ep=None, episode=None):
+        def dev(x, dt):
+            return None if x is None else torch.as_tensor(x, dtype=dt).to(self.device).contiguous()
+        s, h = dev(state, torch.float32), dev(hist, torch.float32)
+        t, e = dev(t_ep, torch.int32), dev(episode, torch.int32)
+        check(self.L.sim_set_state(self.h, _ptr(s), _ptr(h), _ptr(t), _ptr(e), _stream()),
+              "sim_set_state")
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self):
+        th = self._f32(8, self.N)
+        check(self.L.sim_get_params(self.h, _ptr(th), _stream()), "sim_get_params")
+        return th
+
+    def set_params(self, theta):
+        th = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()
+        check(self.L.sim_set_params(self.h, _ptr(th), _stream()), "sim_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def set_variant(self, variant: int, steps_per_launch: int = 0, use_graph: bool = True):
+        check(self.L.sim_set_variant(self.h, variant, steps_per_launch, 1 if use_graph else 0),
+              "sim_set_variant")
+
+    def get_variant(self):
+        v, s, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(self.L.sim_get_variant(self.h, ctypes.byref(v), ctypes.byref(s), ctypes.byref(g)),
+              "sim_get_variant")
+        return v.value, s.value, g.value
+
+    def autotune(self, actor: torch.Tensor, T: int):
+        v, ms = ctypes.c_int(), ctypes.c_float()
+        check(self.L.sim_autotune(self.h, _ptr(actor), T, _stream(), ctypes.byref(v),
+                                  ctypes.byref(ms)), "sim_autotune")
+        return v.value, ms.value
+
+    def last_rollout_timing(self):
+        ms, n = ctypes.c_float(), ctypes.c_int()
+        check(self.L.sim_last_rollout_timing(self.h, ctypes.byref(ms), ctypes.byref(n)),
+              "sim_last_rollout_timing")
+        return ms.value, n.value

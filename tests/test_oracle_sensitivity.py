@@ -1,0 +1,30 @@
+"""Closed-loop sensitivity of the fwd64 workload, from the FP64 oracle alone.
+
+Under the seeded Xavier actor the bodies spin up to hundreds of rad/s within
+64 steps, and a single float32-sized perturbation of the start state (each
+component times 1 +- 2^-24) grows past 1e-4 in the per-step error norm.  This
+is why the GPU trajectory bar is stated relative to this envelope: even an
+exact-arithmetic integrator fed float32 start states could not stay within
+1e-4 of the FP64 trajectory for 64 steps."""
+import numpy as np
+
+import workloads as wl
+from parity import oracle_envelope
+
+
+def test_float32_sized_perturbation_grows_past_1e4_within_64_steps(oracle_lib):
+    cfg = wl.workload_config("fwd64")
+    W = wl.xavier_actor(0)
+    env, base = oracle_envelope(oracle_lib, cfg, W, 64, 64)
+    assert env[1] < 1e-5                   # one step: inside the per-step bar
+    assert env.max() > 1e-4                # 64 steps: beyond the 1e-4 bar
+    w = np.linalg.norm(base[64, :, 10:13], axis=1)
+    assert np.median(w) > 100.0            # the bodies spin fast by then
+
+
+def test_envelope_is_deterministic(oracle_lib):
+    cfg = wl.workload_config("fwd64")
+    W = wl.xavier_actor(0)
+    a, _ = oracle_envelope(oracle_lib, cfg, W, 16, 16)
+    b, _ = oracle_envelope(oracle_lib, cfg, W, 16, 16)
+    assert np.array_equal(a, b)
