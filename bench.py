@@ -87,8 +87,8 @@ def cpu_baseline(cfg, W, seconds):
     t0 = time.perf_counter()
     b.rollout(W, 20, nthreads=nthreads)
     rate = len(probe_ids) * 20 / max(time.perf_counter() - t0, 1e-6)
-    steps = 200
-    n = int(max(nthreads, min(N, rate * seconds / steps)))
+    n = int(max(nthreads, min(N, rate * seconds / 200)))
+    steps = int(max(20, min(1000, rate * seconds / n)))
     ids = np.linspace(0, N - 1, n).astype(np.uint32)
     b = oracle.Batch.init(cfg, n, ids=ids)
     t0 = time.perf_counter()

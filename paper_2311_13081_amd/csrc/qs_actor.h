@@ -1,0 +1,232 @@
+// Actor MLP building blocks shared by the forward and backward kernels: LDS
+// layouts of the staged weights, staging, and the two forward evaluations
+// (vector ALUs, fp32 matrix cores).
+#pragma once
+#include "qs_device.h"
+
+namespace qs {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16 __attribute__((ext_vector_type(16)));
+
+// LDS layouts (floats).
+// MFMA: W1 row-major [64][148] (k padded), b1, W2 [64][68], b2, W3 [16][68]
+// (rows 4..15 zero), b3.  Row pitches keep 16-byte alignment and spread the
+// 16 rows one 16-lane group reads over distinct banks.
+constexpr int M_W1_LD = 148, M_W2_LD = 68;
+constexpr int M_W1 = 0, M_B1 = M_W1 + NHID * M_W1_LD, M_W2 = M_B1 + NHID,
+              M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + 16 * M_W2_LD,
+              M_TOTAL = M_B3 + 4;
+// VALU: transposed weights so consecutive outputs are consecutive floats.
+constexpr int V_W1T = 0, V_B1 = V_W1T + NO * NHID, V_W2T = V_B1 + NHID,
+              V_B2 = V_W2T + NHID * NHID, V_W3T = V_B2 + NHID, V_B3 = V_W3T + NHID * NA,
+              V_TOTAL = V_B3 + NA;
+constexpr int LDS_FLOATS = M_TOTAL > V_TOTAL ? M_TOTAL : V_TOTAL;
+
+template <bool MFMA>
+__device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (MFMA) {
+    for (int i = tid; i < NHID * M_W1_LD; i += nt) {
+      const int r = i / M_W1_LD, k = i % M_W1_LD;
+      lds[M_W1 + i] = k < NO ? W[OFF_W1 + r * NO + k] : 0.0f;
+    }
+    for (int i = tid; i < NHID * M_W2_LD; i += nt) {
+      const int r = i / M_W2_LD, k = i % M_W2_LD;
+      lds[M_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
+    }
+    for (int i = tid; i < 16 * M_W2_LD; i += nt) {
+      const int r = i / M_W2_LD, k = i % M_W2_LD;
+      lds[M_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
+    }
+    for (int i = tid; i < NHID; i += nt) {
+      lds[M_B1 + i] = W[OFF_B1 + i];
+      lds[M_B2 + i] = W[OFF_B2 + i];
+    }
+    for (int i = tid; i < 4; i += nt) lds[M_B3 + i] = W[OFF_B3 + i];
+  } else {
+    for (int i = tid; i < NO * NHID; i += nt) {
+      const int k = i / NHID, n = i % NHID;
+      lds[V_W1T + i] = W[OFF_W1 + n * NO + k];
+    }
+    for (int i = tid; i < NHID * NHID; i += nt) {
+      const int k = i / NHID, n = i % NHID;
+      lds[V_W2T + i] = W[OFF_W2 + n * NHID + k];
+    }
+    for (int i = tid; i < NHID * NA; i += nt) {
+      const int k = i / NA, n = i % NA;
+      lds[V_W3T + i] = W[OFF_W3 + n * NHID + k];
+    }
+    for (int i = tid; i < NHID; i += nt) {
+      lds[V_B1 + i] = W[OFF_B1 + i];
+      lds[V_B2 + i] = W[OFF_B2 + i];
+    }
+    for (int i = tid; i < NA; i += nt) lds[V_B3 + i] = W[OFF_B3 + i];
+  }
+}
+
+// Observation feature k of this lane's env (compile-time k after unrolling).
+#define QS_FEAT(k)                                                                  \
+  ((k) < 3 ? s[(k)] : (k) < 12 ? Rm[(k)-3] : (k) < 15 ? s[(k)-12 + 7] : (k) < 18 ? \
+   s[(k)-15 + 10] : H[(k)-18])
+
+// Actor on matrix cores.  Each wave evaluates its 64 envs together:
+//  layer 1: 146 rank-1 updates per 16-neuron tile with the 4-block
+//           16x16x1 fp32 MFMA; B = feature k of the 64 envs (one per lane,
+//           4 blocks of 16 envs), A = weights of 16 neurons broadcast to the
+//           4 blocks.  The result registers hold (neuron, env) tiles.
+//  layer 2/3: 16x16x4 fp32 MFMA.  A result register of the previous layer is
+//           directly a B operand whose K-chunk is 4 neurons {4g+v}; the
+//           weights are read in the matching order.  Layer 3 uses 4 of 16
+//           rows.
+//  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
+__device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
+                                  const float H[NH * NA], float z3out[NA],
+                                  float* __restrict__ rz1 = nullptr,
+                                  float* __restrict__ rz2 = nullptr, int N = 0, int env0 = 0) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  f16 acc1[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc1[n][r] = lds[M_B1 + 16 * n + 4 * lg + (r & 3)];
+#pragma unroll
+  for (int kc = 0; kc < (NO + 3) / 4; ++kc) {
+    f4 w[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      w[n] = *reinterpret_cast<const f4*>(&lds[M_W1 + (16 * n + li) * M_W1_LD + 4 * kc]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kc + kk;
+      if (k < NO) {
+        const float x = QS_FEAT(k);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], x, acc1[n], 0, 0, 0);
+      }
+    }
+  }
+  // Optional record of the layer-1 pre-activations: register r of tile n holds
+  // neuron 16n + 4lg + (r&3) of env env0 + 16(r>>2) + li.
+  if (rz1) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int env = env0 + 16 * (r >> 2) + li;
+        if (env < N) rz1[(size_t)(16 * n + 4 * lg + (r & 3)) * N + env] = acc1[n][r];
+      }
+  }
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
+
+  f4 acc2[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = lds[M_B2 + 16 * n2 + 4 * lg + r];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const f4 w =
+          *reinterpret_cast<const f4*>(&lds[M_W2 + (16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          acc2[n2][bb] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][4 * bb + v], acc2[n2][bb], 0, 0, 0);
+    }
+  if (rz2) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int env = env0 + 16 * bb + li;
+          if (env < N) rz2[(size_t)(16 * n2 + 4 * lg + r) * N + env] = acc2[n2][bb][r];
+        }
+  }
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = fmaxf(acc2[n2][bb][r], 0.0f);
+
+  f4 acc3[4];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc3[bb][r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + li * M_W2_LD + 16 * n2 + 4 * lg]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][bb][v], acc3[bb], 0, 0, 0);
+  }
+  // lanes 0..15 of block bb hold z3[o] of env 16 bb + lane in register o.
+  const int src = li << 2;
+#pragma unroll
+  for (int o = 0; o < NA; ++o) {
+    float v[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+      v[bb] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[bb][o])));
+    z3out[o] = lg == 0 ? v[0] : lg == 1 ? v[1] : lg == 2 ? v[2] : v[3];
+  }
+}
+
+// Actor on the vector ALUs, one env per lane, weights broadcast from LDS.
+__device__ inline void actor_valu(const float* lds, const float s[NS], const float Rm[9],
+                                  const float H[NH * NA], float z3out[NA]) {
+  float z1[NHID];
+#pragma unroll
+  for (int n = 0; n < NHID; ++n) z1[n] = lds[V_B1 + n];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const float x = QS_FEAT(k);
+#pragma unroll
+    for (int nc = 0; nc < NHID / 4; ++nc) {
+      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W1T + k * NHID + 4 * nc]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z1[4 * nc + j] = fmaf(w[j], x, z1[4 * nc + j]);
+    }
+  }
+  float z2[NHID];
+#pragma unroll
+  for (int n = 0; n < NHID; ++n) z2[n] = lds[V_B2 + n];
+#pragma unroll
+  for (int k = 0; k < NHID; ++k) {
+    const float x = fmaxf(z1[k], 0.0f);
+#pragma unroll
+    for (int nc = 0; nc < NHID / 4; ++nc) {
+      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W2T + k * NHID + 4 * nc]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z2[4 * nc + j] = fmaf(w[j], x, z2[4 * nc + j]);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NA; ++n) z3out[n] = lds[V_B3 + n];
+#pragma unroll
+  for (int k = 0; k < NHID; ++k) {
+    const float x = fmaxf(z2[k], 0.0f);
+    const f4 w = *reinterpret_cast<const f4*>(&lds[V_W3T + k * NA]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z3out[j] = fmaf(w[j], x, z3out[j]);
+  }
+}
+
+
+}  // namespace qs

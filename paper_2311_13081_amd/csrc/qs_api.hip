@@ -342,7 +342,10 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   int rc = sticky_error();
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const int v = effective_variant(h);
+  // A taped rollout always runs on the fused MFMA kernel: the backward pass
+  // recomputes segments with that kernel, and the recompute must reproduce
+  // the forward trajectory bit for bit.
+  const int v = record_tape ? SIM_V_FUSED_MFMA : effective_variant(h);
   const int spl = effective_spl(h);
   float* tape = record_tape ? h->tape : nullptr;
   h->tape_T = 0;

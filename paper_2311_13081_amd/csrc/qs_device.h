@@ -280,4 +280,115 @@ __device__ inline float action_to_rpm(const DevCfg& c, float a) {
   return c.rpm_min + (a + 1.0f) * c.rpm_half_range;
 }
 
+
+// ---------------------------------------------------------------------------
+// Vector-Jacobian products (discrete adjoint) of the maps above, single
+// precision.  Gradients with respect to the body parameters accumulate in
+// gth = d/d(m, Jxx, Jyy, Jzz, c0, c1, c2, Tm).
+// ---------------------------------------------------------------------------
+
+// VJP of deriv() at (x, u) with cotangent gd of dx: accumulates gx, gu, gth.
+__device__ inline void deriv_vjp(const Body<float>& B, const float th[NP], float arm, float km,
+                                 const float x[NS], const float u[4], const float gd[NS],
+                                 float gx[NS], float gu[4], float gth[NP]) {
+  const float w[4] = {x[13], x[14], x[15], x[16]};
+  float T[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) T[i] = B.c0 + w[i] * (B.c1 + B.c2 * w[i]);
+  const float F = (T[0] + T[1]) + (T[2] + T[3]);
+  const float tx = arm * ((T[2] + T[3]) - (T[0] + T[1]));
+  const float ty = arm * ((T[1] + T[2]) - (T[0] + T[3]));
+  const float tz = km * ((T[1] + T[3]) - (T[0] + T[2]));
+  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const float ox = x[10], oy = x[11], oz = x[12];
+  const float n2 = qw * qw + qx * qx + qy * qy + qz * qz;
+  const float inv_n2 = 1.0f / n2;
+  const float sc = F * B.inv_m * inv_n2;
+  // p' = v
+  gx[7] += gd[0];
+  gx[8] += gd[1];
+  gx[9] += gd[2];
+  // q' = 1/2 q (x) (0, w)
+  const float g3 = gd[3], g4 = gd[4], g5 = gd[5], g6 = gd[6];
+  gx[3] += 0.5f * (g4 * ox + g5 * oy + g6 * oz);
+  gx[4] += 0.5f * (-g3 * ox - g5 * oz + g6 * oy);
+  gx[5] += 0.5f * (-g3 * oy + g4 * oz - g6 * ox);
+  gx[6] += 0.5f * (-g3 * oz - g4 * oy + g5 * ox);
+  gx[10] += 0.5f * (-g3 * qx + g4 * qw + g5 * qz - g6 * qy);
+  gx[11] += 0.5f * (-g3 * qy - g4 * qz + g5 * qw + g6 * qx);
+  gx[12] += 0.5f * (-g3 * qz + g4 * qy - g5 * qx + g6 * qw);
+  // v' = sc * P(q) - g e_z,  P = (2(xz+wy), 2(yz-wx), |q|^2 - 2(x^2+y^2))
+  const float g7 = gd[7], g8 = gd[8], g9 = gd[9];
+  const float P0 = 2.0f * (qx * qz + qw * qy), P1 = 2.0f * (qy * qz - qw * qx),
+              P2 = n2 - 2.0f * (qx * qx + qy * qy);
+  const float gsc = g7 * P0 + g8 * P1 + g9 * P2;
+  const float k2 = 2.0f * gsc * sc * inv_n2;  // from sc's 1/|q|^2
+  gx[3] += 2.0f * sc * (g7 * qy - g8 * qx + g9 * qw) - k2 * qw;
+  gx[4] += 2.0f * sc * (g7 * qz - g8 * qw - g9 * qx) - k2 * qx;
+  gx[5] += 2.0f * sc * (g7 * qw + g8 * qz - g9 * qy) - k2 * qy;
+  gx[6] += 2.0f * sc * (g7 * qx + g8 * qy + g9 * qz) - k2 * qz;
+  const float gF = gsc * B.inv_m * inv_n2;
+  gth[0] += -gsc * sc * B.inv_m;
+  // w' = J^-1 (tau - w x J w)
+  const float hx = gd[10] * B.inv_Jx, hy = gd[11] * B.inv_Jy, hz = gd[12] * B.inv_Jz;
+  const float dwx = (tx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
+  const float dwy = (ty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
+  const float dwz = (tz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
+  gth[1] += -hx * dwx;
+  gth[2] += -hy * dwy;
+  gth[3] += -hz * dwz;
+  gx[11] += -hx * (B.Jz - B.Jy) * oz;
+  gx[12] += -hx * (B.Jz - B.Jy) * oy;
+  gth[3] += -hx * oy * oz;
+  gth[2] += hx * oy * oz;
+  gx[12] += -hy * (B.Jx - B.Jz) * ox;
+  gx[10] += -hy * (B.Jx - B.Jz) * oz;
+  gth[1] += -hy * oz * ox;
+  gth[3] += hy * oz * ox;
+  gx[10] += -hz * (B.Jy - B.Jx) * oy;
+  gx[11] += -hz * (B.Jy - B.Jx) * ox;
+  gth[2] += -hz * ox * oy;
+  gth[1] += hz * ox * oy;
+  // torques and collective thrust -> rotor thrusts
+  float gT[4];
+  gT[0] = gF - arm * (hx + hy) - km * hz;
+  gT[1] = gF - arm * hx + arm * hy + km * hz;
+  gT[2] = gF + arm * (hx + hy) - km * hz;
+  gT[3] = gF + arm * hx - arm * hy + km * hz;
+  // thrust curve T = c0 + c1 w + c2 w^2, motor lag w' = (u - w) / Tm
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    gth[4] += gT[i];
+    gth[5] += gT[i] * w[i];
+    gth[6] += gT[i] * w[i] * w[i];
+    const float gm = gd[13 + i];
+    gx[13 + i] += gT[i] * (B.c1 + 2.0f * B.c2 * w[i]) - gm * B.inv_Tm;
+    gu[i] += gm * B.inv_Tm;
+    gth[7] += -gm * (u[i] - w[i]) * B.inv_Tm * B.inv_Tm;
+  }
+  (void)th;
+}
+
+// VJP of rotmat(q) (R of q/|q|, row-major) with cotangent G: accumulates gq.
+__device__ inline void rotmat_vjp(const float q[4], const float G[9], float gq[4]) {
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  const float n2 = w * w + x * x + y * y + z * z;
+  const float s = 2.0f / n2;
+  const float dw = -z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7];
+  const float dx = y * G[1] + z * G[2] + y * G[3] - 2.0f * x * G[4] - w * G[5] + z * G[6] +
+                   w * G[7] - 2.0f * x * G[8];
+  const float dy = -2.0f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
+                   z * G[7] - 2.0f * y * G[8];
+  const float dz = -2.0f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0f * z * G[4] +
+                   y * G[5] + x * G[6] + y * G[7];
+  const float GP = -(y * y + z * z) * G[0] + (x * y - w * z) * G[1] + (x * z + w * y) * G[2] +
+                   (x * y + w * z) * G[3] - (x * x + z * z) * G[4] + (y * z - w * x) * G[5] +
+                   (x * z - w * y) * G[6] + (y * z + w * x) * G[7] - (x * x + y * y) * G[8];
+  const float k = 2.0f * s * GP / n2;
+  gq[0] += s * dw - k * w;
+  gq[1] += s * dx - k * x;
+  gq[2] += s * dy - k * y;
+  gq[3] += s * dz - k * z;
+}
+
 }  // namespace qs

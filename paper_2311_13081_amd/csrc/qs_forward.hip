@@ -5,6 +5,7 @@
 // Layout: one env per lane, struct-of-arrays in HBM ([K][N]) so every global
 // access of a wave is a contiguous 256-byte segment.  Actor weights are staged
 // in LDS once per workgroup.
+#include "qs_actor.h"
 #include "qs_forward.h"
 
 namespace qs {
@@ -186,214 +187,23 @@ __global__ void k_copy_state(SimBufs b, int N, float* __restrict__ out) {
 // Fused multi-step kernel
 // ---------------------------------------------------------------------------
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef float f16 __attribute__((ext_vector_type(16)));
-
-// LDS layouts (floats).
-// MFMA: W1 row-major [64][148] (k padded), b1, W2 [64][68], b2, W3 [16][68]
-// (rows 4..15 zero), b3.  Row pitches keep 16-byte alignment and spread the
-// 16 rows one 16-lane group reads over distinct banks.
-constexpr int M_W1_LD = 148, M_W2_LD = 68;
-constexpr int M_W1 = 0, M_B1 = M_W1 + NHID * M_W1_LD, M_W2 = M_B1 + NHID,
-              M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + 16 * M_W2_LD,
-              M_TOTAL = M_B3 + 4;
-// VALU: transposed weights so consecutive outputs are consecutive floats.
-constexpr int V_W1T = 0, V_B1 = V_W1T + NO * NHID, V_W2T = V_B1 + NHID,
-              V_B2 = V_W2T + NHID * NHID, V_W3T = V_B2 + NHID, V_B3 = V_W3T + NHID * NA,
-              V_TOTAL = V_B3 + NA;
-constexpr int LDS_FLOATS = M_TOTAL > V_TOTAL ? M_TOTAL : V_TOTAL;
-
-template <bool MFMA>
-__device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (MFMA) {
-    for (int i = tid; i < NHID * M_W1_LD; i += nt) {
-      const int r = i / M_W1_LD, k = i % M_W1_LD;
-      lds[M_W1 + i] = k < NO ? W[OFF_W1 + r * NO + k] : 0.0f;
-    }
-    for (int i = tid; i < NHID * M_W2_LD; i += nt) {
-      const int r = i / M_W2_LD, k = i % M_W2_LD;
-      lds[M_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
-    }
-    for (int i = tid; i < 16 * M_W2_LD; i += nt) {
-      const int r = i / M_W2_LD, k = i % M_W2_LD;
-      lds[M_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
-    }
-    for (int i = tid; i < NHID; i += nt) {
-      lds[M_B1 + i] = W[OFF_B1 + i];
-      lds[M_B2 + i] = W[OFF_B2 + i];
-    }
-    for (int i = tid; i < 4; i += nt) lds[M_B3 + i] = W[OFF_B3 + i];
-  } else {
-    for (int i = tid; i < NO * NHID; i += nt) {
-      const int k = i / NHID, n = i % NHID;
-      lds[V_W1T + i] = W[OFF_W1 + n * NO + k];
-    }
-    for (int i = tid; i < NHID * NHID; i += nt) {
-      const int k = i / NHID, n = i % NHID;
-      lds[V_W2T + i] = W[OFF_W2 + n * NHID + k];
-    }
-    for (int i = tid; i < NHID * NA; i += nt) {
-      const int k = i / NA, n = i % NA;
-      lds[V_W3T + i] = W[OFF_W3 + n * NHID + k];
-    }
-    for (int i = tid; i < NHID; i += nt) {
-      lds[V_B1 + i] = W[OFF_B1 + i];
-      lds[V_B2 + i] = W[OFF_B2 + i];
-    }
-    for (int i = tid; i < NA; i += nt) lds[V_B3 + i] = W[OFF_B3 + i];
-  }
-}
-
-// Observation feature k of this lane's env (compile-time k after unrolling).
-#define QS_FEAT(k)                                                                  \
-  ((k) < 3 ? s[(k)] : (k) < 12 ? Rm[(k)-3] : (k) < 15 ? s[(k)-12 + 7] : (k) < 18 ? \
-   s[(k)-15 + 10] : H[(k)-18])
-
-// Actor on matrix cores.  Each wave evaluates its 64 envs together:
-//  layer 1: 146 rank-1 updates per 16-neuron tile with the 4-block
-//           16x16x1 fp32 MFMA; B = feature k of the 64 envs (one per lane,
-//           4 blocks of 16 envs), A = weights of 16 neurons broadcast to the
-//           4 blocks.  The result registers hold (neuron, env) tiles.
-//  layer 2/3: 16x16x4 fp32 MFMA.  A result register of the previous layer is
-//           directly a B operand whose K-chunk is 4 neurons {4g+v}; the
-//           weights are read in the matching order.  Layer 3 uses 4 of 16
-//           rows.
-//  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
-__device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
-                                  const float H[NH * NA], float z3out[NA]) {
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lg = lane >> 4;
-  f16 acc1[4];
-#pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc1[n][r] = lds[M_B1 + 16 * n + 4 * lg + (r & 3)];
-#pragma unroll
-  for (int kc = 0; kc < (NO + 3) / 4; ++kc) {
-    f4 w[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-      w[n] = *reinterpret_cast<const f4*>(&lds[M_W1 + (16 * n + li) * M_W1_LD + 4 * kc]);
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kc + kk;
-      if (k < NO) {
-        const float x = QS_FEAT(k);
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], x, acc1[n], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
-
-  f4 acc2[4][4];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2)
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = lds[M_B2 + 16 * n2 + 4 * lg + r];
-#pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
-      const f4 w =
-          *reinterpret_cast<const f4*>(&lds[M_W2 + (16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb)
-          acc2[n2][bb] =
-              __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][4 * bb + v], acc2[n2][bb], 0, 0, 0);
-    }
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2)
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = fmaxf(acc2[n2][bb][r], 0.0f);
-
-  f4 acc3[4];
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc3[bb][r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) {
-    const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + li * M_W2_LD + 16 * n2 + 4 * lg]);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][bb][v], acc3[bb], 0, 0, 0);
-  }
-  // lanes 0..15 of block bb hold z3[o] of env 16 bb + lane in register o.
-  const int src = li << 2;
-#pragma unroll
-  for (int o = 0; o < NA; ++o) {
-    float v[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-      v[bb] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[bb][o])));
-    z3out[o] = lg == 0 ? v[0] : lg == 1 ? v[1] : lg == 2 ? v[2] : v[3];
-  }
-}
-
-// Actor on the vector ALUs, one env per lane, weights broadcast from LDS.
-__device__ inline void actor_valu(const float* lds, const float s[NS], const float Rm[9],
-                                  const float H[NH * NA], float z3out[NA]) {
-  float z1[NHID];
-#pragma unroll
-  for (int n = 0; n < NHID; ++n) z1[n] = lds[V_B1 + n];
-#pragma unroll
-  for (int k = 0; k < NO; ++k) {
-    const float x = QS_FEAT(k);
-#pragma unroll
-    for (int nc = 0; nc < NHID / 4; ++nc) {
-      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W1T + k * NHID + 4 * nc]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) z1[4 * nc + j] = fmaf(w[j], x, z1[4 * nc + j]);
-    }
-  }
-  float z2[NHID];
-#pragma unroll
-  for (int n = 0; n < NHID; ++n) z2[n] = lds[V_B2 + n];
-#pragma unroll
-  for (int k = 0; k < NHID; ++k) {
-    const float x = fmaxf(z1[k], 0.0f);
-#pragma unroll
-    for (int nc = 0; nc < NHID / 4; ++nc) {
-      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W2T + k * NHID + 4 * nc]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) z2[4 * nc + j] = fmaf(w[j], x, z2[4 * nc + j]);
-    }
-  }
-#pragma unroll
-  for (int n = 0; n < NA; ++n) z3out[n] = lds[V_B3 + n];
-#pragma unroll
-  for (int k = 0; k < NHID; ++k) {
-    const float x = fmaxf(z2[k], 0.0f);
-    const f4 w = *reinterpret_cast<const f4*>(&lds[V_W3T + k * NA]);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) z3out[j] = fmaf(w[j], x, z3out[j]);
-  }
-}
-
 // T steps of the whole step (observation, actor, action map, RK4, reward,
 // history push, termination, truncation, reset) with state and history kept
 // in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
 // the actor when non-NULL.  Inactive lanes of the last wave shadow the wave's
 // first env (read only) so every MFMA operand is finite.
+// Recompute mode of the backward pass (rec != NULL): the start state and
+// history come from checkpoint ck_in ([145][N], history oldest first); each
+// step records x_t, a_t, z1, z2 and o_t into rec ([T][REC_F][N]); nothing
+// else is written.  Record mode is a run-time switch rather than a template
+// parameter so that the taped forward and the recompute execute the same
+// machine code and produce bit-identical trajectories.
 template <bool MFMA>
 __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
-        float* __restrict__ states, float* __restrict__ tape, int ckpt_every) {
+        float* __restrict__ states, float* __restrict__ tape, int ckpt_every,
+        const float* __restrict__ ck_in, float* __restrict__ rec) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
   if (ext_act == nullptr) stage_actor<MFMA>(W, lds);
@@ -403,6 +213,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   if (first >= N) return;  // whole wave past the end
   const bool active = env < N;
   const int e = active ? env : first;
+  const bool REC = MFMA && rec != nullptr;
 
   float th[NP];
 #pragma unroll
@@ -411,17 +222,26 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
 
   float x[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
   float H[NH * NA];
-  const int head0 = b.head[e];
+  int head0 = 0, t_ep = 0, ep = 0;
+  if (REC) {
 #pragma unroll
-  for (int sl = 0; sl < NH; ++sl) {
-    const int slot = (head0 + sl) & (NH - 1);
+    for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
+    for (int i = 0; i < NH * NA; ++i) H[i] = ck_in[(size_t)(NS + i) * N + e];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+    head0 = b.head[e];
+#pragma unroll
+    for (int sl = 0; sl < NH; ++sl) {
+      const int slot = (head0 + sl) & (NH - 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
+    }
+    t_ep = b.t_ep[e];
+    ep = b.ep[e];
   }
-  int t_ep = b.t_ep[e], ep = b.ep[e];
   bool was_reset = false;
 
   if (states && t_base == 0 && active)
@@ -433,6 +253,9 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     // loop would pin thousands of loop-invariant values in registers.
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
+    // Re-read each step through an opaque copy so the optimiser cannot split
+    // the loop into separate record and no-record versions.
+    const bool rec_on = opaque(REC ? 1u : 0u) != 0u;
     const int gt = t_base + t;
     if (tape && (gt % ckpt_every) == 0 && active) {
       float* ck = tape + (size_t)(gt / ckpt_every) * (NS + NH * NA) * N;
@@ -442,6 +265,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       for (int i = 0; i < NH * NA; ++i) ck[(size_t)(NS + i) * N + eo] = H[i];
     }
     float a[NA];
+    float* rt = rec_on ? rec + (size_t)t * REC_F * N : nullptr;
     if (ext_act) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = ext_act[((size_t)t * NA + i) * N + eo];
@@ -451,11 +275,28 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       const float* s = x;
       float z3[NA];
       if (MFMA)
-        actor_mfma(lds, s, Rm, H, z3);
+        actor_mfma(lds, s, Rm, H, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
+                   rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, first);
       else
         actor_valu(lds, s, Rm, H, z3);
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
+      if (rec_on && active) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rt[(size_t)(REC_O + i) * N + eo] = s[i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rt[(size_t)(REC_O + 3 + i) * N + eo] = Rm[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) rt[(size_t)(REC_O + 12 + i) * N + eo] = s[7 + i];
+#pragma unroll
+        for (int i = 0; i < NH * NA; ++i) rt[(size_t)(REC_O + 18 + i) * N + eo] = H[i];
+      }
+    }
+    if (rec_on && active) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) rt[(size_t)(REC_X + i) * N + eo] = x[i];
+#pragma unroll
+      for (int i = 0; i < NA; ++i) rt[(size_t)(REC_A + i) * N + eo] = a[i];
     }
     float u[NA];
 #pragma unroll
@@ -484,7 +325,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
         for (int i = 0; i < NS; ++i) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
     }
   }
-  if (!active) return;
+  if (!active || REC) return;
   const uint32_t ef = opaque((uint32_t)e);
 #pragma unroll
   for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + ef] = x[i];
@@ -503,7 +344,6 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   b.t_ep[ef] = t_ep;
   b.ep[ef] = ep;
 }
-#undef QS_FEAT
 
 // ---------------------------------------------------------------------------
 // Host-side launchers
@@ -561,10 +401,18 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
   if (mfma)
     hipLaunchKernelGGL(k_fused<true>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
-                       states, tape, ckpt_every);
+                       states, tape, ckpt_every, nullptr, nullptr);
   else
     hipLaunchKernelGGL(k_fused<false>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
-                       states, tape, ckpt_every);
+                       states, tape, ckpt_every, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
+                            const float* ck_in, float* rec, hipStream_t st) {
+  const dim3 g(nblk(c.n_envs, 256)), blk(256);
+  hipLaunchKernelGGL(k_fused<true>, g, blk, 0, st, c, b, W, nullptr, T, 0, nullptr, nullptr,
+                     nullptr, nullptr, 1, ck_in, rec);
   return hipGetLastError();
 }
 

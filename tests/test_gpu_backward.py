@@ -1,0 +1,211 @@
+"""GPU discrete adjoint vs the FP64 oracle adjoint and FP64 central finite
+differences, through the C ABI and the autograd wrapper.
+
+Inputs: start states drawn by the oracle from the seed and rounded to float32,
+given identically to both sides.  Bars: actor gradient ||g - g_ref|| /
+||g_ref|| <= 1e-3; parameter gradients per env on the scaled parameters
+(each dtheta_i times theta_i) <= 1e-3.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2311_13081_amd as p
+    p.load()
+    return p
+
+
+def np_(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def param_scale(cfg, theta_aos):
+    """Per-parameter scale: its value; for zero-valued c0, c1 the size that
+    makes the term comparable (m g/4 and m g / (4 w_hover))."""
+    s = np.abs(theta_aos).astype(np.float64).copy()
+    mg4 = theta_aos[:, 0] * cfg["g"] / 4
+    wh = np.sqrt(mg4 / theta_aos[:, 6])
+    s[:, 4] = np.where(s[:, 4] == 0, mg4, s[:, 4])
+    s[:, 5] = np.where(s[:, 5] == 0, mg4 / wh, s[:, 5])
+    return s
+
+
+def setup(pkg, orc, n, T, K, dr=0, seed=0):
+    cfg = wl.crazyflie_config(n_envs=n, flags=wl.F_RENORM_Q, dr_enable=dr, max_episode_steps=0,
+                              max_tape_horizon=T, ckpt_every=K)
+    ob = orc.Batch.init(cfg, n)
+    s32, h32 = (x.astype(np.float32) for x in ob.soa())
+    sim = pkg.QuadSim(cfg)
+    sim.set_state(state=s32, hist=h32)
+    th = np_(sim.get_params())
+    ref = orc.Batch(cfg, n)
+    ref.set_soa(s32, h32, theta_soa=th)
+    return cfg, sim, ref, th
+
+
+def gpu_grad(sim, W, T, dR=None, dS=None):
+    a = sim.actor_tensor(W)
+    snap = {k: v.clone() for k, v in sim.get_state().items()}
+    sim.rollout(a, T, rewards=True, dones=False, states=True, record_tape=True)
+    dRt = None if dR is None else torch.as_tensor(dR, dtype=torch.float32).cuda()
+    dSt = None if dS is None else torch.as_tensor(dS, dtype=torch.float32).cuda()
+    ga, gp = sim.backward(a, d_rewards=dRt, d_states=dSt)
+    sim.set_state(**snap)
+    return np_(ga).astype(np.float64), np_(gp).astype(np.float64).T
+
+
+@pytest.mark.parametrize("n,T,K", [(64, 20, 8), (100, 16, 16), (257, 33, 5)])
+def test_backward_matches_oracle_adjoint(pkg, oracle_lib, n, T, K):
+    cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
+    W = wl.random_actor(4)
+    rng = np.random.default_rng(n)
+    dR = rng.uniform(0.5, 1.5, size=(T, n))
+    dS = rng.normal(size=(T + 1, 17, n)) * 1e-2
+    dS[:, 13:17] *= 1e-4
+    ga, gp = gpu_grad(sim, W, T, dR, dS)
+    J, gW, gth = ref.grad(W, T, dR=dR, dS=np.transpose(dS, (0, 2, 1)), nthreads=4)
+    ea = np.linalg.norm(ga - gW) / np.linalg.norm(gW)
+    sc = param_scale(cfg, th.T.astype(np.float64))
+    ep = np.linalg.norm((gp - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
+    print(f"n={n} T={T} K={K}: actor rel err {ea:.2e}, params max rel err {ep.max():.2e}")
+    assert ea < GRAD_TOL
+    assert ep.max() < GRAD_TOL
+    sim.close()
+
+
+def test_backward_grad1024_workload(pkg, oracle_lib):
+    """1024 envs, horizon 64, d(sum of rewards)/d(actor, params)."""
+    T = wl.workload_steps("grad1024")
+    cfg, sim, ref, th = setup(pkg, oracle_lib, 1024, T, 16, dr=0)
+    W = wl.xavier_actor(0)
+    ga, gp = gpu_grad(sim, W, T)
+    J, gW, gth = ref.grad(W, T, nthreads=8)
+    ea = np.linalg.norm(ga - gW) / np.linalg.norm(gW)
+    sc = param_scale(cfg, th.T.astype(np.float64))
+    ep = np.linalg.norm((gp - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
+    print(f"grad1024: actor rel err {ea:.2e}, params rel err max {ep.max():.2e} "
+          f"median {np.median(ep):.2e} p99 {np.quantile(ep, 0.99):.2e}")
+    assert ea < GRAD_TOL
+    assert np.median(ep) < GRAD_TOL
+    sim.close()
+
+
+def test_backward_vs_fp64_central_differences(pkg, oracle_lib):
+    """8 envs: GPU adjoint against FP64 central differences (step 1e-6,
+    relative for parameters) of the oracle's forward loss."""
+    orc = oracle_lib
+    n, T = 8, 24
+    cfg, sim, ref, th = setup(pkg, orc, n, T, 8, dr=1)
+    W = wl.random_actor(6)
+    ga, gp = gpu_grad(sim, W, T)
+    sc = param_scale(cfg, ref.theta)
+    eps = 1e-6
+    fd = np.zeros((n, 8))
+    for k in range(8):
+        bp, bm = ref.copy(), ref.copy()
+        bp.theta[:, k] += eps * sc[:, k]
+        bm.theta[:, k] -= eps * sc[:, k]
+        # envs are independent: one perturbed batch gives every env's derivative
+        for i in range(n):
+            b1, b2 = ref.copy(), ref.copy()
+            b1.theta[i, k] += eps * sc[i, k]
+            b2.theta[i, k] -= eps * sc[i, k]
+            J1, _, _ = b1.grad(W, T, want_grad=False)
+            J2, _, _ = b2.grad(W, T, want_grad=False)
+            fd[i, k] = (J1 - J2) / (2 * eps * sc[i, k])
+    ep = np.linalg.norm((gp - fd) * sc, axis=1) / np.linalg.norm(fd * sc, axis=1)
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([np.arange(9344, 9408), np.arange(13504, 13568), np.arange(13824, 13828),
+                          rng.choice(9344, 40, replace=False), 9408 + rng.choice(4096, 20, replace=False),
+                          13568 + rng.choice(256, 10, replace=False)])
+    fdw = np.zeros(len(idx))
+    for j, kk in enumerate(idx):
+        Wp = W.astype(np.float64).copy(); Wp[kk] += eps
+        Wm = W.astype(np.float64).copy(); Wm[kk] -= eps
+        fdw[j] = (ref.grad(Wp, T, want_grad=False)[0] - ref.grad(Wm, T, want_grad=False)[0]) / (2 * eps)
+    ea = np.linalg.norm(ga[idx] - fdw) / np.linalg.norm(fdw)
+    print(f"vs FD: params max rel err {ep.max():.2e}, actor (sampled) rel err {ea:.2e}")
+    assert ep.max() < GRAD_TOL
+    assert ea < GRAD_TOL
+    sim.close()
+
+
+def test_checkpoint_interval_does_not_change_param_gradient(pkg, oracle_lib):
+    """The recompute is bit-exact, so per-env parameter gradients are identical
+    for any checkpoint interval; actor gradients agree to fp32 summation
+    order."""
+    n, T = 300, 48
+    res = []
+    for K in (48, 16, 7, 1):
+        cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
+        W = wl.xavier_actor(0)
+        res.append(gpu_grad(sim, W, T))
+        sim.close()
+    for ga, gp in res[1:]:
+        assert np.array_equal(gp, res[0][1])
+        assert np.linalg.norm(ga - res[0][0]) / np.linalg.norm(res[0][0]) < 1e-5
+
+
+def test_backward_is_deterministic(pkg, oracle_lib):
+    cfg, sim, ref, th = setup(pkg, oracle_lib, 500, 32, 8, dr=1)
+    W = wl.xavier_actor(0)
+    a = gpu_grad(sim, W, 32)
+    b = gpu_grad(sim, W, 32)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    sim.close()
+
+
+def test_autograd_function(pkg, oracle_lib):
+    """RolloutFn: loss = sum of rewards + a state term; torch autograd gives
+    the same gradients as the direct C-ABI backward."""
+    n, T = 128, 24
+    cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, 8, dr=1)
+    W = wl.xavier_actor(0)
+    snap = {k: v.clone() for k, v in sim.get_state().items()}
+    actor = torch.as_tensor(W).cuda().requires_grad_(True)
+    theta = sim.get_params().clone().requires_grad_(True)
+    S, R = pkg.rollout(sim, actor, theta, T)
+    loss = R.sum() + 0.5 * (S[:, 0:3] ** 2).sum()
+    loss.backward()
+    sim.set_state(**snap)
+    dS = torch.zeros(T + 1, 17, n, device="cuda")
+    dS[:, 0:3] = S.detach()[:, 0:3]
+    ga, gp = gpu_grad(sim, W, T, dR=np.ones((T, n), np.float32), dS=np_(dS))
+    assert np.allclose(np_(actor.grad), ga, rtol=1e-6, atol=1e-6 * np.abs(ga).max())
+    assert np.allclose(np_(theta.grad).T, gp, rtol=1e-6, atol=0)
+    sim.close()
+
+
+def test_backward_state_errors(pkg):
+    from paper_2311_13081_amd import SimError
+    cfg = wl.crazyflie_config(n_envs=64, flags=wl.F_RENORM_Q, max_tape_horizon=10, ckpt_every=4)
+    sim = pkg.QuadSim(cfg)
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    with pytest.raises(SimError) as ei:
+        sim.backward(a)                         # no tape yet
+    assert ei.value.code == -4
+    with pytest.raises(SimError) as ei:
+        sim.rollout(a, 11, record_tape=True)    # beyond max_tape_horizon
+    assert ei.value.code == -1
+    sim.rollout(a, 10, record_tape=True)
+    sim.step(actor=a)                           # invalidates the tape
+    with pytest.raises(SimError):
+        sim.backward(a)
+    sim.close()
+    cfg2 = wl.crazyflie_config(n_envs=64, flags=wl.F_RENORM_Q | wl.F_TERMINATE,
+                               max_tape_horizon=10)
+    sim2 = pkg.QuadSim(cfg2)
+    with pytest.raises(SimError) as ei:
+        sim2.rollout(a, 5, record_tape=True)
+    assert ei.value.code == -4
+    sim2.close()
