@@ -37,6 +37,32 @@ PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
 PEAK_HBM = 8.0e12
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_mfma_fwd65536_dr_hbm_traffic.md")
+KERNEL_SOURCES = ("qs_device.h", "qs_actor.h", "qs_forward.hip")
+
+
+def measured_traffic(n_envs, steps_per_launch):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken or the launch
+    shape differs."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                  if line.startswith("    ") and ": " in line and not line.strip().startswith(("rocprofv3", "python3")))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_13081_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("sources_sha256") != h.hexdigest():
+        return None
+    if fields.get("launch_shape") != f"{n_envs} envs x {steps_per_launch} steps":
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +75,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain / per-step comparison legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (3 times): the "
+                         "reference for scaling HBM traffic counters")
     ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu"],
                     help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
                          "per rollout (used for profiling so only timed launches appear)")
@@ -99,6 +128,54 @@ def cpu_baseline(cfg, W, seconds):
                       f"{dt:.1f} s"}
 
 
+def fwd_bwd(torch, pkg, name, K, W, warmup=1):
+    """Forward rollout with tape + discrete adjoint on a differentiable
+    workload; returns env-steps/s of the pair (N x H per fwd+bwd)."""
+    cfg = wl.workload_config(name)
+    H = wl.workload_steps(name)
+    N = cfg["n_envs"]
+    sim = pkg.QuadSim(cfg)
+    a = sim.actor_tensor(W)
+    snap = {k: v.clone() for k, v in sim.get_state().items()}
+    if name.startswith("sysid"):
+        # ground truth with the randomised parameters theta*, then a perturbed
+        # body theta* (1 + delta), delta ~ U(-0.1, 0.1) (seed 3); loss = MSE
+        # over position, attitude, velocity and angular velocity
+        theta_star = sim.get_params().clone()
+        truth = sim.rollout(a, H, rewards=False, dones=False, states=True)["states"].clone()
+        g = torch.Generator(device="cpu").manual_seed(3)
+        delta = (torch.rand(theta_star.shape, generator=g) * 0.2 - 0.1).to(theta_star.device)
+        theta = theta_star * (1 + delta)
+    else:
+        truth = None
+        theta = sim.get_params().clone()
+
+    def one():
+        sim.set_state(**snap)
+        S, R = pkg.rollout(sim, a, theta, H)
+        if truth is not None:
+            d = S[:, :13] - truth[:, :13]
+            dS = torch.zeros_like(S)
+            dS[:, :13] = 2.0 * d / d.numel()
+            ga, gp = sim.backward(a, d_rewards=torch.zeros_like(R), d_states=dS)
+        else:
+            ga, gp = sim.backward(a)
+        return ga, gp
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    sim.close()
+    return {"env_steps_per_s": N * H / dt, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
+            "horizon": H, "ckpt_every": cfg["ckpt_every"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,6 +192,14 @@ def main():
     N = cfg["n_envs"]
     W = wl.xavier_actor(0)
 
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sim = pkg.QuadSim(cfg)
     actor = sim.actor_tensor(W)
     if args.variant == "auto":
@@ -148,7 +233,8 @@ def main():
                    "terminate_autoreset": True, "variant": vname, "steps_per_launch": spl,
                    "hipgraph": bool(graph), "launches_per_step": launches},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": (measured_traffic(N, T // launches) if v == 3 else None),
                      "kernel": f"k_fused<{'MFMA' if v == 3 else 'VALU'}>",
                      "kernel_ms": kernel_ms, "flop_per_env_step": FLOP_PER_ENV_STEP},
     }
@@ -172,6 +258,9 @@ def main():
         extras["fused_vs_plain_speedup"] = value / extras["plain_graph"]["env_steps_per_s"]
         res["comparison"] = extras
     sim.close()
+    if not args.no_extras:
+        res["fwd_bwd"] = {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
+                          "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0))}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, W, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -112,7 +112,6 @@ class QuadSim:
         t, e = dev(t_ep, torch.int32), dev(episode, torch.int32)
         check(self.L.sim_set_state(self.h, _ptr(s), _ptr(h), _ptr(t), _ptr(e), _stream()),
               "sim_set_state")
-        torch.cuda.current_stream().synchronize()
 
     def get_params(self):
         th = self._f32(8, self.N)
@@ -122,7 +121,6 @@ class QuadSim:
     def set_params(self, theta):
         th = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()
         check(self.L.sim_set_params(self.h, _ptr(th), _stream()), "sim_set_params")
-        torch.cuda.current_stream().synchronize()
 
     def set_variant(self, variant: int, steps_per_launch: int = 0, use_graph: bool = True):
         check(self.L.sim_set_variant(self.h, variant, steps_per_launch, 1 if use_graph else 0),

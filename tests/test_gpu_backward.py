@@ -209,3 +209,81 @@ def test_backward_state_errors(pkg):
         sim2.rollout(a, 5, record_tape=True)
     assert ei.value.code == -4
     sim2.close()
+
+
+def test_sysid16384_full_size(pkg, oracle_lib):
+    """System identification at full size: 16384 randomised envs, horizon
+    256, checkpoints every 16 steps.  Loss = MSE over (p, q, v, w) between a
+    rollout with theta = theta* (1 + delta) and the ground truth with theta*.
+    At delta = 0 the loss and every gradient are exactly zero; otherwise the
+    gradient is finite and a small step along it lowers the loss.  Sampled
+    envs of the same batch match the oracle's per-env VJP over 32 steps."""
+    orc = oracle_lib
+    cfg = wl.workload_config("sysid16384")
+    H = wl.workload_steps("sysid16384")
+    N = cfg["n_envs"]
+    sim = pkg.QuadSim(cfg)
+    W = wl.sysid_actor(0)
+    a = sim.actor_tensor(W)
+    snap = {k: v.clone() for k, v in sim.get_state().items()}
+    theta_star = sim.get_params().clone()
+    truth = sim.rollout(a, H, rewards=False, dones=False, states=True)["states"].clone()
+    assert bool(torch.isfinite(truth).all())
+
+    def loss_and_grad(theta):
+        sim.set_state(**snap)
+        S, R = pkg.rollout(sim, a, theta, H)
+        d = S[:, :13] - truth[:, :13]
+        L = float((d.double() ** 2).mean())
+        dS = torch.zeros_like(S)
+        dS[:, :13] = 2.0 * d / d.numel()
+        ga, gp = sim.backward(a, d_rewards=torch.zeros_like(R), d_states=dS)
+        return L, np_(ga), np_(gp)
+
+    L0, ga0, gp0 = loss_and_grad(theta_star)
+    assert L0 == 0.0 and not ga0.any() and not gp0.any()
+    g = torch.Generator().manual_seed(3)
+    delta = (torch.rand(theta_star.shape, generator=g) * 0.2 - 0.1).cuda()
+    theta = theta_star * (1 + delta)
+    L1, ga1, gp1 = loss_and_grad(theta)
+    assert L1 > 0 and np.all(np.isfinite(gp1)) and np.all(np.isfinite(ga1))
+    # a small step along -g, per env in scaled coordinates, lowers the loss
+    th = np_(theta).astype(np.float64)
+    sc = param_scale(cfg, np.abs(th.T) + 0)  # [N][8]
+    gs = gp1.T.astype(np.float64) * sc
+    direction = -gs / np.maximum(np.abs(gs).max(axis=1, keepdims=True), 1e-30) * sc
+    L2 = {}
+    for eta in (1e-3, 1e-4, 1e-5, 1e-6):
+        L2[eta], _, _ = loss_and_grad(
+            torch.as_tensor((th.T + eta * direction).T, dtype=torch.float32).cuda())
+    print(f"sysid16384: L(delta=0)={L0}, L1={L1:.6e}, after steps {L2}")
+    assert min(L2.values()) < L1
+
+    # sampled per-env VJP parity inside the full batch (horizon 32)
+    T = 32
+    ids = np.random.default_rng(7).choice(N, 32, replace=False).astype(np.uint32)
+    ob = orc.Batch.init(cfg, len(ids), ids=ids)
+    s32, h32 = (x.astype(np.float32) for x in ob.soa())
+    st = {k: v.clone() for k, v in snap.items()}
+    idx = torch.as_tensor(ids.astype(np.int64)).cuda()
+    st["state"][:, idx] = torch.as_tensor(s32).cuda()
+    st["hist"][:, :, idx] = torch.as_tensor(h32).cuda()
+    sim.set_params(theta_star)
+    sim.set_state(**st)
+    rng = np.random.default_rng(11)
+    dS = (rng.normal(size=(T + 1, 17, N)) * 1e-3).astype(np.float32)
+    dS[:, 13:17] *= 1e-4
+    sim.rollout(a, T, rewards=False, dones=False, record_tape=True)
+    _, gp = sim.backward(a, d_rewards=torch.zeros(T, N).cuda(),
+                         d_states=torch.as_tensor(dS).cuda())
+    gp = np_(gp).T[ids].astype(np.float64)
+    ref = orc.Batch(cfg, len(ids), ids=ids)
+    ref.set_soa(s32, h32, theta_soa=np_(theta_star)[:, ids])
+    _, _, gth = ref.grad(W, T, dR=np.zeros((T, len(ids))),
+                         dS=np.transpose(dS[:, :, ids], (0, 2, 1)).astype(np.float64),
+                         nthreads=8)
+    sc = param_scale(cfg, ref.theta)
+    ep = np.linalg.norm((gp - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
+    print(f"sysid16384 sampled VJP (H=32): max rel err {ep.max():.2e}, median {np.median(ep):.2e}")
+    assert ep.max() < GRAD_TOL
+    sim.close()

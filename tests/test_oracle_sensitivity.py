@@ -28,3 +28,16 @@ def test_envelope_is_deterministic(oracle_lib):
     a, _ = oracle_envelope(oracle_lib, cfg, W, 16, 16)
     b, _ = oracle_envelope(oracle_lib, cfg, W, 16, 16)
     assert np.array_equal(a, b)
+
+
+def test_sysid_actor_keeps_long_rollouts_finite(oracle_lib):
+    """The sys-ID workload rolls out 256 steps without termination.  The
+    plain Xavier policy drives part of the batch past the RK4 stability limit
+    (states overflow), the scaled, hover-biased policy does not."""
+    cfg = wl.workload_config("sysid16384", n_envs=48)
+    b = oracle_lib.Batch.init(cfg, 48)
+    S = b.copy().rollout(wl.sysid_actor(0), 256, record=True, nthreads=4)["states"]
+    assert np.isfinite(S).all()
+    assert np.abs(S[:, :, 10:13]).max() < 50.0
+    S2 = b.copy().rollout(wl.xavier_actor(0), 256, record=True, nthreads=4)["states"]
+    assert not np.isfinite(S2[-1]).all()

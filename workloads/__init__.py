@@ -129,6 +129,21 @@ def xavier_actor(seed: int = 0) -> np.ndarray:
     return w
 
 
+def sysid_actor(seed: int = 0, scale: float = 0.1) -> np.ndarray:
+    """Policy of the system-identification workload: the Xavier draw of
+    xavier_actor(seed) scaled by `scale`, with the output bias set so a zero
+    hidden state commands the nominal hover action (atanh(C_rab)).  The
+    unscaled Xavier policy spins a third of the bodies past the stability
+    limit of RK4 at dt = 0.01 s within 256 steps (their states overflow);
+    this one keeps 256-step rollouts finite while still feeding the state
+    back through all three layers."""
+    w = xavier_actor(seed).astype(np.float64)
+    n_w = NACTOR - NACT
+    w[:n_w] *= scale
+    w[n_w:] = math.atanh(HOVER_ACTION_NOMINAL)
+    return w.astype(np.float32)
+
+
 def random_actor(seed: int, scale: float = 1.0) -> np.ndarray:
     """Xavier weights with non-zero biases (so bias paths are exercised)."""
     w = xavier_actor(seed).astype(np.float64)
