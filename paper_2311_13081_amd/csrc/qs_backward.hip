@@ -41,18 +41,60 @@ __global__ void k_bwd_init(int N, const float* __restrict__ dS_T, float* __restr
   for (int i = 0; i < NP; ++i) gth[(size_t)i * N + e] = 0.0f;
 }
 
-// Reverse sweep over steps t0 + n - 1 .. t0 of one segment.
+// LDS layout of the reverse kernel (floats).  Transposed weights packed so
+// that each lane's MFMA A operand for 4 consecutive K-chunks is one 16-byte
+// read:
+//   R_W3: W3 row-major [4][64]; A of the 4-block 16x16x1 for dh2 = W3^T dz3.
+//   R_W2P[((n*4 + g)*4 + m)*16 + i][v] = W2[16n + 4g + v][16m + i]  (dh1 = W2^T dz2)
+//   R_W1P[((m*4 + g)*10 + f)*16 + i][v] = W1[16m + 4g + v][16f + i] (do = W1^T dz1),
+//     zero for features 16f + i >= 146.
+//   R_ST: per-wave 16 x 68 staging tile for moving do to one env per lane.
+constexpr int R_W3 = 0, R_W2P = R_W3 + NA * NHID, R_W1P = R_W2P + NHID * NHID,
+              R_ST = R_W1P + 10 * 16 * NHID, R_ST_P = 68, R_ST_SZ = 16 * R_ST_P,
+              R_TOTAL = R_ST + 4 * R_ST_SZ;
+
+__device__ inline void stage_reverse(const float* __restrict__ W, float* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < NA * NHID; i += nt) lds[R_W3 + i] = W[OFF_W3 + i];
+  for (int idx = tid; idx < NHID * NHID; idx += nt) {
+    const int v = idx & 3, i = (idx >> 2) & 15, m = (idx >> 6) & 3, g = (idx >> 8) & 3,
+              n = idx >> 10;
+    lds[R_W2P + idx] = W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i];
+  }
+  for (int idx = tid; idx < 10 * 16 * NHID; idx += nt) {
+    const int v = idx & 3, i = (idx >> 2) & 15, rest = idx >> 6;  // rest = (m*4 + g)*10 + f
+    const int f = rest % 10, g = (rest / 10) & 3, m = rest / 40;
+    const int feat = 16 * f + i;
+    lds[R_W1P + idx] = feat < NO ? W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat] : 0.0f;
+  }
+}
+
+// Reverse sweep over steps t0 + n - 1 .. t0 of one segment.  One env per lane
+// for the state adjoint, the history adjoint, the RK4/dynamics VJP and the
+// parameter gradients; the actor VJP runs on fp32 matrix cores for the wave's
+// 64 envs (the forward's layer chaining in reverse): dh2 = W3^T dz3 with the
+// 4-block 16x16x1 MFMA from the per-lane dz3, dh1 = W2^T dz2 and
+// do = W1^T dz1 with 16x16x4 MFMAs fed by the previous result registers.  do
+// comes out as (feature, env) tiles; each 16-feature tile goes through a
+// per-wave LDS tile to one env per lane, newest history feature first so the
+// history-adjoint shift can run in place.  Inactive lanes of the last wave
+// shadow the wave's first env (reads only).
 __global__ void __launch_bounds__(256)
 k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict__ W,
               const float* __restrict__ rec, int n, int t0, const float* __restrict__ d_rewards,
               const float* __restrict__ d_states, float* __restrict__ lam,
               float* __restrict__ gth_io, float* __restrict__ dz) {
-  __shared__ __attribute__((aligned(16))) float lds[V_TOTAL];
-  stage_actor<false>(W, lds);
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  stage_reverse(W, lds);
   __syncthreads();
   const int N = c.n_envs;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N) return;
+  const int env = blockIdx.x * blockDim.x + threadIdx.x;
+  const int first = env - (threadIdx.x & 63);
+  if (first >= N) return;
+  const bool active = env < N;
+  const int e = active ? env : first;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  float* stg = lds + R_ST + (threadIdx.x >> 6) * R_ST_SZ;
 
   float th[NP];
 #pragma unroll
@@ -74,6 +116,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     const uint32_t eo = opaque((uint32_t)e);
     const int t = t0 + tl;
     const float* rt = rec + (size_t)tl * REC_F * N;
+    float* dzt = dz + (size_t)tl * DZ_F * N;
     float x[NS], a[NA], u[NA];
 #pragma unroll
     for (int i = 0; i < NS; ++i) x[i] = rt[(size_t)(REC_X + i) * N + eo];
@@ -108,12 +151,11 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     float sn[NS];  // post-step state (renormalised)
 #pragma unroll
     for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + k[i]);
-    float qr[4] = {sn[3], sn[4], sn[5], sn[6]};
     float rn = 1.0f;
     if (renorm) {
-      rn = 1.0f / sqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+      rn = 1.0f / sqrtf(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sn[3 + i] = qr[i] * rn;
+      for (int i = 0; i < 4; ++i) sn[3 + i] *= rn;
     }
 
     // --- reward and history coupling -----------------------------------------
@@ -170,64 +212,124 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 #pragma unroll
     for (int i = 0; i < NA; ++i) ga[i] += gu[i] * c.rpm_half_range;
 
-    // --- actor: dz3 -> dz2 -> dz1 ---------------------------------------------
-    float* dzt = dz + (size_t)tl * DZ_F * N;
+    // --- actor VJP on matrix cores --------------------------------------------
+    // Pre-activations of the wave's 64 envs in the (neuron, env) tile layout:
+    // register r of tile q holds neuron 16q + 4lg + (r&3) of env
+    // first + 16(r>>2) + li (clamped to the last env for the ragged tail).
+    const int ed = opaque((uint32_t)(first + li));
+    float m2[4][16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ee = min(ed + 16 * (r >> 2), N - 1);
+        m2[q][r] = rt[(size_t)(REC_Z2 + 16 * q + 4 * lg + (r & 3)) * N + ee];
+      }
     float d3[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       d3[i] = ga[i] * (1.0f - a[i] * a[i]);
-      dzt[(size_t)(2 * NHID + i) * N + eo] = d3[i];
+      if (active) dzt[(size_t)(2 * NHID + i) * N + eo] = d3[i];
     }
-    float d2[NHID];
+    // dz2 = (W3^T dz3) * [z2 > 0]
+    f16 dz2[4];
 #pragma unroll
-    for (int kk = 0; kk < NHID; ++kk) {
-      const f4 w = *reinterpret_cast<const f4*>(&lds[V_W3T + kk * NA]);
-      const float v = w[0] * d3[0] + w[1] * d3[1] + w[2] * d3[2] + w[3] * d3[3];
-      const float z2 = rt[(size_t)(REC_Z2 + kk) * N + eo];
-      d2[kk] = z2 > 0.0f ? v : 0.0f;
-      dzt[(size_t)(NHID + kk) * N + eo] = d2[kk];
-    }
-    float d1[NHID];
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int kk = 0; kk < NHID; ++kk) {
-      float v = 0.0f;
+      for (int r = 0; r < 16; ++r) dz2[q][r] = 0.0f;
 #pragma unroll
-      for (int nc = 0; nc < NHID / 4; ++nc) {
-        const f4 w = *reinterpret_cast<const f4*>(&lds[V_W2T + kk * NHID + 4 * nc]);
-        v = fmaf(w[0], d2[4 * nc], v);
-        v = fmaf(w[1], d2[4 * nc + 1], v);
-        v = fmaf(w[2], d2[4 * nc + 2], v);
-        v = fmaf(w[3], d2[4 * nc + 3], v);
+      for (int o = 0; o < NA; ++o)
+        dz2[q] = __builtin_amdgcn_mfma_f32_16x16x1f32(lds[R_W3 + o * NHID + 16 * q + li], d3[o],
+                                                      dz2[q], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        dz2[q][r] = m2[q][r] > 0.0f ? dz2[q][r] : 0.0f;
+        const int ee = ed + 16 * (r >> 2);
+        if (ee < N) dzt[(size_t)(NHID + 16 * q + 4 * lg + (r & 3)) * N + ee] = dz2[q][r];
       }
-      const float z1 = rt[(size_t)(REC_Z1 + kk) * N + eo];
-      d1[kk] = z1 > 0.0f ? v : 0.0f;
-      dzt[(size_t)kk * N + eo] = d1[kk];
     }
-    // --- observation cotangent do = W1^T dz1, feature by feature -----------
-    // History features, newest first, so the shift reads older adjoints that
-    // are not yet overwritten: H_t[j] feeds H_{t+1}[j-1] (j >= 1).
+    float m1[4][16];
 #pragma unroll
-    for (int kk = NO - 1; kk >= 0; --kk) {
-      float v = 0.0f;
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int nc = 0; nc < NHID / 4; ++nc) {
-        const f4 w = *reinterpret_cast<const f4*>(&lds[V_W1T + kk * NHID + 4 * nc]);
-        v = fmaf(w[0], d1[4 * nc], v);
-        v = fmaf(w[1], d1[4 * nc + 1], v);
-        v = fmaf(w[2], d1[4 * nc + 2], v);
-        v = fmaf(w[3], d1[4 * nc + 3], v);
+      for (int r = 0; r < 16; ++r) {
+        const int ee = min(ed + 16 * (r >> 2), N - 1);
+        m1[q][r] = rt[(size_t)(REC_Z1 + 16 * q + 4 * lg + (r & 3)) * N + ee];
       }
-      if (kk >= 18) {
-        const int j = kk - 18;
-        lH[j] = (j >= NA ? lH[j - NA] : 0.0f) + v;
-      } else if (kk < 3) {
-        gx[kk] += v;
-      } else if (kk < 12) {
-        k[kk - 3] = v;  // reuse k[0..8] as the rotation-matrix cotangent
-      } else if (kk < 15) {
-        gx[7 + kk - 12] += v;
-      } else {
-        gx[10 + kk - 15] += v;
+    // dz1 = (W2^T dz2) * [z1 > 0]; tile m, env block b in dz1[m][4b .. 4b+3]
+    f16 dz1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f4 accb[4];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) accb[bb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4 w = *reinterpret_cast<const f4*>(
+            &lds[R_W2P + (((q * 4 + lg) * 4 + mt) * 16 + li) * 4]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb)
+            accb[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz2[q][4 * bb + v], accb[bb],
+                                                            0, 0, 0);
+      }
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float v = m1[mt][4 * bb + r] > 0.0f ? accb[bb][r] : 0.0f;
+          dz1[mt][4 * bb + r] = v;
+          const int ee = ed + 16 * bb;
+          if (ee < N) dzt[(size_t)(16 * mt + 4 * lg + r) * N + ee] = v;
+        }
+    }
+    // do = W1^T dz1, one 16-feature tile at a time, newest features first.
+#pragma unroll
+    for (int f = 9; f >= 0; --f) {
+      f4 accb[4];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) accb[bb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const f4 w = *reinterpret_cast<const f4*>(
+            &lds[R_W1P + (((mt * 4 + lg) * 10 + f) * 16 + li) * 4]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb)
+            accb[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz1[mt][4 * bb + v], accb[bb],
+                                                            0, 0, 0);
+      }
+      // tile -> one env per lane: row 4lg + r, column 16bb + li
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) stg[(4 * lg + r) * R_ST_P + 16 * bb + li] = accb[bb][r];
+      __builtin_amdgcn_wave_barrier();
+      float dob[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dob[r] = stg[r * R_ST_P + lane];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 15; r >= 0; --r) {
+        const int kk = 16 * f + r;
+        if (kk >= NO) continue;
+        const float v = dob[r];
+        if (kk >= 18) {
+          // H_t[j] feeds H_{t+1}[j-1] (j >= 1); j descending keeps older
+          // adjoints intact until read.
+          const int jj = kk - 18;
+          lH[jj] = (jj >= NA ? lH[jj - NA] : 0.0f) + v;
+        } else if (kk < 3) {
+          gx[kk] += v;
+        } else if (kk < 12) {
+          k[kk - 3] = v;  // rotation-matrix cotangent
+        } else if (kk < 15) {
+          gx[7 + kk - 12] += v;
+        } else {
+          gx[10 + kk - 15] += v;
+        }
       }
     }
     {
@@ -241,6 +343,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     for (int i = 0; i < NS; ++i)
       ls[i] = gx[i] + (d_states ? d_states[((size_t)t * NS + i) * N + eo] : 0.0f);
   }
+  if (!active) return;
   const uint32_t ef = opaque((uint32_t)e);
 #pragma unroll
   for (int i = 0; i < NS; ++i) lam[(size_t)i * N + ef] = ls[i];
@@ -281,34 +384,46 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
     const float* rt = rec + (size_t)tl * REC_F * N;
     const float* dzt = dz + (size_t)tl * DZ_F * N;
     __syncthreads();  // previous step's tiles consumed
-    // stage: each of the 64 columns is one env; rows are features
-    for (int idx = tid; idx < (DW_TOTAL / DW_P) * 64; idx += 256) {
-      const int row = idx >> 6, col = idx & 63;
-      const int env = env0 + col;
-      const bool ok = env < N;
-      float v = 0.0f;
-      if (row < NHID) {
-        v = ok ? dzt[(size_t)row * N + env] : 0.0f;
-      } else if (row < 2 * NHID) {
-        v = ok ? dzt[(size_t)row * N + env] : 0.0f;
+    // Stage the 64-env chunk: rows are features, columns envs.  Each thread
+    // moves 4 consecutive envs of a row; the loads of one pass are issued
+    // together (unrolled) so their latencies overlap.
+    const bool full = (env0 + 64 <= N) && ((N & 3) == 0);
+    const int c4 = (tid & 15) * 4;
+#pragma unroll 4
+    for (int row = tid >> 4; row < DW_TOTAL / DW_P; row += 16) {
+      const float* src = nullptr;
+      int kind = 0;  // 0: copy, 1: relu, 2: ones (valid envs), 3: zeros
+      if (row < 2 * NHID) {
+        src = dzt + (size_t)row * N;
       } else if (row < 2 * NHID + 16) {
         const int r = row - 2 * NHID;
-        v = (ok && r < NA) ? dzt[(size_t)(2 * NHID + r) * N + env] : 0.0f;
+        if (r < NA) src = dzt + (size_t)(2 * NHID + r) * N; else kind = 3;
       } else if (row < 2 * NHID + 16 + DW_O_ROWS) {
         const int r = row - (2 * NHID + 16);
-        v = !ok ? 0.0f : r < NO ? rt[(size_t)(REC_O + r) * N + env] : r == NO ? 1.0f : 0.0f;
+        if (r < NO) src = rt + (size_t)(REC_O + r) * N; else kind = r == NO ? 2 : 3;
       } else if (row < 2 * NHID + 16 + DW_O_ROWS + DW_H_ROWS) {
         const int r = row - (2 * NHID + 16 + DW_O_ROWS);
-        v = !ok ? 0.0f
-                : r < NHID ? fmaxf(rt[(size_t)(REC_Z1 + r) * N + env], 0.0f)
-                           : r == NHID ? 1.0f : 0.0f;
+        if (r < NHID) { src = rt + (size_t)(REC_Z1 + r) * N; kind = 1; } else kind = r == NHID ? 2 : 3;
       } else {
         const int r = row - (2 * NHID + 16 + DW_O_ROWS + DW_H_ROWS);
-        v = !ok ? 0.0f
-                : r < NHID ? fmaxf(rt[(size_t)(REC_Z2 + r) * N + env], 0.0f)
-                           : r == NHID ? 1.0f : 0.0f;
+        if (r < NHID) { src = rt + (size_t)(REC_Z2 + r) * N; kind = 1; } else kind = r == NHID ? 2 : 3;
       }
-      sm[row * DW_P + col] = v;
+      f4 v;
+      if (src) {
+        if (full) {
+          v = *reinterpret_cast<const f4*>(src + env0 + c4);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = env0 + c4 + q < N ? src[env0 + c4 + q] : 0.0f;
+        }
+        if (kind == 1)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.0f);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (kind == 2 && env0 + c4 + q < N) ? 1.0f : 0.0f;
+      }
+      *reinterpret_cast<f4*>(&sm[row * DW_P + c4]) = v;
     }
     __syncthreads();
 #pragma unroll
@@ -403,6 +518,10 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   if ((e = hipMalloc(&bw.gth, (size_t)NP * N * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gpart, (size_t)bw.n_parts * NW * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gsum, (size_t)NW * 4)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_bwd_reverse,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4)) !=
+      hipSuccess)
+    return e;
   return hipFuncSetAttribute((const void*)k_bwd_dw, hipFuncAttributeMaxDynamicSharedMemorySize,
                              DW_TOTAL * 4);
 }
@@ -429,8 +548,8 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
     const int n = (T - t0) < K ? (T - t0) : K;
     hipError_t e = launch_recompute(c, b, W, n, tape + (size_t)j * LAM_F * N, bw.seg, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 256)), dim3(256), 0, st, c, b.theta, W, bw.seg,
-                       n, t0, d_rewards, d_states, bw.lam, bw.gth, bw.dz);
+    hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 256)), dim3(256), R_TOTAL * 4, st, c, b.theta, W,
+                       bw.seg, n, t0, d_rewards, d_states, bw.lam, bw.gth, bw.dz);
     hipLaunchKernelGGL(k_bwd_dw, dim3(bw.n_parts), dim3(256), DW_TOTAL * 4, st, N, bw.seg, bw.dz,
                        n, bw.gpart);
   }
