@@ -37,28 +37,35 @@ PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
 PEAK_HBM = 8.0e12
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_mfma_fwd65536_dr_hbm_traffic.md")
-KERNEL_SOURCES = ("qs_device.h", "qs_actor.h", "qs_forward.hip")
+TRAFFIC_PROFILES = {
+    "k_fused<MFMA>": os.path.join(ROOT, "profiles", "k_fused_mfma_fwd65536_dr_hbm_traffic.md"),
+    "k_fused4<MFMA>": os.path.join(ROOT, "profiles", "k_fused4_mfma_fwd65536_dr_hbm_traffic.md"),
+}
 
 
-def measured_traffic(n_envs, steps_per_launch):
-    """HBM bytes per launch from the committed counter summary, or None when
-    the kernel sources changed since the counters were taken or the launch
-    shape differs."""
+def measured_traffic(kernel, n_envs, steps_per_launch):
+    """HBM bytes per launch from the committed counter summary of `kernel`,
+    or None when there is none, the kernel sources changed since the counters
+    were taken, or the launch shape differs."""
     import hashlib
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
+    path = TRAFFIC_PROFILES.get(kernel)
+    if path is None or not os.path.exists(path):
         return None
-    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
-                  if line.startswith("    ") and ": " in line and not line.strip().startswith(("rocprofv3", "python3")))
+    fields = {}
+    for line in open(path).read().splitlines():
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch", "launch_shape", "sources", "sources_sha256"):
+            if line.startswith(key + ": "):
+                fields[key] = line.split(": ", 1)[1]
+    if not {"traffic_bytes_per_launch", "launch_shape", "sources", "sources_sha256"} <= set(fields):
+        return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2311_13081_amd", "csrc", f), "rb") as fh:
+    for f in fields["sources"].split():
+        with open(os.path.join(ROOT, "paper_2311_13081_amd", "csrc", os.path.basename(f)), "rb") as fh:
             h.update(fh.read())
-    if fields.get("sources_sha256") != h.hexdigest():
+    if fields["sources_sha256"] != h.hexdigest():
         return None
-    if fields.get("launch_shape") != f"{n_envs} envs x {steps_per_launch} steps":
+    if fields["launch_shape"] != f"{n_envs} envs x {steps_per_launch} steps":
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -78,7 +85,7 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (3 times): the "
                          "reference for scaling HBM traffic counters")
-    ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu"],
+    ap.add_argument("--variant", default="auto", choices=["auto", "mfma4", "mfma", "valu"],
                     help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
                          "per rollout (used for profiling so only timed launches appear)")
     return ap.parse_args()
@@ -135,6 +142,7 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1):
     H = wl.workload_steps(name)
     N = cfg["n_envs"]
     sim = pkg.QuadSim(cfg)
+    sim.set_variant(pkg.SIM_V_FUSED_MFMA4)   # the kernel taped rollouts use
     a = sim.actor_tensor(W)
     snap = {k: v.clone() for k, v in sim.get_state().items()}
     if name.startswith("sysid"):
@@ -205,8 +213,8 @@ def main():
     if args.variant == "auto":
         sim.autotune(actor, T)
     else:
-        sim.set_variant(pkg.SIM_V_FUSED_MFMA if args.variant == "mfma" else pkg.SIM_V_FUSED_VALU,
-                        0, True)
+        sim.set_variant({"mfma4": pkg.SIM_V_FUSED_MFMA4, "mfma": pkg.SIM_V_FUSED_MFMA,
+                         "valu": pkg.SIM_V_FUSED_VALU}[args.variant], 0, True)
     v, spl, graph = sim.get_variant()
     wall, dev_ms, launches = time_rollouts(torch, sim, actor, T, args.steps, args.warmup)
     env_steps = N * T * args.steps
@@ -215,7 +223,9 @@ def main():
     kernel_ms = dev_ms / (args.steps * launches)
     flop_per_launch = FLOP_PER_ENV_STEP * N * (T / launches)
     achieved = flop_per_launch / (kernel_ms * 1e-3)
-    vname = {1: "plain", 2: "fused_valu", 3: "fused_mfma"}[v]
+    vname = {1: "plain", 2: "fused_valu", 3: "fused_mfma", 4: "fused_mfma4"}[v]
+    kname = {1: "plain (5 kernels)", 2: "k_fused<VALU>", 3: "k_fused<MFMA>",
+             4: "k_fused4<MFMA>"}[v]
     res = {
         "metric": METRIC,
         "value": value,
@@ -234,8 +244,8 @@ def main():
                    "hipgraph": bool(graph), "launches_per_step": launches},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": (measured_traffic(N, T // launches) if v == 3 else None),
-                     "kernel": f"k_fused<{'MFMA' if v == 3 else 'VALU'}>",
+                     "traffic": measured_traffic(kname, N, T // launches),
+                     "kernel": kname,
                      "kernel_ms": kernel_ms, "flop_per_env_step": FLOP_PER_ENV_STEP},
     }
     if not args.no_extras:

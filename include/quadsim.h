@@ -76,7 +76,11 @@ enum {
   SIM_V_AUTO = 0,        /* the autotuned choice (fused MFMA until tuned)         */
   SIM_V_PLAIN = 1,       /* five kernels per step, intermediates through HBM      */
   SIM_V_FUSED_VALU = 2,  /* one fused kernel, actor on the vector ALUs            */
-  SIM_V_FUSED_MFMA = 3   /* one fused kernel, actor on fp32 matrix cores          */
+  SIM_V_FUSED_MFMA = 3,  /* one fused kernel, actor on fp32 matrix cores, one env
+                            per lane (64 envs per wave)                           */
+  SIM_V_FUSED_MFMA4 = 4  /* one fused kernel, actor on fp32 matrix cores, four
+                            lanes per env (16 envs per wave); also the kernel of
+                            taped rollouts and of the backward recompute          */
 };
 
 typedef struct sim_config {
@@ -159,7 +163,8 @@ int sim_set_state(sim_handle* h, const float* state, const float* hist, const in
 int sim_get_params(sim_handle* h, float* theta, void* stream);
 int sim_set_params(sim_handle* h, const float* theta, void* stream);
 
-/* Chooses the forward variant (SIM_V_*), steps per launch for the fused
+/* Chooses the forward variant (SIM_V_*; taped rollouts always use
+ * SIM_V_FUSED_MFMA4, the kernel the backward pass recomputes with), steps per launch for the fused
  * variants (0 = whole rollout in one launch) and whether multi-launch
  * rollouts are replayed from a captured hipGraph (use_graph != 0). */
 int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph);

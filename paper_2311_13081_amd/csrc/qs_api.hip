@@ -200,7 +200,11 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
     const int chunk = (spl <= 0 || spl > T) ? T : spl;
     for (int t0 = 0; t0 < T; t0 += chunk) {
       const int n = (T - t0) < chunk ? (T - t0) : chunk;
-      HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, tape, K, st));
+      if (variant == SIM_V_FUSED_MFMA4)
+        HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
+                              st));
+      else
+        HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, tape, K, st));
       ++nl;
     }
   }
@@ -320,9 +324,14 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
   if (v == SIM_V_PLAIN) {
     HIP_TRY(launch_plain_step(h->dc, h->b, h->p, actor, actor ? nullptr : actions, reward, done,
                               nullptr, st));
+  } else if (v == SIM_V_FUSED_MFMA4 && actor) {
+    HIP_TRY(launch_fused4(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr,
+                          h->cfg.ckpt_every, nullptr, nullptr, st));
   } else {
-    HIP_TRY(launch_fused(v == SIM_V_FUSED_MFMA, h->dc, h->b, actor, actor ? nullptr : actions, 1, 0,
-                         reward, done, nullptr, nullptr, h->cfg.ckpt_every, st));
+    // external actions run on the one-env-per-lane kernel (it has the
+    // action-input path); both kernels share the state layout
+    HIP_TRY(launch_fused(v != SIM_V_FUSED_VALU, h->dc, h->b, actor, actor ? nullptr : actions, 1,
+                         0, reward, done, nullptr, nullptr, h->cfg.ckpt_every, st));
   }
   return SIM_OK;
 }
@@ -342,10 +351,10 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   int rc = sticky_error();
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  // A taped rollout always runs on the fused MFMA kernel: the backward pass
-  // recomputes segments with that kernel, and the recompute must reproduce
-  // the forward trajectory bit for bit.
-  const int v = record_tape ? SIM_V_FUSED_MFMA : effective_variant(h);
+  // A taped rollout always runs on the quarter-lane fused kernel: the
+  // backward pass recomputes segments with that kernel, and the recompute
+  // must reproduce the forward trajectory bit for bit.
+  const int v = record_tape ? SIM_V_FUSED_MFMA4 : effective_variant(h);
   const int spl = effective_spl(h);
   float* tape = record_tape ? h->tape : nullptr;
   h->tape_T = 0;
@@ -466,7 +475,8 @@ int sim_set_params(sim_handle* h, const float* theta, void* stream) {
 
 int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
-  if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_MFMA) return fail(SIM_E_INVAL, "unknown variant %d", variant);
+  if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_MFMA4)
+    return fail(SIM_E_INVAL, "unknown variant %d", variant);
   if (steps_per_launch < 0) return fail(SIM_E_INVAL, "steps_per_launch < 0");
   h->variant = variant;
   h->spl = steps_per_launch;
@@ -503,8 +513,9 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   HIP_TRY(hipMalloc(&s_ep, N * 4));
   HIP_TRY(launch_get_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
   struct Cand { int v, spl; };
-  std::vector<Cand> cands = {{SIM_V_FUSED_MFMA, 0}, {SIM_V_FUSED_MFMA, 100}, {SIM_V_FUSED_VALU, 0},
-                             {SIM_V_PLAIN, 0}};
+  std::vector<Cand> cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0},
+                             {SIM_V_FUSED_MFMA4, 100}, {SIM_V_FUSED_MFMA, 100},
+                             {SIM_V_FUSED_VALU, 0},  {SIM_V_PLAIN, 0}};
   const int save_v = h->variant, save_spl = h->spl;
   float best = 1e30f;
   Cand bestc = cands[0];

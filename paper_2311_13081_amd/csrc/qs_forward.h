@@ -29,6 +29,11 @@ constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z
 
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st);
+// Quarter-lane fused kernel (qs_fused4.hip): 16 envs per wave, 4 lanes per
+// env.  With rec != NULL it runs in recompute mode from checkpoint ck_in.
+hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
+                         float* rewards, uint8_t* dones, float* states, float* tape,
+                         int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
                         float* states, float* tape, int ckpt_every, hipStream_t st);

@@ -410,10 +410,8 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
 
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st) {
-  const dim3 g(nblk(c.n_envs, 256)), blk(256);
-  hipLaunchKernelGGL(k_fused<true>, g, blk, 0, st, c, b, W, nullptr, T, 0, nullptr, nullptr,
-                     nullptr, nullptr, 1, ck_in, rec);
-  return hipGetLastError();
+  // the kernel of taped rollouts, in record mode
+  return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, st);
 }
 
 }  // namespace qs

@@ -1,0 +1,299 @@
+// Fused multi-step kernel, quarter-lane layout: each wave advances 16 envs
+// and each env occupies 4 lanes (lane L = j + 16 k: env j of the wave,
+// quarter k).  Compared with the one-env-per-lane kernel this quadruples the
+// number of waves for a given batch (so small batches fill the chip and large
+// ones keep two waves per SIMD to overlap matrix-core and vector work) and
+// cuts the per-lane history from 128 to 32 registers.
+//
+// Observation layout across the 4 lanes of an env: register c of quarter k
+// holds feature PHI(c, k):
+//   c = 0..4:  state feature 4c + k (p, R row-major, v, w: 18 values; the two
+//              slots 4*4+2, 4*4+3 are padding);
+//   c = 5..36: action history slot c-5 (oldest first), component k.
+// This is exactly the B operand of v_mfma_f32_16x16x4f32 for 16 envs with
+// K-chunk c, so layer 1 is 37 x 4 MFMAs against W1 columns read in PHI order
+// (zeros for padding).  Layers 2 and 3 chain through the result registers as
+// in the one-env-per-lane kernel; the 4 actions of env j are broadcast to its
+// 4 lanes with 4 lane shuffles.  The dynamics run replicated on the 4 lanes
+// (identical inputs, identical arithmetic, identical results); memory writes
+// are split among the lanes.
+#include "qs_device.h"
+#include "qs_forward.h"
+
+namespace qs {
+
+typedef float f4q __attribute__((ext_vector_type(4)));
+
+constexpr int Q_C = 37;          // K-chunks of layer 1
+constexpr int Q_CP = 40;         // padded to whole float4s
+constexpr int Q_W1_P = 44;       // LDS pitch of one (neuron, quarter) row
+constexpr int Q_W1 = 0, Q_B1 = Q_W1 + NHID * 4 * Q_W1_P, Q_W2 = Q_B1 + NHID,
+              Q_B2 = Q_W2 + NHID * 68, Q_W3 = Q_B2 + NHID, Q_B3 = Q_W3 + 16 * 68,
+              Q_TOTAL = Q_B3 + 4;
+
+// Observation feature of chunk c, quarter k (or -1 for padding).
+__host__ __device__ constexpr int q_phi(int c, int k) {
+  return c < 5 ? (4 * c + k < 18 ? 4 * c + k : -1) : 18 + 4 * (c - 5) + k;
+}
+
+__device__ inline void stage_q(const float* __restrict__ W, float* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // W1 in PHI order: [neuron][quarter][chunk], pitch Q_W1_P
+  for (int idx = tid; idx < NHID * 4 * Q_W1_P; idx += nt) {
+    const int c = idx % Q_W1_P, rest = idx / Q_W1_P, k = rest & 3, nrn = rest >> 2;
+    const int f = c < Q_C ? q_phi(c, k) : -1;
+    lds[Q_W1 + idx] = f >= 0 ? W[OFF_W1 + nrn * NO + f] : 0.0f;
+  }
+  for (int i = tid; i < NHID * 68; i += nt) {
+    const int r = i / 68, k = i % 68;
+    lds[Q_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
+  }
+  for (int i = tid; i < 16 * 68; i += nt) {
+    const int r = i / 68, k = i % 68;
+    lds[Q_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
+  }
+  for (int i = tid; i < NHID; i += nt) {
+    lds[Q_B1 + i] = W[OFF_B1 + i];
+    lds[Q_B2 + i] = W[OFF_B2 + i];
+  }
+  for (int i = tid; i < NA; i += nt) lds[Q_B3 + i] = W[OFF_B3 + i];
+}
+
+// Actor for the wave's 16 envs.  F: this lane's 37 layer-1 operands.  Returns
+// z3 (pre-tanh) of this lane's env in every lane.  When rz1/rz2 are given,
+// writes the layer pre-activations ([64][N] rows, env0 + j columns).
+__device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA],
+                               float* __restrict__ rz1, float* __restrict__ rz2, int N,
+                               int env0, uint32_t rec_lane_off) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  f4q acc1[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc1[n][r] = lds[Q_B1 + 16 * n + 4 * lg + r];
+#pragma unroll
+  for (int cc = 0; cc < Q_CP / 4; ++cc) {
+    f4q w[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      w[n] = *reinterpret_cast<const f4q*>(
+          &lds[Q_W1 + ((16 * n + li) * 4 + lg) * Q_W1_P + 4 * cc]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * cc + q;
+      if (c < Q_C) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[n][q], F[c], acc1[n], 0, 0, 0);
+      }
+    }
+  }
+  const int env = env0 + li;
+  if (rz1 && env < N) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * N + rec_lane_off] = acc1[n][r];
+  }
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
+  f4q acc2[4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc2[n2][r] = lds[Q_B2 + 16 * n2 + 4 * lg + r];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W2 + (16 * n2 + li) * 68 + 16 * n + 4 * lg]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc2[n2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][v], acc2[n2], 0, 0, 0);
+    }
+  if (rz2 && env < N) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * N + rec_lane_off] = acc2[n2][r];
+  }
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc2[n2][r] = fmaxf(acc2[n2][r], 0.0f);
+  f4q acc3;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc3[r] = lg == 0 ? lds[Q_B3 + r] : 0.0f;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W3 + li * 68 + 16 * n2 + 4 * lg]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][v], acc3, 0, 0, 0);
+  }
+  // lane li of quarter 0 holds z3[o] of env li in register o
+  const int src = li << 2;
+#pragma unroll
+  for (int o = 0; o < NA; ++o)
+    z3[o] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[o])));
+}
+
+// Two waves per SIMD (256 registers each) so one wave's vector work overlaps
+// the other's matrix-core work.
+template <int DUMMY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
+         float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states,
+         float* __restrict__ tape, int ckpt_every, const float* __restrict__ ck_in,
+         float* __restrict__ rec) {
+  __shared__ __attribute__((aligned(16))) float lds[Q_TOTAL];
+  const int N = c.n_envs;
+  stage_q(W, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, j = lane & 15, k = lane >> 4;
+  const int env0 = (blockIdx.x * blockDim.x + threadIdx.x - lane) / 4;  // first env of the wave
+  if (env0 >= N) return;
+  const int env = env0 + j;
+  const bool active = env < N;
+  const int e = active ? env : env0;
+  const bool REC = rec != nullptr;
+
+  float th[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) th[i] = b.theta[(size_t)i * N + e];
+  const Body<float> B = make_body<float>(th);
+  const bool renorm = (c.flags & F_RENORM_Q) != 0;
+
+  float x[NS];
+  float F[Q_C];  // F[0..4] observation state part (refreshed each step), F[5..36] history
+  int head0 = 0, t_ep = 0, ep = 0;
+  if (REC) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
+#pragma unroll
+    for (int s = 0; s < NH; ++s) F[5 + s] = ck_in[(size_t)(NS + s * NA + k) * N + e];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
+    head0 = b.head[e];
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int slot = (head0 + s) & (NH - 1);
+      F[5 + s] = b.ring[(size_t)(slot * NA + k) * N + e];
+    }
+    t_ep = b.t_ep[e];
+    ep = b.ep[e];
+  }
+  bool was_reset = false;
+
+  if (states && t_base == 0 && active)
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      if ((i & 3) == k) states[(size_t)i * N + e] = x[i];
+
+  for (int t = 0; t < T; ++t) {
+    __asm__ volatile("" ::: "memory");
+    const uint32_t eo = opaque((uint32_t)e);
+    const bool rec_on = opaque(REC ? 1u : 0u) != 0u;
+    const int gt = t_base + t;
+    if (tape && (gt % ckpt_every) == 0 && active) {
+      float* ck = tape + (size_t)(gt / ckpt_every) * (NS + NH * NA) * N;
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if ((i & 3) == k) ck[(size_t)i * N + eo] = x[i];
+      const uint32_t kc = opaque((uint32_t)(k * N + e));
+#pragma unroll
+      for (int s = 0; s < NH; ++s) ck[(size_t)(NS + s * NA) * N + kc] = F[5 + s];
+    }
+    // observation state part: 18 features, this quarter keeps 4c + k
+    float Rm[9];
+    rotmat(x + 3, Rm);
+    {
+      const float sf[20] = {x[0], x[1], x[2], Rm[0], Rm[1], Rm[2], Rm[3], Rm[4], Rm[5], Rm[6],
+                            Rm[7], Rm[8], x[7], x[8], x[9], x[10], x[11], x[12], 0.0f, 0.0f};
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc)
+        F[cc] = k == 0 ? sf[4 * cc] : k == 1 ? sf[4 * cc + 1] : k == 2 ? sf[4 * cc + 2]
+                                                                        : sf[4 * cc + 3];
+    }
+    float* rt = rec_on ? rec + (size_t)t * REC_F * N : nullptr;
+    float z3[NA];
+    // per-lane part of record addresses, recomputed every step (see opaque())
+    const uint32_t zoff = opaque((uint32_t)(4 * k * N + env0 + j));
+    const uint32_t koff = opaque((uint32_t)(k * N + e));
+    actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
+            rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
+    float a[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
+    if (rec_on && active) {
+#pragma unroll
+      for (int cc = 0; cc < Q_C; ++cc) {
+        // feature q_phi(cc, k) = base + k for valid slots
+        const int base = cc < 5 ? 4 * cc : 18 + 4 * (cc - 5);
+        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + base) * N + koff] = F[cc];
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if ((i & 3) == k) rt[(size_t)(REC_X + i) * N + eo] = x[i];
+      rt[(size_t)REC_A * N + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+    }
+    float u[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
+    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    const float r = reward(c, x, a);
+#pragma unroll
+    for (int s = 5; s < Q_C - 1; ++s) F[s] = F[s + 1];
+    F[Q_C - 1] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+    ++t_ep;
+    const uint32_t d = episode_end(c, x, t_ep);
+    if (d && (c.flags & F_AUTORESET)) {
+      ++ep;
+      t_ep = 0;
+      was_reset = true;
+      const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
+#pragma unroll
+      for (int s = 5; s < Q_C; ++s) F[s] = ah;
+    }
+    if (active) {
+      if (k == 0 && rewards) rewards[(size_t)gt * N + eo] = r;
+      if (k == 1 && dones) dones[(size_t)gt * N + eo] = (uint8_t)d;
+      if (states)
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+          if ((i & 3) == k) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
+    }
+  }
+  if (!active || REC) return;
+  const uint32_t ef = opaque((uint32_t)e);
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    if ((i & 3) == k) b.state[(size_t)i * N + ef] = x[i];
+  const int head1 = (head0 + T) & (NH - 1);
+#pragma unroll
+  for (int s = 0; s < NH; ++s) {
+    if (was_reset || s >= NH - T) {
+      const int slot = (head1 + s) & (NH - 1);
+      b.ring[(size_t)(slot * NA + k) * N + ef] = F[5 + s];
+    }
+  }
+  if (k == 0) {
+    b.head[ef] = head1;
+    b.t_ep[ef] = t_ep;
+    b.ep[ef] = ep;
+  }
+}
+
+hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
+                         float* rewards, uint8_t* dones, float* states, float* tape,
+                         int ckpt_every, const float* ck_in, float* rec, hipStream_t st) {
+  const unsigned grid = (unsigned)((c.n_envs + 63) / 64);
+  hipLaunchKernelGGL(k_fused4<0>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards,
+                     dones, states, tape, ckpt_every, ck_in, rec);
+  return hipGetLastError();
+}
+
+}  // namespace qs

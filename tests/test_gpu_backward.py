@@ -223,6 +223,9 @@ def test_sysid16384_full_size(pkg, oracle_lib):
     H = wl.workload_steps("sysid16384")
     N = cfg["n_envs"]
     sim = pkg.QuadSim(cfg)
+    # ground truth from the kernel that taped rollouts use, so that at the
+    # true parameters both trajectories are the same bits
+    sim.set_variant(pkg.SIM_V_FUSED_MFMA4)
     W = wl.sysid_actor(0)
     a = sim.actor_tensor(W)
     snap = {k: v.clone() for k, v in sim.get_state().items()}

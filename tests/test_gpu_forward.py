@@ -16,7 +16,7 @@ from parity import (ENVELOPE_FACTOR, STEP_TOL, TRAJ_TOL, box_margin, max_state_e
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-VARIANTS = {"plain": 1, "valu": 2, "mfma": 3}
+VARIANTS = {"plain": 1, "valu": 2, "mfma": 3, "mfma4": 4}
 
 
 @pytest.fixture(scope="module")
@@ -305,7 +305,7 @@ def _run(pkg, cfg, variant, spl, graph, T, W):
     return res
 
 
-@pytest.mark.parametrize("variant", ["mfma", "valu"])
+@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4"])
 def test_chunked_and_graph_launches_are_bitwise_equal(pkg, variant):
     n, T = 1000, 300
     flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
