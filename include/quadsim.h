@@ -68,7 +68,14 @@ typedef enum sim_status {
 enum {
   SIM_F_TERMINATE = 1,  /* end episodes that leave the box or become non-finite */
   SIM_F_AUTORESET = 2,  /* reset ended episodes inside the step                  */
-  SIM_F_RENORM_Q = 4    /* renormalise the quaternion after each step           */
+  SIM_F_RENORM_Q = 4,   /* renormalise the quaternion after each step           */
+  SIM_F_FP64 = 8        /* whole forward step in double precision: state, history
+                           and parameters stored in double, observation, actor,
+                           RK4, reward and reset draws evaluated in double (the
+                           termination box test stays in float32).  Forward only:
+                           such a handle records no tape; float32 interfaces
+                           (states, snapshots, parameters) round on output and
+                           widen on input.  Fixed at creation.                  */
 };
 
 /* Execution variants of the forward step. */

@@ -13,6 +13,7 @@
 #include "../../include/quadsim.h"
 #include "qs_backward.h"
 #include "qs_forward.h"
+#include "qs_precise.h"
 
 using namespace qs;
 
@@ -81,6 +82,9 @@ struct sim_handle {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int last_launches = 0;
   bool timing_valid = false;
+  bool fp64 = false;          // SIM_F_FP64: double-precision path only
+  PreciseCfg pc{};
+  PreciseBufs pb{};
 };
 
 namespace {
@@ -91,8 +95,10 @@ int check_config(const sim_config* c) {
   if (!c) return fail(SIM_E_INVAL, "config is NULL");
   if (c->n_envs < 1 || c->n_envs > (1 << 24)) return fail(SIM_E_INVAL, "n_envs %d out of range", c->n_envs);
   if (c->max_episode_steps < 0) return fail(SIM_E_INVAL, "max_episode_steps < 0");
-  if (c->flags & ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q))
+  if (c->flags & ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q | SIM_F_FP64))
     return fail(SIM_E_INVAL, "unknown flags 0x%x", c->flags);
+  if ((c->flags & SIM_F_FP64) && c->max_tape_horizon > 0)
+    return fail(SIM_E_UNSUPPORTED, "SIM_F_FP64 handles are forward only (max_tape_horizon 0)");
   if (c->max_tape_horizon < 0 || c->max_tape_horizon > (1 << 20))
     return fail(SIM_E_INVAL, "max_tape_horizon out of range");
   if (c->ckpt_every < 1 || c->ckpt_every > 4096) return fail(SIM_E_INVAL, "ckpt_every must be in [1, 4096]");
@@ -152,6 +158,43 @@ DevCfg make_devcfg(const sim_config& c, uint64_t seed) {
   d.dr_seed_lo = (uint32_t)c.dr_seed;
   d.dr_seed_hi = (uint32_t)(c.dr_seed >> 32);
   return d;
+}
+
+PreciseCfg make_precise(const sim_config& c, uint64_t seed) {
+  PreciseCfg p{};
+  p.n_envs = c.n_envs;
+  p.max_steps = c.max_episode_steps;
+  p.flags = c.flags;
+  p.dr_enable = c.dr_enable;
+  p.dt = c.dt;
+  p.g = c.g;
+  p.arm = c.arm;
+  p.km = c.k_m;
+  p.rpm_min = c.rpm_min;
+  p.rpm_max = c.rpm_max;
+  p.pos_limit = c.pos_limit;
+  p.vel_limit = c.vel_limit;
+  p.init_pos = c.init_pos;
+  p.init_angle = c.init_angle;
+  p.init_vel = c.init_vel;
+  p.init_angvel = c.init_angvel;
+  p.C_rp = c.C_rp;
+  p.C_rq = c.C_rq;
+  p.C_rv = c.C_rv;
+  p.C_rw = c.C_rw;
+  p.C_ra = c.C_ra;
+  p.C_rab = c.C_rab;
+  p.C_rs = c.C_rs;
+  for (int i = 0; i < NP; ++i) {
+    p.nominal[i] = c.nominal[i];
+    p.dr_lo[i] = c.dr_lo[i];
+    p.dr_hi[i] = c.dr_hi[i];
+  }
+  p.seed_lo = (uint32_t)seed;
+  p.seed_hi = (uint32_t)(seed >> 32);
+  p.dr_seed_lo = (uint32_t)c.dr_seed;
+  p.dr_seed_hi = (uint32_t)(c.dr_seed >> 32);
+  return p;
 }
 
 // Error left by earlier asynchronous work on this device, if any.
@@ -247,6 +290,30 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
     return SIM_OK;
   };
   rc = SIM_OK;
+  h->fp64 = (cfg->flags & SIM_F_FP64) != 0;
+  if (h->fp64) {
+    h->pc = make_precise(*cfg, cfg->seed);
+    rc = rc ? rc : alloc((void**)&h->pb.state, N * NS * 8);
+    rc = rc ? rc : alloc((void**)&h->pb.ring, N * NH * NA * 8);
+    rc = rc ? rc : alloc((void**)&h->pb.head, N * 4);
+    rc = rc ? rc : alloc((void**)&h->pb.t_ep, N * 4);
+    rc = rc ? rc : alloc((void**)&h->pb.ep, N * 4);
+    rc = rc ? rc : alloc((void**)&h->pb.theta, N * NP * 8);
+    if (!rc && precise_prepare() != hipSuccess) rc = fail(SIM_E_DEVICE, "fp64 kernel setup failed");
+    if (!rc && hipEventCreate(&h->ev0) == hipSuccess && hipEventCreate(&h->ev1) == hipSuccess) {
+      hipError_t e = precise_init(h->pc, h->pb, 1, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      if (e != hipSuccess) rc = fail(SIM_E_DEVICE, "init: %s", hipGetErrorString(e));
+    } else if (!rc) {
+      rc = fail(SIM_E_DEVICE, "event creation failed");
+    }
+    if (rc) {
+      sim_destroy(h);
+      return rc;
+    }
+    *out = h;
+    return SIM_OK;
+  }
   rc = rc ? rc : alloc((void**)&h->b.state, N * NS * 4);
   rc = rc ? rc : alloc((void**)&h->b.ring, N * NH * NA * 4);
   rc = rc ? rc : alloc((void**)&h->b.head, N * 4);
@@ -286,8 +353,9 @@ int sim_destroy(sim_handle* h) {
   DeviceGuard g(h->device);
   (void)hipDeviceSynchronize();
   drop_graph(h);
-  void* ptrs[] = {h->b.state, h->b.ring, h->b.head, h->b.t_ep, h->b.ep, h->b.theta,
-                  h->p.obs,   h->p.h1,   h->p.h2,   h->p.act,  h->tape};
+  void* ptrs[] = {h->b.state, h->b.ring, h->b.head,  h->b.t_ep,  h->b.ep,    h->b.theta,
+                  h->p.obs,   h->p.h1,   h->p.h2,    h->p.act,   h->tape,    h->pb.state,
+                  h->pb.ring, h->pb.head, h->pb.t_ep, h->pb.ep,  h->pb.theta};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   bwd_free(h->bw);
@@ -307,6 +375,11 @@ int sim_reset(sim_handle* h, uint64_t seed, void* stream) {
   h->dc = make_devcfg(h->cfg, seed);
   h->tape_T = 0;
   drop_graph(h);
+  if (h->fp64) {
+    h->pc = make_precise(h->cfg, seed);
+    HIP_TRY(precise_init(h->pc, h->pb, 0, (hipStream_t)stream));
+    return SIM_OK;
+  }
   HIP_TRY(launch_init(h->dc, h->b, 0, (hipStream_t)stream));
   return SIM_OK;
 }
@@ -320,6 +393,11 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
   if (rc) return rc;
   h->tape_T = 0;
   hipStream_t st = (hipStream_t)stream;
+  if (h->fp64) {
+    HIP_TRY(precise_run(h->pc, h->pb, actor, actor ? nullptr : actions, 1, 0, reward, done,
+                        nullptr, st));
+    return SIM_OK;
+  }
   const int v = effective_variant(h);
   if (v == SIM_V_PLAIN) {
     HIP_TRY(launch_plain_step(h->dc, h->b, h->p, actor, actor ? nullptr : actions, reward, done,
@@ -351,6 +429,14 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   int rc = sticky_error();
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  if (h->fp64) {
+    HIP_TRY(hipEventRecord(h->ev0, st));
+    HIP_TRY(precise_run(h->pc, h->pb, actor, nullptr, T, 0, rewards, dones, states, st));
+    HIP_TRY(hipEventRecord(h->ev1, st));
+    h->last_launches = 1;
+    h->timing_valid = true;
+    return SIM_OK;
+  }
   // A taped rollout always runs on the quarter-lane fused kernel: the
   // backward pass recomputes segments with that kernel, and the recompute
   // must reproduce the forward trajectory bit for bit.
@@ -437,6 +523,10 @@ int sim_get_state(sim_handle* h, float* state, float* hist, int32_t* t_ep, int32
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;
+  if (h->fp64) {
+    HIP_TRY(precise_get(h->pb, h->N, state, hist, t_ep, episode, nullptr, (hipStream_t)stream));
+    return SIM_OK;
+  }
   HIP_TRY(launch_get_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
   return SIM_OK;
 }
@@ -448,6 +538,10 @@ int sim_set_state(sim_handle* h, const float* state, const float* hist, const in
   int rc = sticky_error();
   if (rc) return rc;
   h->tape_T = 0;
+  if (h->fp64) {
+    HIP_TRY(precise_set(h->pb, h->N, state, hist, t_ep, episode, nullptr, (hipStream_t)stream));
+    return SIM_OK;
+  }
   HIP_TRY(launch_set_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
   return SIM_OK;
 }
@@ -457,6 +551,11 @@ int sim_get_params(sim_handle* h, float* theta, void* stream) {
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;
+  if (h->fp64) {
+    HIP_TRY(precise_get(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta,
+                        (hipStream_t)stream));
+    return SIM_OK;
+  }
   HIP_TRY(hipMemcpyAsync(theta, h->b.theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
                          (hipStream_t)stream));
   return SIM_OK;
@@ -468,6 +567,11 @@ int sim_set_params(sim_handle* h, const float* theta, void* stream) {
   int rc = sticky_error();
   if (rc) return rc;
   h->tape_T = 0;
+  if (h->fp64) {
+    HIP_TRY(precise_set(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta,
+                        (hipStream_t)stream));
+    return SIM_OK;
+  }
   HIP_TRY(hipMemcpyAsync(h->b.theta, theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
                          (hipStream_t)stream));
   return SIM_OK;
@@ -498,6 +602,7 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
                  float* ms_out) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
   if (!actor || T < 1) return fail(SIM_E_INVAL, "need actor and T >= 1");
+  if (h->fp64) return fail(SIM_E_UNSUPPORTED, "SIM_F_FP64 handles have a single variant");
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;

@@ -5,11 +5,18 @@
 namespace qs {
 
 // Scratch owned by the handle for the backward pass (allocated at create).
+// Segments are pipelined over three streams (recompute, reverse sweep on the
+// caller's stream, weight gradients) with NBUF rotating segment buffers.
+constexpr int BWD_NBUF = 3;
 struct BwdBufs {
   int N = 0, K = 0, H = 0;
-  int n_parts = 0;         // workgroups of the weight-gradient reduction
-  float* seg = nullptr;    // [K][REC_F][N] per-step recompute record of a segment
-  float* dz = nullptr;     // [K][132][N] layer cotangents of a segment
+  int n_parts = 0;                    // workgroups of the weight-gradient reduction
+  int n_cu = 0;                       // compute units of the device
+  float* seg[BWD_NBUF] = {};          // [K][REC_F][N] per-step recompute record of a segment
+  float* dz[BWD_NBUF] = {};           // [K][132][N] layer cotangents of a segment
+  hipStream_t s_rec = nullptr, s_dw = nullptr;
+  hipEvent_t e_init = nullptr, e_rec[BWD_NBUF] = {}, e_rev[BWD_NBUF] = {},
+             e_dw[BWD_NBUF] = {};
   float* lam = nullptr;    // [145][N] state and history adjoints between segments
   float* gth = nullptr;    // [8][N] parameter gradients
   float* gpart = nullptr;  // [n_parts][13828] per-workgroup weight-gradient partials

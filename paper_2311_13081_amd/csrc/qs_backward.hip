@@ -4,12 +4,12 @@
 // backward walks the segments last to first; per segment:
 //   1. recompute: the fused MFMA kernel restarts from the checkpoint and
 //      records x_t, a_t, the layer pre-activations z1, z2 and o_t per step;
-//   2. reverse sweep (k_bwd_reverse): one env per lane, the adjoints of the
-//      state (17) and of the action history (128) in registers, stepping
-//      back through reward, quaternion renormalisation, the four RK4 stages,
-//      the action map, the actor and the history shift; per-env parameter
-//      gradients accumulate in registers; the layer cotangents dz1, dz2, dz3
-//      of every (step, env) go to scratch;
+//   2. reverse sweep (k_bwd_reverse): four lanes per env, the adjoints of
+//      the state and of the action history in registers, stepping back
+//      through reward, quaternion renormalisation, the four RK4 stages, the
+//      action map, the actor (on MFMA) and the history shift; per-env
+//      parameter gradients accumulate in registers; the layer cotangents
+//      dz1, dz2, dz3 of every (step, env) go to scratch;
 //   3. weight gradients (k_bwd_dw): sum over (step, env) rows of dz (x) input
 //      on fp32 MFMA, one workgroup per 64-env chunk accumulating into its own
 //      partial; biases come from a constant-one input column.
@@ -41,17 +41,30 @@ __global__ void k_bwd_init(int N, const float* __restrict__ dS_T, float* __restr
   for (int i = 0; i < NP; ++i) gth[(size_t)i * N + e] = 0.0f;
 }
 
-// LDS layout of the reverse kernel (floats).  Transposed weights packed so
-// that each lane's MFMA A operand for 4 consecutive K-chunks is one 16-byte
-// read:
-//   R_W3: W3 row-major [4][64]; A of the 4-block 16x16x1 for dh2 = W3^T dz3.
-//   R_W2P[((n*4 + g)*4 + m)*16 + i][v] = W2[16n + 4g + v][16m + i]  (dh1 = W2^T dz2)
-//   R_W1P[((m*4 + g)*10 + f)*16 + i][v] = W1[16m + 4g + v][16f + i] (do = W1^T dz1),
-//     zero for features 16f + i >= 146.
-//   R_ST: per-wave 16 x 68 staging tile for moving do to one env per lane.
+// Quarter-lane reverse sweep (16 envs per wave, lane L = j + 16 k: env j,
+// quarter k), the adjoint of the quarter-lane forward kernel.  Per lane:
+// the state adjoint (17) and the dynamics VJP, replicated over the 4 quarters
+// of an env; the history adjoint of action component k (32 slots).  The actor
+// VJP runs on 16x16x4 fp32 MFMAs:
+//   dh2 = W3^T dz3: one K=4 MFMA per 16-neuron tile (quarter k supplies
+//         dz3[k]);
+//   dh1 = W2^T dz2, do = W1^T dz1: chained through the result registers.
+// The rows of W1^T are taken in the forward's observation order, so tile p
+// of do leaves in quarter k exactly the features PHI(4p + r, k): history
+// slot 4p + r - 5, component k (the lane's own history adjoint) or, for
+// chunks 0..4, state features 4c + k, gathered across quarters with 20
+// lane shuffles.
+//
+// LDS (floats):
+//   R_W3 [4][64] = W3;
+//   R_W2P[((n*4 + g)*4 + m)*16 + i][v] = W2[16n + 4g + v][16m + i];
+//   R_W1P[((m*4 + g)*10 + p)*16 + i][v] = W1[16m + 4g + v][PHI(4p + i%4, i/4)] (0 if pad).
 constexpr int R_W3 = 0, R_W2P = R_W3 + NA * NHID, R_W1P = R_W2P + NHID * NHID,
-              R_ST = R_W1P + 10 * 16 * NHID, R_ST_P = 68, R_ST_SZ = 16 * R_ST_P,
-              R_TOTAL = R_ST + 4 * R_ST_SZ;
+              R_TOTAL = R_W1P + 10 * 16 * NHID;
+
+__host__ __device__ constexpr int r_phi(int c, int k) {
+  return c < 5 ? (4 * c + k < 18 ? 4 * c + k : -1) : c < 37 ? 18 + 4 * (c - 5) + k : -1;
+}
 
 __device__ inline void stage_reverse(const float* __restrict__ W, float* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -62,23 +75,13 @@ __device__ inline void stage_reverse(const float* __restrict__ W, float* lds) {
     lds[R_W2P + idx] = W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i];
   }
   for (int idx = tid; idx < 10 * 16 * NHID; idx += nt) {
-    const int v = idx & 3, i = (idx >> 2) & 15, rest = idx >> 6;  // rest = (m*4 + g)*10 + f
-    const int f = rest % 10, g = (rest / 10) & 3, m = rest / 40;
-    const int feat = 16 * f + i;
-    lds[R_W1P + idx] = feat < NO ? W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat] : 0.0f;
+    const int v = idx & 3, i = (idx >> 2) & 15, rest = idx >> 6;  // rest = (m*4 + g)*10 + p
+    const int p = rest % 10, g = (rest / 10) & 3, m = rest / 40;
+    const int feat = r_phi(4 * p + (i & 3), i >> 2);
+    lds[R_W1P + idx] = feat >= 0 ? W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat] : 0.0f;
   }
 }
 
-// Reverse sweep over steps t0 + n - 1 .. t0 of one segment.  One env per lane
-// for the state adjoint, the history adjoint, the RK4/dynamics VJP and the
-// parameter gradients; the actor VJP runs on fp32 matrix cores for the wave's
-// 64 envs (the forward's layer chaining in reverse): dh2 = W3^T dz3 with the
-// 4-block 16x16x1 MFMA from the per-lane dz3, dh1 = W2^T dz2 and
-// do = W1^T dz1 with 16x16x4 MFMAs fed by the previous result registers.  do
-// comes out as (feature, env) tiles; each 16-feature tile goes through a
-// per-wave LDS tile to one env per lane, newest history feature first so the
-// history-adjoint shift can run in place.  Inactive lanes of the last wave
-// shadow the wave's first env (reads only).
 __global__ void __launch_bounds__(256)
 k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict__ W,
               const float* __restrict__ rec, int n, int t0, const float* __restrict__ d_rewards,
@@ -88,13 +91,12 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   stage_reverse(W, lds);
   __syncthreads();
   const int N = c.n_envs;
-  const int env = blockIdx.x * blockDim.x + threadIdx.x;
-  const int first = env - (threadIdx.x & 63);
-  if (first >= N) return;
+  const int lane = threadIdx.x & 63, j = lane & 15, k = lane >> 4;
+  const int env0 = (blockIdx.x * blockDim.x + threadIdx.x - lane) / 4;
+  if (env0 >= N) return;
+  const int env = env0 + j;
   const bool active = env < N;
-  const int e = active ? env : first;
-  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  float* stg = lds + R_ST + (threadIdx.x >> 6) * R_ST_SZ;
+  const int e = active ? env : env0;
 
   float th[NP];
 #pragma unroll
@@ -103,17 +105,19 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
   const float h = c.dt;
 
-  float ls[NS], lH[NH * NA], gth[NP];
+  float ls[NS], lH[NH], gth[NP];
 #pragma unroll
   for (int i = 0; i < NS; ++i) ls[i] = lam[(size_t)i * N + e];
 #pragma unroll
-  for (int i = 0; i < NH * NA; ++i) lH[i] = lam[(size_t)(NS + i) * N + e];
+  for (int s = 0; s < NH; ++s) lH[s] = lam[(size_t)(NS + s * NA + k) * N + e];
 #pragma unroll
   for (int i = 0; i < NP; ++i) gth[i] = gth_io[(size_t)i * N + e];
 
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
+    const uint32_t zoff = opaque((uint32_t)(4 * k * N + e));  // (row 4k, this env)
+    const uint32_t koff = opaque((uint32_t)(k * N + e));             // (row k, env)
     const int t = t0 + tl;
     const float* rt = rec + (size_t)tl * REC_F * N;
     float* dzt = dz + (size_t)tl * DZ_F * N;
@@ -128,29 +132,29 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     const float dR = d_rewards ? d_rewards[(size_t)t * N + eo] : 1.0f;
 
     // --- forward recompute of the RK4 stages -------------------------------
-    float x2[NS], x3[NS], x4[NS], k[NS], acc[NS];
-    deriv<float>(B, c.arm, c.km, c.g, x, u, k);
+    float x2[NS], x3[NS], x4[NS], kd[NS], acc[NS];
+    deriv<float>(B, c.arm, c.km, c.g, x, u, kd);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      acc[i] = k[i];
-      x2[i] = x[i] + 0.5f * h * k[i];
+      acc[i] = kd[i];
+      x2[i] = x[i] + 0.5f * h * kd[i];
     }
-    deriv<float>(B, c.arm, c.km, c.g, x2, u, k);
+    deriv<float>(B, c.arm, c.km, c.g, x2, u, kd);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      acc[i] += 2.0f * k[i];
-      x3[i] = x[i] + 0.5f * h * k[i];
+      acc[i] += 2.0f * kd[i];
+      x3[i] = x[i] + 0.5f * h * kd[i];
     }
-    deriv<float>(B, c.arm, c.km, c.g, x3, u, k);
+    deriv<float>(B, c.arm, c.km, c.g, x3, u, kd);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      acc[i] += 2.0f * k[i];
-      x4[i] = x[i] + h * k[i];
+      acc[i] += 2.0f * kd[i];
+      x4[i] = x[i] + h * kd[i];
     }
-    deriv<float>(B, c.arm, c.km, c.g, x4, u, k);
+    deriv<float>(B, c.arm, c.km, c.g, x4, u, kd);
     float sn[NS];  // post-step state (renormalised)
 #pragma unroll
-    for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + k[i]);
+    for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + kd[i]);
     float rn = 1.0f;
     if (renorm) {
       rn = 1.0f / sqrtf(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
@@ -169,9 +173,13 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
       g[10 + i] += -2.0f * c.C_rw * sn[10 + i] * dR;
     }
     g[3] += 2.0f * c.C_rq * sn[3] * dR;
+    // newest history slot: component i lives in quarter i of the same env
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-      ga[i] = -2.0f * c.C_ra * (a[i] - c.C_rab) * dR + lH[(NH - 1) * NA + i];
+    for (int i = 0; i < NA; ++i) {
+      const float hn = __int_as_float(
+          __builtin_amdgcn_ds_bpermute((j + 16 * i) << 2, __float_as_int(lH[NH - 1])));
+      ga[i] = -2.0f * c.C_ra * (a[i] - c.C_rab) * dR + hn;
+    }
 
     // --- renormalisation ------------------------------------------------------
     if (renorm) {
@@ -213,129 +221,83 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     for (int i = 0; i < NA; ++i) ga[i] += gu[i] * c.rpm_half_range;
 
     // --- actor VJP on matrix cores --------------------------------------------
-    // Pre-activations of the wave's 64 envs in the (neuron, env) tile layout:
-    // register r of tile q holds neuron 16q + 4lg + (r&3) of env
-    // first + 16(r>>2) + li (clamped to the last env for the ragged tail).
-    const int ed = opaque((uint32_t)(first + li));
-    float m2[4][16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ee = min(ed + 16 * (r >> 2), N - 1);
-        m2[q][r] = rt[(size_t)(REC_Z2 + 16 * q + 4 * lg + (r & 3)) * N + ee];
-      }
     float d3[NA];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      d3[i] = ga[i] * (1.0f - a[i] * a[i]);
-      if (active) dzt[(size_t)(2 * NHID + i) * N + eo] = d3[i];
-    }
-    // dz2 = (W3^T dz3) * [z2 > 0]
-    f16 dz2[4];
+    for (int i = 0; i < NA; ++i) d3[i] = ga[i] * (1.0f - a[i] * a[i]);
+    const float d3k = k == 0 ? d3[0] : k == 1 ? d3[1] : k == 2 ? d3[2] : d3[3];
+    if (active) dzt[(size_t)(2 * NHID) * N + koff] = d3k;
+    // dz2 = (W3^T dz3) * [z2 > 0]: tile q rows 16q + 4k + r, env j
+    f4 dz2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      dz2[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lds[R_W3 + k * NHID + 16 * q + j], d3k,
+                                                    f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dz2[q][r] = 0.0f;
-#pragma unroll
-      for (int o = 0; o < NA; ++o)
-        dz2[q] = __builtin_amdgcn_mfma_f32_16x16x1f32(lds[R_W3 + o * NHID + 16 * q + li], d3[o],
-                                                      dz2[q], 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        dz2[q][r] = m2[q][r] > 0.0f ? dz2[q][r] : 0.0f;
-        const int ee = ed + 16 * (r >> 2);
-        if (ee < N) dzt[(size_t)(NHID + 16 * q + 4 * lg + (r & 3)) * N + ee] = dz2[q][r];
+      for (int r = 0; r < 4; ++r) {
+        const float z2 = rt[(size_t)(REC_Z2 + 16 * q + r) * N + zoff];
+        dz2[q][r] = z2 > 0.0f ? dz2[q][r] : 0.0f;
+        if (active) dzt[(size_t)(NHID + 16 * q + r) * N + zoff] = dz2[q][r];
       }
     }
-    float m1[4][16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ee = min(ed + 16 * (r >> 2), N - 1);
-        m1[q][r] = rt[(size_t)(REC_Z1 + 16 * q + 4 * lg + (r & 3)) * N + ee];
-      }
-    // dz1 = (W2^T dz2) * [z1 > 0]; tile m, env block b in dz1[m][4b .. 4b+3]
-    f16 dz1[4];
+    // dz1 = (W2^T dz2) * [z1 > 0]
+    f4 dz1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      f4 accb[4];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) accb[bb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      f4 accm = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f4 w = *reinterpret_cast<const f4*>(
-            &lds[R_W2P + (((q * 4 + lg) * 4 + mt) * 16 + li) * 4]);
+            &lds[R_W2P + (((q * 4 + k) * 4 + mt) * 16 + j) * 4]);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int bb = 0; bb < 4; ++bb)
-            accb[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz2[q][4 * bb + v], accb[bb],
-                                                            0, 0, 0);
+          accm = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz2[q][v], accm, 0, 0, 0);
       }
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = m1[mt][4 * bb + r] > 0.0f ? accb[bb][r] : 0.0f;
-          dz1[mt][4 * bb + r] = v;
-          const int ee = ed + 16 * bb;
-          if (ee < N) dzt[(size_t)(16 * mt + 4 * lg + r) * N + ee] = v;
-        }
+      for (int r = 0; r < 4; ++r) {
+        const float z1 = rt[(size_t)(REC_Z1 + 16 * mt + r) * N + zoff];
+        dz1[mt][r] = z1 > 0.0f ? accm[r] : 0.0f;
+        if (active) dzt[(size_t)(16 * mt + r) * N + zoff] = dz1[mt][r];
+      }
     }
-    // do = W1^T dz1, one 16-feature tile at a time, newest features first.
+    // do = W1^T dz1 in observation order: tile p, register r of quarter k is
+    // the cotangent of feature PHI(4p + r, k)
+    float dob[40];
 #pragma unroll
-    for (int f = 9; f >= 0; --f) {
-      f4 accb[4];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) accb[bb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < 10; ++p) {
+      f4 accp = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         const f4 w = *reinterpret_cast<const f4*>(
-            &lds[R_W1P + (((mt * 4 + lg) * 10 + f) * 16 + li) * 4]);
+            &lds[R_W1P + (((mt * 4 + k) * 10 + p) * 16 + j) * 4]);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int bb = 0; bb < 4; ++bb)
-            accb[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz1[mt][4 * bb + v], accb[bb],
-                                                            0, 0, 0);
+          accp = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz1[mt][v], accp, 0, 0, 0);
       }
-      // tile -> one env per lane: row 4lg + r, column 16bb + li
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
+      for (int r = 0; r < 4; ++r) dob[4 * p + r] = accp[r];
+    }
+    // history adjoint: H_t[s] feeds H_{t+1}[s-1]; descending s reads the
+    // older adjoint before it is overwritten
 #pragma unroll
-        for (int r = 0; r < 4; ++r) stg[(4 * lg + r) * R_ST_P + 16 * bb + li] = accb[bb][r];
-      __builtin_amdgcn_wave_barrier();
-      float dob[16];
+    for (int s = NH - 1; s >= 0; --s) lH[s] = (s >= 1 ? lH[s - 1] : 0.0f) + dob[5 + s];
+    // state features 4cc + q live in quarter q: gather them into every lane
+    float gf[20];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dob[r] = stg[r * R_ST_P + lane];
-      __builtin_amdgcn_wave_barrier();
+    for (int cc = 0; cc < 5; ++cc)
 #pragma unroll
-      for (int r = 15; r >= 0; --r) {
-        const int kk = 16 * f + r;
-        if (kk >= NO) continue;
-        const float v = dob[r];
-        if (kk >= 18) {
-          // H_t[j] feeds H_{t+1}[j-1] (j >= 1); j descending keeps older
-          // adjoints intact until read.
-          const int jj = kk - 18;
-          lH[jj] = (jj >= NA ? lH[jj - NA] : 0.0f) + v;
-        } else if (kk < 3) {
-          gx[kk] += v;
-        } else if (kk < 12) {
-          k[kk - 3] = v;  // rotation-matrix cotangent
-        } else if (kk < 15) {
-          gx[7 + kk - 12] += v;
-        } else {
-          gx[10 + kk - 15] += v;
-        }
-      }
+      for (int q = 0; q < 4; ++q)
+        gf[4 * cc + q] = __int_as_float(
+            __builtin_amdgcn_ds_bpermute((j + 16 * q) << 2, __float_as_int(dob[cc])));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gx[i] += gf[i];
+      gx[7 + i] += gf[12 + i];
+      gx[10 + i] += gf[15 + i];
     }
     {
       float gq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       const float q[4] = {x[3], x[4], x[5], x[6]};
-      rotmat_vjp(q, k, gq);
+      rotmat_vjp(q, gf + 3, gq);
 #pragma unroll
       for (int i = 0; i < 4; ++i) gx[3 + i] += gq[i];
     }
@@ -345,12 +307,15 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   }
   if (!active) return;
   const uint32_t ef = opaque((uint32_t)e);
+  const uint32_t kf = opaque((uint32_t)(k * N + e));
 #pragma unroll
-  for (int i = 0; i < NS; ++i) lam[(size_t)i * N + ef] = ls[i];
+  for (int i = 0; i < NS; ++i)
+    if ((i & 3) == k) lam[(size_t)i * N + ef] = ls[i];
 #pragma unroll
-  for (int i = 0; i < NH * NA; ++i) lam[(size_t)(NS + i) * N + ef] = lH[i];
+  for (int s = 0; s < NH; ++s) lam[(size_t)(NS + s * NA) * N + kf] = lH[s];
+  if (k == 0)
 #pragma unroll
-  for (int i = 0; i < NP; ++i) gth_io[(size_t)i * N + ef] = gth[i];
+    for (int i = 0; i < NP; ++i) gth_io[(size_t)i * N + ef] = gth[i];
 }
 
 // Weight gradients of one segment: for every (step, env) row,
@@ -512,8 +477,21 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   bw.H = H;
   bw.n_parts = (int)nb(N, 64);
   hipError_t e;
-  if ((e = hipMalloc(&bw.seg, (size_t)K * REC_F * N * 4)) != hipSuccess) return e;
-  if ((e = hipMalloc(&bw.dz, (size_t)K * DZ_F * N * 4)) != hipSuccess) return e;
+  for (int i = 0; i < BWD_NBUF; ++i) {
+    if ((e = hipMalloc(&bw.seg[i], (size_t)K * REC_F * N * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * N * 4)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&bw.e_rec[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&bw.e_rev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&bw.e_dw[i], hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&bw.n_cu, hipDeviceAttributeMultiprocessorCount, dev)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipEventCreateWithFlags(&bw.e_init, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&bw.s_rec, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&bw.s_dw, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.lam, (size_t)LAM_F * N * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gth, (size_t)NP * N * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gpart, (size_t)bw.n_parts * NW * 4)) != hipSuccess) return e;
@@ -527,12 +505,41 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
 }
 
 void bwd_free(BwdBufs& bw) {
-  void* ptrs[] = {bw.seg, bw.dz, bw.lam, bw.gth, bw.gpart, bw.gsum};
+  for (int i = 0; i < BWD_NBUF; ++i) {
+    if (bw.seg[i]) (void)hipFree(bw.seg[i]);
+    if (bw.dz[i]) (void)hipFree(bw.dz[i]);
+    if (bw.e_rec[i]) (void)hipEventDestroy(bw.e_rec[i]);
+    if (bw.e_rev[i]) (void)hipEventDestroy(bw.e_rev[i]);
+    if (bw.e_dw[i]) (void)hipEventDestroy(bw.e_dw[i]);
+  }
+  if (bw.e_init) (void)hipEventDestroy(bw.e_init);
+  if (bw.s_rec) (void)hipStreamDestroy(bw.s_rec);
+  if (bw.s_dw) (void)hipStreamDestroy(bw.s_dw);
+  void* ptrs[] = {bw.lam, bw.gth, bw.gpart, bw.gsum};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   bw = BwdBufs{};
 }
 
+#define BWD_TRY(x)                 \
+  do {                             \
+    hipError_t e_ = (x);           \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+// Segments run last to first.  Per segment j (buffer j mod 3):
+//   recompute stream: waits for the weight-gradient pass that last used the
+//     buffer, then records the segment;
+//   caller stream: waits for the record, runs the reverse sweep (the
+//     segment-to-segment adjoint carry keeps these in order);
+//   weight-gradient stream: waits for the sweep, reduces the segment.
+// So the recompute of the next segments and the weight gradients of the
+// previous ones overlap the sweep.  The caller's stream finally waits for
+// the last weight-gradient pass before the fixed-order partial sum.
+// Overlap only pays while the sweep leaves compute units idle (fewer
+// workgroups than CUs): a full-chip sweep and the LDS-heavy weight-gradient
+// pass cannot share a CU, so for large batches everything stays on the
+// caller's stream in order.
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
@@ -542,17 +549,39 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
   hipLaunchKernelGGL(k_fill, dim3(nb((int)np, 256)), dim3(256), 0, st, bw.gpart, np, 0.0f);
   hipLaunchKernelGGL(k_bwd_init, dim3(nb(N, 256)), dim3(256), 0, st, N,
                      d_states ? d_states + (size_t)T * NS * N : nullptr, bw.lam, bw.gth);
+  const bool overlap = (int)nb(N, 64) < bw.n_cu;
+  hipStream_t s_rec = overlap ? bw.s_rec : st, s_dw = overlap ? bw.s_dw : st;
+  if (overlap) {
+    BWD_TRY(hipEventRecord(bw.e_init, st));
+    BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_init, 0));
+    BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_init, 0));
+  }
   const int J = (T + K - 1) / K;
-  for (int j = J - 1; j >= 0; --j) {
+  int last = 0;
+  for (int j = J - 1, idx = 0; j >= 0; --j, ++idx) {
     const int t0 = j * K;
     const int n = (T - t0) < K ? (T - t0) : K;
-    hipError_t e = launch_recompute(c, b, W, n, tape + (size_t)j * LAM_F * N, bw.seg, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 256)), dim3(256), R_TOTAL * 4, st, c, b.theta, W,
-                       bw.seg, n, t0, d_rewards, d_states, bw.lam, bw.gth, bw.dz);
-    hipLaunchKernelGGL(k_bwd_dw, dim3(bw.n_parts), dim3(256), DW_TOTAL * 4, st, N, bw.seg, bw.dz,
-                       n, bw.gpart);
+    const int buf = idx % BWD_NBUF;
+    if (overlap && idx >= BWD_NBUF) BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_dw[buf], 0));
+    BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * LAM_F * N, bw.seg[buf], s_rec));
+    if (overlap) {
+      BWD_TRY(hipEventRecord(bw.e_rec[buf], s_rec));
+      BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
+    }
+    hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 64)), dim3(256), R_TOTAL * 4, st, c, b.theta, W,
+                       bw.seg[buf], n, t0, d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf]);
+    BWD_TRY(hipGetLastError());
+    if (overlap) {
+      BWD_TRY(hipEventRecord(bw.e_rev[buf], st));
+      BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_rev[buf], 0));
+    }
+    hipLaunchKernelGGL(k_bwd_dw, dim3(bw.n_parts), dim3(256), DW_TOTAL * 4, s_dw, N,
+                       bw.seg[buf], bw.dz[buf], n, bw.gpart);
+    BWD_TRY(hipGetLastError());
+    if (overlap) BWD_TRY(hipEventRecord(bw.e_dw[buf], s_dw));
+    last = buf;
   }
+  if (overlap) BWD_TRY(hipStreamWaitEvent(st, bw.e_dw[last], 0));
   hipLaunchKernelGGL(k_bwd_reduce, dim3(nb(NW, 256)), dim3(256), 0, st, bw.gpart, bw.n_parts,
                      grad_actor ? grad_actor : bw.gsum);
   if (grad_params)

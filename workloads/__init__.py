@@ -31,6 +31,7 @@ NACTOR = NHID * NOBS + NHID + NHID * NHID + NHID + NACT * NHID + NACT  # 13828
 F_TERMINATE = 1
 F_AUTORESET = 2
 F_RENORM_Q = 4
+F_FP64 = 8
 
 PARAM_NAMES = ("m", "Jxx", "Jyy", "Jzz", "c0", "c1", "c2", "Tm")
 
