@@ -184,6 +184,28 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1):
             "horizon": H, "ckpt_every": cfg["ckpt_every"]}
 
 
+def dynamics_only(torch, pkg, n_envs, T, reps=3):
+    """Dynamics-only rollouts (no actor): a constant action per env, the
+    nominal body's hover command (the reward's action baseline), over T steps
+    with randomised bodies, termination and reset; rewards and dones written
+    each step."""
+    cfg = wl.workload_config("fwd65536_dr")
+    cfg["n_envs"] = n_envs
+    sim = pkg.QuadSim(cfg)
+    a = torch.full((4, n_envs), cfg["C_rab"], dtype=torch.float32, device="cuda")
+    sim.rollout_actions(a, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.rollout_actions(a, T)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    kernel_ms, _ = sim.last_rollout_timing()
+    sim.close()
+    return {"env_steps_per_s": n_envs * T / dt, "n_envs": n_envs, "rollout_steps": T,
+            "ms_per_rollout": dt * 1e3, "kernel_ms": kernel_ms}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -271,6 +293,8 @@ def main():
     if not args.no_extras:
         res["fwd_bwd"] = {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
                           "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0))}
+        res["dynamics_only"] = {"n8192_T2000": dynamics_only(torch, pkg, 8192, 2000),
+                                "n65536_T1000": dynamics_only(torch, pkg, 65536, 1000)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, W, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -143,6 +143,16 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
 int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
                 float* states, int32_t record_tape, void* stream);
 
+/* Dynamics-only rollout: T >= 1 steps with the policy replaced by given
+ * normalised actions -- the simulator alone, as in the throughput experiment
+ * of Sec. V (Simulation).  actions: dev [4][N] held for every step
+ * (actions_per_step == 0) or dev [T][4][N] (actions_per_step != 0).  Outputs
+ * as in sim_rollout.  Reward, termination, truncation and reset behave as in
+ * sim_step; the action history is left exactly as T single steps would leave
+ * it.  Not available on SIM_F_FP64 handles. */
+int sim_rollout_actions(sim_handle* h, const float* actions, int32_t actions_per_step, int32_t T,
+                        float* rewards, uint8_t* dones, float* states, void* stream);
+
 /* Vector-Jacobian product of the last taped rollout (discrete adjoint through
  * the observation, actor, action map, RK4 stages, quaternion normalisation and
  * history shift).  Cotangents: d_rewards dev [T][N] (NULL = all ones),

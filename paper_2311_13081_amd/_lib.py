@@ -24,6 +24,7 @@ EXPORTS = (
     "sim_create", "sim_destroy", "sim_reset", "sim_step", "sim_rollout", "sim_backward",
     "sim_get_state", "sim_set_state", "sim_get_params", "sim_set_params", "sim_set_variant",
     "sim_get_variant", "sim_autotune", "sim_last_rollout_timing", "sim_n_envs", "sim_last_error",
+    "sim_rollout_actions",
 )
 
 
@@ -84,6 +85,7 @@ def load(path: str | None = None):
         "sim_step": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_rollout": ([H, vp, i32, vp, vp, vp, i32, vp], ctypes.c_int),
         "sim_backward": ([H, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "sim_rollout_actions": ([H, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "sim_get_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_set_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_get_params": ([H, vp, vp], ctypes.c_int),

@@ -492,6 +492,26 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   return SIM_OK;
 }
 
+int sim_rollout_actions(sim_handle* h, const float* actions, int32_t actions_per_step, int32_t T,
+                        float* rewards, uint8_t* dones, float* states, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actions) return fail(SIM_E_INVAL, "actions is NULL");
+  if (T < 1) return fail(SIM_E_INVAL, "T = %d < 1", T);
+  if (h->fp64) return fail(SIM_E_UNSUPPORTED, "not available on SIM_F_FP64 handles");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  h->tape_T = 0;
+  HIP_TRY(hipEventRecord(h->ev0, st));
+  HIP_TRY(launch_dyn_rollout(h->dc, h->b, actions, actions_per_step ? NA : 0, T, rewards, dones,
+                             states, st));
+  HIP_TRY(hipEventRecord(h->ev1, st));
+  h->last_launches = 1;
+  h->timing_valid = true;
+  return SIM_OK;
+}
+
 int sim_last_rollout_timing(sim_handle* h, float* ms_per_launch, int* launches) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
   if (!h->timing_valid) return fail(SIM_E_STATE, "no rollout timed yet");

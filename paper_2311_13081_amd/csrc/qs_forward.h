@@ -22,6 +22,11 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
                              const float* W, const float* ext_act, float* reward, uint8_t* done,
                              float* state_out, hipStream_t st);
 hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st);
+// Dynamics-only rollout with given actions ([4][N] constant if a_tstride == 0,
+// [T][4][N] if a_tstride == 4).
+hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* act, int a_tstride,
+                              int T, float* rewards, uint8_t* dones, float* states,
+                              hipStream_t st);
 // Per-step record of the backward recompute, [T][REC_F][N]: x_t (17), a_t (4),
 // layer-1 and layer-2 pre-activations (64 + 64), observation o_t (146).
 constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z1 + NHID,

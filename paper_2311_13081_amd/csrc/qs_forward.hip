@@ -346,6 +346,86 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Dynamics-only rollout: the policy is replaced by given actions, either held
+// constant ([4][N], a_tstride = 0) or one set per step ([T][4][N],
+// a_tstride = 4).  One env per thread, no LDS, so many waves fit per SIMD.
+// The action history is brought up to date once at the end (the last 32
+// applied actions, or the reset fill after a reset), so a later policy step
+// observes exactly what it would have after stepping one by one.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride, int T,
+              float* __restrict__ rewards, uint8_t* __restrict__ dones,
+              float* __restrict__ states) {
+  const int N = c.n_envs;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float th[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) th[i] = b.theta[(size_t)i * N + e];
+  const Body<float> B = make_body<float>(th);
+  const bool renorm = (c.flags & F_RENORM_Q) != 0;
+  float x[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
+  int t_ep = b.t_ep[e], ep = b.ep[e];
+  int last_reset = -1;  // step after which the history was refilled
+  float ah = 0.0f;
+  if (states)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) states[(size_t)i * N + e] = x[i];
+  for (int t = 0; t < T; ++t) {
+    float a[NA], u[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      a[i] = act[((size_t)t * a_tstride + i) * N + e];
+      u[i] = action_to_rpm(c, a[i]);
+    }
+    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    const float r = reward(c, x, a);
+    ++t_ep;
+    const uint32_t d = episode_end(c, x, t_ep);
+    if (d && (c.flags & F_AUTORESET)) {
+      ++ep;
+      t_ep = 0;
+      last_reset = t;
+      ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
+    }
+    if (rewards) rewards[(size_t)t * N + e] = r;
+    if (dones) dones[(size_t)t * N + e] = (uint8_t)d;
+    if (states)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) states[((size_t)(t + 1) * NS + i) * N + e] = x[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + e] = x[i];
+  // history: slot 31 newest.  Actions applied after the last reset, older
+  // slots from the previous history (or the reset fill).
+  const int head0 = b.head[e];
+  const int n_new = T - 1 - last_reset;  // actions pushed since the last reset (or all T)
+  float hist[NH * NA];
+  for (int s = 0; s < NH; ++s) {
+    const int age = NH - 1 - s;  // 0 = newest
+    for (int i = 0; i < NA; ++i) {
+      float v;
+      if (age < n_new) {
+        v = act[((size_t)(T - 1 - age) * a_tstride + i) * N + e];
+      } else if (last_reset >= 0) {
+        v = ah;
+      } else {
+        const int sl = s + n_new;  // logical slot in the old history
+        v = b.ring[(size_t)((((head0 + sl) & (NH - 1)) * NA) + i) * N + e];
+      }
+      hist[s * NA + i] = v;
+    }
+  }
+  for (int i = 0; i < NH * NA; ++i) b.ring[(size_t)i * N + e] = hist[i];
+  b.head[e] = 0;
+  b.t_ep[e] = t_ep;
+  b.ep[e] = ep;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 
@@ -387,6 +467,14 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
     act = p.act;
   }
   hipLaunchKernelGGL(k_plain_dyn, g, blk, 0, st, c, b, act, reward, done, state_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* act, int a_tstride,
+                              int T, float* rewards, uint8_t* dones, float* states,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_dyn_rollout, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, act,
+                     a_tstride, T, rewards, dones, states);
   return hipGetLastError();
 }
 

@@ -88,6 +88,23 @@ class QuadSim:
                                  1 if record_tape else 0, _stream()), "sim_rollout")
         return out
 
+    def rollout_actions(self, actions: torch.Tensor, T: int, rewards=True, dones=True,
+                        states=False):
+        """Dynamics-only rollout: actions [4][N] held constant, or [T][4][N]."""
+        per_step = actions.dim() == 3
+        out = {}
+        if rewards:
+            out["rewards"] = self._f32(T, self.N)
+        if dones:
+            out["dones"] = torch.empty(T, self.N, dtype=torch.uint8, device=self.device)
+        if states:
+            out["states"] = self._f32(T + 1, 17, self.N)
+        check(self.L.sim_rollout_actions(self.h, _ptr(actions), 1 if per_step else 0, T,
+                                         _ptr(out.get("rewards")), _ptr(out.get("dones")),
+                                         _ptr(out.get("states")), _stream()),
+              "sim_rollout_actions")
+        return out
+
     def backward(self, actor: torch.Tensor, d_rewards=None, d_states=None, want_actor=True,
                  want_params=True):
         ga = torch.empty(_lib.SIM_NACTOR, dtype=torch.float32, device=self.device) if want_actor else None
