@@ -91,18 +91,21 @@ def parse():
     return ap.parse_args()
 
 
-def time_rollouts(torch, sim, actor, T, K, W):
+def time_rollouts(torch, sim, actor, T, K, W, record=False):
     """W warm-up rollouts, then K timed rollouts bracketed by synchronisation;
-    HIP events on the launch stream give the device time."""
+    HIP events on the launch stream give the device time.  record=True also
+    writes the per-step rewards [T][N] and done flags [T][N] (buffers
+    allocated before the timed region)."""
+    out = sim.rollout(actor, T, rewards=record, dones=record) if record else None
     for _ in range(W):
-        sim.rollout(actor, T, rewards=False, dones=False)
+        sim.rollout(actor, T, rewards=record, dones=record, out=out)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
     for _ in range(K):
-        sim.rollout(actor, T, rewards=False, dones=False)
+        sim.rollout(actor, T, rewards=record, dones=record, out=out)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -182,6 +185,34 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1):
     sim.close()
     return {"env_steps_per_s": N * H / dt, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
             "horizon": H, "ckpt_every": cfg["ckpt_every"]}
+
+
+def fixed_episodes(torch, pkg, actor):
+    """4096 nominal envs x 1000 steps with every episode truncated at 500
+    steps: the plain five-kernel step launched from the host, the same
+    graph-captured, the fused kernel launched once per step, and the
+    persistent fused kernel (autotuned, graph-replayed)."""
+    cfg = wl.workload_config("fwd4096")
+    T = wl.workload_steps("fwd4096")
+    N = cfg["n_envs"]
+    res = {"n_envs": N, "rollout_steps": T}
+    for label, variant, spl, use_graph in (
+            ("plain_eager", pkg.SIM_V_PLAIN, 0, False), ("plain_graph", pkg.SIM_V_PLAIN, 0, True),
+            ("fused_per_step_launch", pkg.SIM_V_FUSED_MFMA, 1, True), ("persistent", None, 0, True)):
+        sim = pkg.QuadSim(cfg)
+        if variant is None:
+            sim.autotune(actor, T)
+        else:
+            sim.set_variant(variant, spl, use_graph)
+        w, _, _ = time_rollouts(torch, sim, actor, T, 2, 1)
+        res[label] = {"env_steps_per_s": N * T * 2 / w, "ms_per_env_step": w * 1e3 / (2 * T)}
+        if variant is None:
+            v, s, g = sim.get_variant()
+            res[label]["variant"] = {1: "plain", 2: "fused_valu", 3: "fused_mfma",
+                                     4: "fused_mfma4"}[v]
+            res[label]["steps_per_launch"] = s
+        sim.close()
+    return res
 
 
 def dynamics_only(torch, pkg, n_envs, T, reps=3):
@@ -288,7 +319,14 @@ def main():
                                            "ms_per_env_step": w3 * 1e3 / (2 * args.plain_steps)}
         s3.close()
         extras["fused_vs_plain_speedup"] = value / extras["plain_graph"]["env_steps_per_s"]
+        # the headline kernel and shape with per-step rewards and done flags
+        # written to HBM (5 B per env step)
+        sim.set_variant(v, spl, graph)
+        w4, d4, l4 = time_rollouts(torch, sim, actor, T, 2, 1, record=True)
+        extras["headline_recorded"] = {"env_steps_per_s": N * T * 2 / w4,
+                                       "kernel_ms": d4 / (2 * l4)}
         res["comparison"] = extras
+        res["fixed_episodes_4096"] = fixed_episodes(torch, pkg, actor)
     sim.close()
     if not args.no_extras:
         res["fwd_bwd"] = {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
