@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain / per-step comparison legs")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (3 times): the "
                          "reference for scaling HBM traffic counters")
@@ -138,10 +138,13 @@ def cpu_baseline(cfg, W, seconds):
                       f"{dt:.1f} s"}
 
 
-def fwd_bwd(torch, pkg, name, K, W, warmup=1):
+def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
     """Forward rollout with tape + discrete adjoint on a differentiable
-    workload; returns env-steps/s of the pair (N x H per fwd+bwd)."""
+    workload; returns env-steps/s of the pair (N x H per fwd+bwd).  bf16:
+    the actor on bf16 matrix cores (SIM_F_ACTOR_BF16)."""
     cfg = wl.workload_config(name)
+    if bf16:
+        cfg["flags"] |= wl.F_ACTOR_BF16
     H = wl.workload_steps(name)
     N = cfg["n_envs"]
     sim = pkg.QuadSim(cfg)
@@ -184,7 +187,7 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1):
     dt = (time.perf_counter() - t0) / reps
     sim.close()
     return {"env_steps_per_s": N * H / dt, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
-            "horizon": H, "ckpt_every": cfg["ckpt_every"]}
+            "horizon": H, "ckpt_every": cfg["ckpt_every"], "actor": "bf16" if bf16 else "f32"}
 
 
 def fixed_episodes(torch, pkg, actor):
@@ -325,12 +328,24 @@ def main():
         w4, d4, l4 = time_rollouts(torch, sim, actor, T, 2, 1, record=True)
         extras["headline_recorded"] = {"env_steps_per_s": N * T * 2 / w4,
                                        "kernel_ms": d4 / (2 * l4)}
+        # the same workload with the bf16 actor option (a precision trade,
+        # not the headline arithmetic)
+        cfg_b = dict(cfg)
+        cfg_b["flags"] = cfg["flags"] | wl.F_ACTOR_BF16
+        s5 = pkg.QuadSim(cfg_b)
+        s5.autotune(actor, T)
+        w5, d5, l5 = time_rollouts(torch, s5, actor, T, 2, 1)
+        extras["headline_bf16_actor"] = {"env_steps_per_s": N * T * 2 / w5,
+                                         "kernel_ms": d5 / (2 * l5)}
+        s5.close()
         res["comparison"] = extras
         res["fixed_episodes_4096"] = fixed_episodes(torch, pkg, actor)
     sim.close()
     if not args.no_extras:
         res["fwd_bwd"] = {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
-                          "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0))}
+                          "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0)),
+                          "sysid16384_bf16": fwd_bwd(torch, pkg, "sysid16384", 16,
+                                                     wl.sysid_actor(0), bf16=True)}
         res["dynamics_only"] = {"n8192_T2000": dynamics_only(torch, pkg, 8192, 2000),
                                 "n65536_T1000": dynamics_only(torch, pkg, 65536, 1000)}
     if not args.no_cpu_baseline:

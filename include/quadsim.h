@@ -69,13 +69,25 @@ enum {
   SIM_F_TERMINATE = 1,  /* end episodes that leave the box or become non-finite */
   SIM_F_AUTORESET = 2,  /* reset ended episodes inside the step                  */
   SIM_F_RENORM_Q = 4,   /* renormalise the quaternion after each step           */
-  SIM_F_FP64 = 8        /* whole forward step in double precision: state, history
+  SIM_F_FP64 = 8,       /* whole forward step in double precision: state, history
                            and parameters stored in double, observation, actor,
                            RK4, reward and reset draws evaluated in double (the
                            termination box test stays in float32).  Forward only:
                            such a handle records no tape; float32 interfaces
                            (states, snapshots, parameters) round on output and
                            widen on input.  Fixed at creation.                  */
+  SIM_F_ACTOR_BF16 = 16 /* actor layers on bf16 matrix cores: weights and layer
+                           inputs rounded to bf16 (nearest even), fp32
+                           accumulation, biases and activations; the dynamics
+                           stay fp32.  Policy steps and rollouts then run on
+                           the quarter-lane kernel only (SIM_V_AUTO or
+                           SIM_V_FUSED_MFMA4); taped rollouts and their
+                           backward recompute use the same bf16 forward, the
+                           reverse sweep differentiates it with bf16-rounded
+                           weights.  Not combinable with SIM_F_FP64.  Fixed
+                           at creation.  (A precision option, not the
+                           reference arithmetic: the FP64 oracle stays the
+                           reference, and the error against it is larger.)   */
 };
 
 /* Execution variants of the forward step. */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libquadsim.so")
 SIM_NSTATE, SIM_NHIST, SIM_NACT, SIM_NOBS, SIM_NHID, SIM_NPARAM, SIM_NACTOR = (
     17, 32, 4, 146, 64, 8, 13828)
 SIM_OK, SIM_E_INVAL, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE, SIM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-SIM_F_TERMINATE, SIM_F_AUTORESET, SIM_F_RENORM_Q, SIM_F_FP64 = 1, 2, 4, 8
+SIM_F_TERMINATE, SIM_F_AUTORESET, SIM_F_RENORM_Q, SIM_F_FP64, SIM_F_ACTOR_BF16 = 1, 2, 4, 8, 16
 SIM_V_AUTO, SIM_V_PLAIN, SIM_V_FUSED_VALU, SIM_V_FUSED_MFMA, SIM_V_FUSED_MFMA4 = 0, 1, 2, 3, 4
 
 EXPORTS = (

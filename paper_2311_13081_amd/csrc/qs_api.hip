@@ -63,6 +63,8 @@ struct GraphKey {
 
 }  // namespace
 
+static_assert(SIM_F_ACTOR_BF16 == 16, "flag value is read by the quarter-lane kernel");
+
 struct sim_handle {
   sim_config cfg{};
   DevCfg dc{};
@@ -83,6 +85,7 @@ struct sim_handle {
   int last_launches = 0;
   bool timing_valid = false;
   bool fp64 = false;          // SIM_F_FP64: double-precision path only
+  bool bf16 = false;          // SIM_F_ACTOR_BF16: quarter-lane kernel with bf16 actor
   PreciseCfg pc{};
   PreciseBufs pb{};
 };
@@ -95,8 +98,11 @@ int check_config(const sim_config* c) {
   if (!c) return fail(SIM_E_INVAL, "config is NULL");
   if (c->n_envs < 1 || c->n_envs > (1 << 24)) return fail(SIM_E_INVAL, "n_envs %d out of range", c->n_envs);
   if (c->max_episode_steps < 0) return fail(SIM_E_INVAL, "max_episode_steps < 0");
-  if (c->flags & ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q | SIM_F_FP64))
+  if (c->flags &
+      ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q | SIM_F_FP64 | SIM_F_ACTOR_BF16))
     return fail(SIM_E_INVAL, "unknown flags 0x%x", c->flags);
+  if ((c->flags & SIM_F_FP64) && (c->flags & SIM_F_ACTOR_BF16))
+    return fail(SIM_E_INVAL, "SIM_F_FP64 and SIM_F_ACTOR_BF16 exclude each other");
   if ((c->flags & SIM_F_FP64) && c->max_tape_horizon > 0)
     return fail(SIM_E_UNSUPPORTED, "SIM_F_FP64 handles are forward only (max_tape_horizon 0)");
   if (c->max_tape_horizon < 0 || c->max_tape_horizon > (1 << 20))
@@ -291,6 +297,8 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   };
   rc = SIM_OK;
   h->fp64 = (cfg->flags & SIM_F_FP64) != 0;
+  h->bf16 = (cfg->flags & SIM_F_ACTOR_BF16) != 0;
+  if (h->bf16) h->tuned_variant = SIM_V_FUSED_MFMA4;  // the only kernel with the bf16 actor
   if (h->fp64) {
     h->pc = make_precise(*cfg, cfg->seed);
     rc = rc ? rc : alloc((void**)&h->pb.state, N * NS * 8);
@@ -602,6 +610,8 @@ int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_gr
   if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_MFMA4)
     return fail(SIM_E_INVAL, "unknown variant %d", variant);
   if (steps_per_launch < 0) return fail(SIM_E_INVAL, "steps_per_launch < 0");
+  if (h->bf16 && variant != SIM_V_AUTO && variant != SIM_V_FUSED_MFMA4)
+    return fail(SIM_E_UNSUPPORTED, "SIM_F_ACTOR_BF16 handles run the quarter-lane kernel only");
   h->variant = variant;
   h->spl = steps_per_launch;
   h->use_graph = use_graph ? 1 : 0;
@@ -641,6 +651,7 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   std::vector<Cand> cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0},
                              {SIM_V_FUSED_MFMA4, 100}, {SIM_V_FUSED_MFMA, 100},
                              {SIM_V_FUSED_VALU, 0},  {SIM_V_PLAIN, 0}};
+  if (h->bf16) cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA4, 100}};
   const int save_v = h->variant, save_spl = h->spl;
   float best = 1e30f;
   Cand bestc = cands[0];

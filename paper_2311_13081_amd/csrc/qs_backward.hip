@@ -66,19 +66,23 @@ __host__ __device__ constexpr int r_phi(int c, int k) {
   return c < 5 ? (4 * c + k < 18 ? 4 * c + k : -1) : c < 37 ? 18 + 4 * (c - 5) + k : -1;
 }
 
-__device__ inline void stage_reverse(const float* __restrict__ W, float* lds) {
+// Weight as the forward used it: rounded to bf16 under the bf16-actor flag.
+__device__ inline float fwd_weight(float w, bool bf16) { return bf16 ? (float)(__bf16)w : w; }
+
+__device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bool bf16) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < NA * NHID; i += nt) lds[R_W3 + i] = W[OFF_W3 + i];
+  for (int i = tid; i < NA * NHID; i += nt) lds[R_W3 + i] = fwd_weight(W[OFF_W3 + i], bf16);
   for (int idx = tid; idx < NHID * NHID; idx += nt) {
     const int v = idx & 3, i = (idx >> 2) & 15, m = (idx >> 6) & 3, g = (idx >> 8) & 3,
               n = idx >> 10;
-    lds[R_W2P + idx] = W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i];
+    lds[R_W2P + idx] = fwd_weight(W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i], bf16);
   }
   for (int idx = tid; idx < 10 * 16 * NHID; idx += nt) {
     const int v = idx & 3, i = (idx >> 2) & 15, rest = idx >> 6;  // rest = (m*4 + g)*10 + p
     const int p = rest % 10, g = (rest / 10) & 3, m = rest / 40;
     const int feat = r_phi(4 * p + (i & 3), i >> 2);
-    lds[R_W1P + idx] = feat >= 0 ? W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat] : 0.0f;
+    lds[R_W1P + idx] =
+        feat >= 0 ? fwd_weight(W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat], bf16) : 0.0f;
   }
 }
 
@@ -88,7 +92,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
               const float* __restrict__ d_states, float* __restrict__ lam,
               float* __restrict__ gth_io, float* __restrict__ dz) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
-  stage_reverse(W, lds);
+  stage_reverse(W, lds, (c.flags & F_ACTOR_BF16) != 0);
   __syncthreads();
   const int N = c.n_envs;
   const int lane = threadIdx.x & 63, j = lane & 15, k = lane >> 4;
@@ -331,7 +335,7 @@ constexpr int DW_D1 = 0, DW_D2 = DW_D1 + NHID * DW_P, DW_D3 = DW_D2 + NHID * DW_
 
 __global__ void __launch_bounds__(256)
 k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n,
-         float* __restrict__ gpart) {
+         float* __restrict__ gpart, int bf16) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -384,6 +388,10 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
         if (kind == 1)
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.0f);
+        // layer inputs as the bf16 actor saw them
+        if (bf16 && row >= 2 * NHID + 16)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = (float)(__bf16)v[q];
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = (kind == 2 && env0 + c4 + q < N) ? 1.0f : 0.0f;
@@ -576,7 +584,7 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
       BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_rev[buf], 0));
     }
     hipLaunchKernelGGL(k_bwd_dw, dim3(bw.n_parts), dim3(256), DW_TOTAL * 4, s_dw, N,
-                       bw.seg[buf], bw.dz[buf], n, bw.gpart);
+                       bw.seg[buf], bw.dz[buf], n, bw.gpart, (c.flags & F_ACTOR_BF16) ? 1 : 0);
     BWD_TRY(hipGetLastError());
     if (overlap) BWD_TRY(hipEventRecord(bw.e_dw[buf], s_dw));
     last = buf;

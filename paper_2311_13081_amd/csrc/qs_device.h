@@ -11,7 +11,7 @@ namespace qs {
 constexpr int NS = 17, NH = 32, NA = 4, NO = 146, NHID = 64, NP = 8, NW = 13828;
 constexpr int OFF_W1 = 0, OFF_B1 = NHID * NO, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
               OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NA * NHID;
-constexpr int F_TERMINATE = 1, F_AUTORESET = 2, F_RENORM_Q = 4;
+constexpr int F_TERMINATE = 1, F_AUTORESET = 2, F_RENORM_Q = 4, F_ACTOR_BF16 = 16;
 constexpr uint32_t STREAM_RESET = 0, STREAM_DR = 1;
 
 // Everything a kernel needs from the configuration, in single precision,

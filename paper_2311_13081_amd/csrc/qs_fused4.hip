@@ -17,12 +17,19 @@
 // 4 lanes with 4 lane shuffles.  The dynamics run replicated on the 4 lanes
 // (identical inputs, identical arithmetic, identical results); memory writes
 // are split among the lanes.
+//
+// Optional bf16 actor (config flag 16): weights are staged in LDS as bf16 and
+// the layer inputs are rounded to bf16 (round to nearest even) before
+// v_mfma_f32_16x16x32_bf16; accumulation, biases, activations and the whole
+// dynamics stay fp32.  The same quarter layout serves: one bf16 instruction
+// takes 8 consecutive chunks of the lane's quarter as its 8 K-elements.
 #include "qs_device.h"
 #include "qs_forward.h"
 
 namespace qs {
 
 typedef float f4q __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8q __attribute__((ext_vector_type(8)));
 
 constexpr int Q_C = 37;          // K-chunks of layer 1
 constexpr int Q_CP = 40;         // padded to whole float4s
@@ -140,17 +147,149 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
     z3[o] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[o])));
 }
 
+// ---------------------------------------------------------------------------
+// bf16 actor.  LDS layout in bf16 elements:
+//   QB_W1: row lg * 64 + neuron, 40 chunks (PHI order of quarter lg, zero
+//          padded): one lane reads the 8 chunks of one instruction as 16 B;
+//          the pitch of 20 dwords puts 8 consecutive lanes on distinct banks.
+//   QB_W2: row = output neuron, pitch 72; within a row, instruction m (layer-1
+//          tiles 2m, 2m+1) and lane group lg hold the 8 inputs
+//          32m + 16 (e >> 2) + 4 lg + (e & 3), e = 0..7, which is the order in
+//          which the previous layer's result registers arrive.
+//   QB_W3: as QB_W2 for the 4 outputs (rows 4..15 zero).
+// Biases stay fp32 after the bf16 part.
+// ---------------------------------------------------------------------------
+constexpr int QB_P1 = 40, QB_P2 = 72;
+constexpr int QB_W1 = 0, QB_W2 = QB_W1 + 4 * NHID * QB_P1, QB_W3 = QB_W2 + NHID * QB_P2,
+              QB_BF16_END = QB_W3 + 16 * QB_P2;
+constexpr int QB_FBASE = QB_BF16_END / 2;  // first fp32 slot after the bf16 part
+constexpr int QB_B1 = QB_FBASE, QB_B2 = QB_B1 + NHID, QB_B3 = QB_B2 + NHID,
+              QB_TOTAL = QB_B3 + 4;          // in floats
+static_assert(QB_BF16_END % 8 == 0, "fp32 part must stay 16-byte aligned");
+
+// Input index (within 0..63) of element e of instruction m, lane group lg.
+__host__ __device__ constexpr int qb_in(int m, int lg, int e) {
+  return 32 * m + 16 * (e >> 2) + 4 * lg + (e & 3);
+}
+
+__device__ inline void stage_qb(const float* __restrict__ W, float* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __bf16* h = reinterpret_cast<__bf16*>(lds);
+  for (int idx = tid; idx < 4 * NHID * QB_P1; idx += nt) {
+    const int c = idx % QB_P1, row = idx / QB_P1, nrn = row & (NHID - 1), k = row / NHID;
+    const int f = c < Q_C ? q_phi(c, k) : -1;
+    h[QB_W1 + idx] = (__bf16)(f >= 0 ? W[OFF_W1 + nrn * NO + f] : 0.0f);
+  }
+  for (int idx = tid; idx < NHID * QB_P2; idx += nt) {
+    const int r = idx / QB_P2, col = idx % QB_P2;
+    float v = 0.0f;
+    if (col < NHID) v = W[OFF_W2 + r * NHID + qb_in(col >> 5, (col >> 3) & 3, col & 7)];
+    h[QB_W2 + idx] = (__bf16)v;
+  }
+  for (int idx = tid; idx < 16 * QB_P2; idx += nt) {
+    const int r = idx / QB_P2, col = idx % QB_P2;
+    float v = 0.0f;
+    if (r < NA && col < NHID) v = W[OFF_W3 + r * NHID + qb_in(col >> 5, (col >> 3) & 3, col & 7)];
+    h[QB_W3 + idx] = (__bf16)v;
+  }
+  for (int i = tid; i < NHID; i += nt) {
+    lds[QB_B1 + i] = W[OFF_B1 + i];
+    lds[QB_B2 + i] = W[OFF_B2 + i];
+  }
+  for (int i = tid; i < NA; i += nt) lds[QB_B3 + i] = W[OFF_B3 + i];
+}
+
+// bf16 operand of one instruction from two result tiles (ReLU applied).
+__device__ inline bf8q relu_pack(const f4q& lo, const f4q& hi) {
+  bf8q v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    v[e] = (__bf16)fmaxf(lo[e], 0.0f);
+    v[4 + e] = (__bf16)fmaxf(hi[e], 0.0f);
+  }
+  return v;
+}
+
+// Same contract as actor_q, bf16 operands.
+__device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[NA],
+                                float* __restrict__ rz1, float* __restrict__ rz2, int N,
+                                int env0, uint32_t rec_lane_off) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const __bf16* h = reinterpret_cast<const __bf16*>(lds);
+  f4q acc1[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc1[n][r] = lds[QB_B1 + 16 * n + 4 * lg + r];
+#pragma unroll
+  for (int g = 0; g < QB_P1 / 8; ++g) {
+    bf8q x;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (__bf16)(8 * g + e < Q_C ? F[8 * g + e] : 0.0f);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const bf8q w = *reinterpret_cast<const bf8q*>(
+          &h[QB_W1 + (lg * NHID + 16 * n + li) * QB_P1 + 8 * g]);
+      acc1[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, acc1[n], 0, 0, 0);
+    }
+  }
+  const int env = env0 + li;
+  if (rz1 && env < N) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * N + rec_lane_off] = acc1[n][r];
+  }
+  f4q acc2[4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc2[n2][r] = lds[QB_B2 + 16 * n2 + 4 * lg + r];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const bf8q x = relu_pack(acc1[2 * m], acc1[2 * m + 1]);
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const bf8q w =
+          *reinterpret_cast<const bf8q*>(&h[QB_W2 + (16 * n2 + li) * QB_P2 + 32 * m + 8 * lg]);
+      acc2[n2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, acc2[n2], 0, 0, 0);
+    }
+  }
+  if (rz2 && env < N) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * N + rec_lane_off] = acc2[n2][r];
+  }
+  f4q acc3;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc3[r] = lg == 0 ? lds[QB_B3 + r] : 0.0f;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const bf8q x = relu_pack(acc2[2 * m], acc2[2 * m + 1]);
+    const bf8q w = *reinterpret_cast<const bf8q*>(&h[QB_W3 + li * QB_P2 + 32 * m + 8 * lg]);
+    acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, acc3, 0, 0, 0);
+  }
+  const int src = li << 2;
+#pragma unroll
+  for (int o = 0; o < NA; ++o)
+    z3[o] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[o])));
+}
+
 // Two waves per SIMD (256 registers each) so one wave's vector work overlaps
 // the other's matrix-core work.
-template <int DUMMY>
+template <bool BF16>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
          float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states,
          float* __restrict__ tape, int ckpt_every, const float* __restrict__ ck_in,
          float* __restrict__ rec) {
-  __shared__ __attribute__((aligned(16))) float lds[Q_TOTAL];
+  __shared__ __attribute__((aligned(16))) float lds[BF16 ? QB_TOTAL : Q_TOTAL];
   const int N = c.n_envs;
-  stage_q(W, lds);
+  if (BF16)
+    stage_qb(W, lds);
+  else
+    stage_q(W, lds);
   __syncthreads();
   const int lane = threadIdx.x & 63, j = lane & 15, k = lane >> 4;
   const int env0 = (blockIdx.x * blockDim.x + threadIdx.x - lane) / 4;  // first env of the wave
@@ -223,8 +362,12 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     // per-lane part of record addresses, recomputed every step (see opaque())
     const uint32_t zoff = opaque((uint32_t)(4 * k * N + env0 + j));
     const uint32_t koff = opaque((uint32_t)(k * N + e));
-    actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
-            rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
+    if (BF16)
+      actor_qb(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
+               rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
+    else
+      actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
+              rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
     float a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
@@ -291,8 +434,12 @@ hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int 
                          float* rewards, uint8_t* dones, float* states, float* tape,
                          int ckpt_every, const float* ck_in, float* rec, hipStream_t st) {
   const unsigned grid = (unsigned)((c.n_envs + 63) / 64);
-  hipLaunchKernelGGL(k_fused4<0>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards,
-                     dones, states, tape, ckpt_every, ck_in, rec);
+  if (c.flags & F_ACTOR_BF16)
+    hipLaunchKernelGGL(k_fused4<true>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards,
+                       dones, states, tape, ckpt_every, ck_in, rec);
+  else
+    hipLaunchKernelGGL(k_fused4<false>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base,
+                       rewards, dones, states, tape, ckpt_every, ck_in, rec);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ F_TERMINATE = 1
 F_AUTORESET = 2
 F_RENORM_Q = 4
 F_FP64 = 8
+F_ACTOR_BF16 = 16
 
 PARAM_NAMES = ("m", "Jxx", "Jyy", "Jzz", "c0", "c1", "c2", "Tm")
 
