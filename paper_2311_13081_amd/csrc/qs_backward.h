@@ -10,16 +10,17 @@ namespace qs {
 constexpr int BWD_NBUF = 3;
 struct BwdBufs {
   int N = 0, K = 0, H = 0;
-  int n_parts = 0;                    // workgroups of the weight-gradient reduction
+  int n_parts = 0;                    // partial slots of the weight gradients (chunks x groups)
+  int dw_groups = 1;                  // step groups per 64-env chunk
   int n_cu = 0;                       // compute units of the device
-  float* seg[BWD_NBUF] = {};          // [K][REC_F][N] per-step recompute record of a segment
-  float* dz[BWD_NBUF] = {};           // [K][132][N] layer cotangents of a segment
+  float* seg[BWD_NBUF] = {};          // [K] steps of REC_F blocked rows (rb_at) per env: record
+  float* dz[BWD_NBUF] = {};           // [K] steps of 132 blocked rows per env: layer cotangents
   hipStream_t s_rec = nullptr, s_dw = nullptr;
   hipEvent_t e_init = nullptr, e_rec[BWD_NBUF] = {}, e_rev[BWD_NBUF] = {},
              e_dw[BWD_NBUF] = {};
   float* lam = nullptr;    // [145][N] state and history adjoints between segments
   float* gth = nullptr;    // [8][N] parameter gradients
-  float* gpart = nullptr;  // [n_parts][13828] per-workgroup weight-gradient partials
+  float* gpart = nullptr;  // [n_parts][13828] weight-gradient partials, one per slot
   float* gsum = nullptr;   // [13828] sink when no actor gradient is requested
 };
 

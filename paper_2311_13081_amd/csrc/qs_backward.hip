@@ -86,6 +86,39 @@ __device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bo
   }
 }
 
+// Inputs of one reverse step: the recorded state and action, this lane's
+// 16 layer-1 and layer-2 pre-activations (rows 16 q + 4 k + r), the reward
+// and state cotangents.
+struct StepIn {
+  float x[NS], a[NA], z1[16], z2[16], dS[NS], dR;
+};
+
+__device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __restrict__ rec,
+                                 const float* __restrict__ d_rewards,
+                                 const float* __restrict__ d_states, int tl, int t0, int N, int e,
+                                 int k) {
+  const uint32_t eo = opaque((uint32_t)e);
+  const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
+  const uint32_t zoff = opaque((uint32_t)(rb_at(e, REC_F) + 4 * k * RB));
+  const int t = t0 + tl;
+  const float* rt = rec + (size_t)tl * REC_F * rb_pad(N);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) in.x[i] = rt[(size_t)(REC_X + i) * RB + roff];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) in.a[i] = rt[(size_t)(REC_A + i) * RB + roff];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      in.z1[4 * q + r] = rt[(size_t)(REC_Z1 + 16 * q + r) * RB + zoff];
+      in.z2[4 * q + r] = rt[(size_t)(REC_Z2 + 16 * q + r) * RB + zoff];
+    }
+  in.dR = d_rewards ? d_rewards[(size_t)t * N + eo] : 1.0f;
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    in.dS[i] = d_states ? d_states[((size_t)t * NS + i) * N + eo] : 0.0f;
+}
+
 __global__ void __launch_bounds__(256)
 k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict__ W,
               const float* __restrict__ rec, int n, int t0, const float* __restrict__ d_rewards,
@@ -117,23 +150,26 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 #pragma unroll
   for (int i = 0; i < NP; ++i) gth[i] = gth_io[(size_t)i * N + e];
 
+  // The per-step inputs (record rows and cotangents) of step tl - 1 are
+  // loaded while step tl is processed, so their latency hides behind it.
+  StepIn cur, nxt;
+  load_step(cur, c, rec, d_rewards, d_states, n - 1, t0, N, e, k);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
-    const uint32_t eo = opaque((uint32_t)e);
-    const uint32_t zoff = opaque((uint32_t)(4 * k * N + e));  // (row 4k, this env)
-    const uint32_t koff = opaque((uint32_t)(k * N + e));             // (row k, env)
-    const int t = t0 + tl;
-    const float* rt = rec + (size_t)tl * REC_F * N;
-    float* dzt = dz + (size_t)tl * DZ_F * N;
+    load_step(nxt, c, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k);
+    // blocked cotangent rows of this env: row k and row 4k
+    const uint32_t koff = opaque((uint32_t)(rb_at(e, DZ_F) + k * RB));
+    const uint32_t zoff = opaque((uint32_t)(rb_at(e, DZ_F) + 4 * k * RB));
+    float* dzt = dz + (size_t)tl * DZ_F * rb_pad(N);
     float x[NS], a[NA], u[NA];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) x[i] = rt[(size_t)(REC_X + i) * N + eo];
+    for (int i = 0; i < NS; ++i) x[i] = cur.x[i];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      a[i] = rt[(size_t)(REC_A + i) * N + eo];
+      a[i] = cur.a[i];
       u[i] = action_to_rpm(c, a[i]);
     }
-    const float dR = d_rewards ? d_rewards[(size_t)t * N + eo] : 1.0f;
+    const float dR = cur.dR;
 
     // --- forward recompute of the RK4 stages -------------------------------
     float x2[NS], x3[NS], x4[NS], kd[NS], acc[NS];
@@ -229,7 +265,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 #pragma unroll
     for (int i = 0; i < NA; ++i) d3[i] = ga[i] * (1.0f - a[i] * a[i]);
     const float d3k = k == 0 ? d3[0] : k == 1 ? d3[1] : k == 2 ? d3[2] : d3[3];
-    if (active) dzt[(size_t)(2 * NHID) * N + koff] = d3k;
+    if (active) dzt[(size_t)(2 * NHID) * RB + koff] = d3k;
     // dz2 = (W3^T dz3) * [z2 > 0]: tile q rows 16q + 4k + r, env j
     f4 dz2[4];
 #pragma unroll
@@ -238,9 +274,9 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
                                                     f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float z2 = rt[(size_t)(REC_Z2 + 16 * q + r) * N + zoff];
+        const float z2 = cur.z2[4 * q + r];
         dz2[q][r] = z2 > 0.0f ? dz2[q][r] : 0.0f;
-        if (active) dzt[(size_t)(NHID + 16 * q + r) * N + zoff] = dz2[q][r];
+        if (active) dzt[(size_t)(NHID + 16 * q + r) * RB + zoff] = dz2[q][r];
       }
     }
     // dz1 = (W2^T dz2) * [z1 > 0]
@@ -258,9 +294,9 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float z1 = rt[(size_t)(REC_Z1 + 16 * mt + r) * N + zoff];
+        const float z1 = cur.z1[4 * mt + r];
         dz1[mt][r] = z1 > 0.0f ? accm[r] : 0.0f;
-        if (active) dzt[(size_t)(16 * mt + r) * N + zoff] = dz1[mt][r];
+        if (active) dzt[(size_t)(16 * mt + r) * RB + zoff] = dz1[mt][r];
       }
     }
     // do = W1^T dz1 in observation order: tile p, register r of quarter k is
@@ -307,7 +343,8 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i)
-      ls[i] = gx[i] + (d_states ? d_states[((size_t)t * NS + i) * N + eo] : 0.0f);
+      ls[i] = gx[i] + cur.dS[i];
+    cur = nxt;
   }
   if (!active) return;
   const uint32_t ef = opaque((uint32_t)e);
@@ -324,23 +361,115 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 
 // Weight gradients of one segment: for every (step, env) row,
 //   dW1 += dz1 o^T, dW2 += dz2 relu(z1)^T, dW3 += dz3 relu(z2)^T, db += dz,
-// as MFMA reductions over 16 rows at a time.  Workgroup = 4 waves over a
-// 64-env chunk; wave w owns neuron tile w of dW1 and dW2 and feature tile w
-// of dW3 (wave 0 also tile 4).
-constexpr int DW_P = 68;  // LDS row pitch (64 envs + 4)
-constexpr int DW_O_ROWS = 160, DW_H_ROWS = 80;
-constexpr int DW_D1 = 0, DW_D2 = DW_D1 + NHID * DW_P, DW_D3 = DW_D2 + NHID * DW_P,
-              DW_O = DW_D3 + 16 * DW_P, DW_H1 = DW_O + DW_O_ROWS * DW_P,
-              DW_H2 = DW_H1 + DW_H_ROWS * DW_P, DW_TOTAL = DW_H2 + DW_H_ROWS * DW_P;
+// on fp32 MFMA (v_mfma_f32_16x16x4f32) with the rows as the K dimension:
+// A[i][k] (lane i + 16 k) = dz of neuron 16 w + i at env e0 + k, B[k][j] =
+// input column j of a 16-column tile at the same env; the result register r
+// of a tile holds row 4 lg + r, column li.  Biases come from a constant-one
+// input column (generated, not stored).
+//
+// One workgroup per (64-env block, step group), one wave per 16-neuron tile
+// w.  The layer inputs of a step (o, relu(z1), relu(z2): 274 rows x 64 envs,
+// read once from HBM as whole 256-byte block rows) are staged in LDS and
+// shared by the four waves; the staging of step t + 1 is issued into
+// registers before step t's matrix work and written to the other LDS buffer
+// after it, so the loads' latency hides behind the MFMAs.  Each wave reads its
+// own dz rows straight from the record, also one step ahead.  Layer 3 (4
+// outputs) is split by column tiles: wave w takes tile w, wave 0 also tile 4
+// (the bias column).  Each (block, step group) owns one partial slot,
+// accumulated across segments.
+constexpr int DW_ROWS = NO + 2 * NHID;  // staged input rows per step: o | z1 | z2
+constexpr int DW_P = 68;                // LDS row pitch in floats (64 envs + 4)
+constexpr int DW_BUF = DW_ROWS * DW_P;  // floats per staging buffer
+constexpr int DW_LD = (DW_ROWS * 16 + 255) / 256;  // float4 staging loads per thread
+
+// Four consecutive envs e..e+3 of one blocked row (p points at env e);
+// envs >= N read as zero.
+__device__ inline f4 dw_load(const float* __restrict__ p, int e, int N) {
+  if (e + 4 <= N) return *reinterpret_cast<const f4*>(p);
+  f4 v;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = e + m < N ? p[m] : 0.0f;
+  return v;
+}
+
+struct DwStage {
+  f4 v[DW_LD];
+};
+
+// Issues the staging loads of one step (input row r, envs 4 c4 .. 4 c4 + 3
+// for slot i of thread tid: r = tid / 16 + 16 i, c4 = tid % 16).
+__device__ inline void dw_stage_load(DwStage& sg, const float* __restrict__ rt, int env0, int N,
+                                     int tid) {
+  const int c = (tid & 15) * 4;
+#pragma unroll
+  for (int i = 0; i < DW_LD; ++i) {
+    const int r = (tid >> 4) + 16 * i;
+    const int f = r < NO ? REC_O + r : REC_Z1 + (r - NO);  // z1 and z2 rows are adjacent
+    sg.v[i] = r < DW_ROWS ? dw_load(rt + (size_t)f * RB + c, env0 + c, N)
+                          : f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+}
+
+// Writes staged rows to an LDS buffer: ReLU on the z rows, bf16 rounding of
+// every input when the forward rounded it.
+__device__ inline void dw_stage_store(const DwStage& sg, float* buf, int tid, int bf16) {
+  const int c = (tid & 15) * 4;
+#pragma unroll
+  for (int i = 0; i < DW_LD; ++i) {
+    const int r = (tid >> 4) + 16 * i;
+    if (r < DW_ROWS) {
+      f4 v = sg.v[i];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (r >= NO) v[m] = fmaxf(v[m], 0.0f);
+        if (bf16) v[m] = (float)(__bf16)v[m];
+      }
+      *reinterpret_cast<f4*>(&buf[r * DW_P + c]) = v;
+    }
+  }
+}
+
+struct DwA {
+  f4 a1[4], a2[4], a3[4];
+};
+
+__device__ inline void dw_a_load(DwA& A, const float* __restrict__ dzt, int env0, int N, int w,
+                                 int li, int lg) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = 16 * q + 4 * lg;
+    A.a1[q] = dw_load(dzt + (size_t)(16 * w + li) * RB + col, env0 + col, N);
+    A.a2[q] = dw_load(dzt + (size_t)(NHID + 16 * w + li) * RB + col, env0 + col, N);
+    A.a3[q] = li < NA ? dw_load(dzt + (size_t)(2 * NHID + li) * RB + col, env0 + col, N)
+                      : f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+}
+
+// B operand: input column `row` of a layer with n_in inputs whose staged
+// rows start at LDS row `base`: the staged value, the bias column of ones
+// (valid envs) at row == n_in, zeros beyond.
+__device__ inline f4 dw_b(const float* buf, int base, int row, int n_in, int col, int env0,
+                          int N) {
+  if (row < n_in) return *reinterpret_cast<const f4*>(&buf[(base + row) * DW_P + col]);
+  f4 v;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = (row == n_in && env0 + col + m < N) ? 1.0f : 0.0f;
+  return v;
+}
 
 __global__ void __launch_bounds__(256)
-k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n,
+k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n, int S,
          float* __restrict__ gpart, int bf16) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int env0 = blockIdx.x * 64;
+  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int chunk = blockIdx.x, w = tid >> 6, sg = blockIdx.y;
+  const int env0 = chunk * RB;
+  const int per = (n + S - 1) / S;
+  const int t_begin = sg * per, t_end = (t_begin + per) < n ? (t_begin + per) : n;
+  const size_t rstep = (size_t)REC_F * rb_pad(N), dstep = (size_t)DZ_F * rb_pad(N);
+  const float* rblk = rec + (size_t)chunk * REC_F * RB;
+  const float* dblk = dz + (size_t)chunk * DZ_F * RB;
 
   f4 acc1[10], acc2[5], acc3[2];
 #pragma unroll
@@ -349,94 +478,61 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
   for (int i = 0; i < 5; ++i) acc2[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   acc3[0] = acc3[1] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  for (int tl = 0; tl < n; ++tl) {
-    const float* rt = rec + (size_t)tl * REC_F * N;
-    const float* dzt = dz + (size_t)tl * DZ_F * N;
-    __syncthreads();  // previous step's tiles consumed
-    // Stage the 64-env chunk: rows are features, columns envs.  Each thread
-    // moves 4 consecutive envs of a row; the loads of one pass are issued
-    // together (unrolled) so their latencies overlap.
-    const bool full = (env0 + 64 <= N) && ((N & 3) == 0);
-    const int c4 = (tid & 15) * 4;
-#pragma unroll 4
-    for (int row = tid >> 4; row < DW_TOTAL / DW_P; row += 16) {
-      const float* src = nullptr;
-      int kind = 0;  // 0: copy, 1: relu, 2: ones (valid envs), 3: zeros
-      if (row < 2 * NHID) {
-        src = dzt + (size_t)row * N;
-      } else if (row < 2 * NHID + 16) {
-        const int r = row - 2 * NHID;
-        if (r < NA) src = dzt + (size_t)(2 * NHID + r) * N; else kind = 3;
-      } else if (row < 2 * NHID + 16 + DW_O_ROWS) {
-        const int r = row - (2 * NHID + 16);
-        if (r < NO) src = rt + (size_t)(REC_O + r) * N; else kind = r == NO ? 2 : 3;
-      } else if (row < 2 * NHID + 16 + DW_O_ROWS + DW_H_ROWS) {
-        const int r = row - (2 * NHID + 16 + DW_O_ROWS);
-        if (r < NHID) { src = rt + (size_t)(REC_Z1 + r) * N; kind = 1; } else kind = r == NHID ? 2 : 3;
-      } else {
-        const int r = row - (2 * NHID + 16 + DW_O_ROWS + DW_H_ROWS);
-        if (r < NHID) { src = rt + (size_t)(REC_Z2 + r) * N; kind = 1; } else kind = r == NHID ? 2 : 3;
-      }
-      f4 v;
-      if (src) {
-        if (full) {
-          v = *reinterpret_cast<const f4*>(src + env0 + c4);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = env0 + c4 + q < N ? src[env0 + c4 + q] : 0.0f;
-        }
-        if (kind == 1)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.0f);
-        // layer inputs as the bf16 actor saw them
-        if (bf16 && row >= 2 * NHID + 16)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = (float)(__bf16)v[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (kind == 2 && env0 + c4 + q < N) ? 1.0f : 0.0f;
-      }
-      *reinterpret_cast<f4*>(&sm[row * DW_P + c4]) = v;
-    }
+  if (t_begin < t_end) {
+    DwStage st;
+    DwA A, An;
+    dw_stage_load(st, rblk + (size_t)t_begin * rstep, env0, N, tid);
+    dw_a_load(A, dblk + (size_t)t_begin * dstep, env0, N, w, li, lg);
+    dw_stage_store(st, sm, tid, bf16);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c0 = 16 * q + 4 * lg;  // this lane's 4 rows (envs) of the 16
-      const f4 a1 = *reinterpret_cast<const f4*>(&sm[DW_D1 + (16 * wave + li) * DW_P + c0]);
-      const f4 a2 = *reinterpret_cast<const f4*>(&sm[DW_D2 + (16 * wave + li) * DW_P + c0]);
-      const f4 a3 = *reinterpret_cast<const f4*>(&sm[DW_D3 + li * DW_P + c0]);
-#pragma unroll
-      for (int kt = 0; kt < 10; ++kt) {
-        const f4 bo = *reinterpret_cast<const f4*>(&sm[DW_O + (16 * kt + li) * DW_P + c0]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[m], bo[m], acc1[kt], 0, 0, 0);
+    for (int tl = t_begin; tl < t_end; ++tl) {
+      const int cur = (tl - t_begin) & 1;
+      const float* buf = sm + cur * DW_BUF;
+      const bool more = tl + 1 < t_end;
+      if (more) {  // next step's loads in flight during this step's MFMAs
+        dw_stage_load(st, rblk + (size_t)(tl + 1) * rstep, env0, N, tid);
+        dw_a_load(An, dblk + (size_t)(tl + 1) * dstep, env0, N, w, li, lg);
       }
 #pragma unroll
-      for (int kt = 0; kt < 5; ++kt) {
-        const f4 bh = *reinterpret_cast<const f4*>(&sm[DW_H1 + (16 * kt + li) * DW_P + c0]);
+      for (int q = 0; q < 4; ++q) {
+        const int col = 16 * q + 4 * lg;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-          acc2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[m], bh[m], acc2[kt], 0, 0, 0);
+        for (int kt = 0; kt < 10; ++kt) {
+          const f4 bo = dw_b(buf, 0, 16 * kt + li, NO, col, env0, N);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a1[q][m], bo[m], acc1[kt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int kt = 0; kt < 5; ++kt) {
+          const f4 bh = dw_b(buf, NO, 16 * kt + li, NHID, col, env0, N);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            acc2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a2[q][m], bh[m], acc2[kt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (j == 1 && w != 0) break;
+          const int kt = j == 0 ? w : 4;
+          const f4 bh = dw_b(buf, NO + NHID, 16 * kt + li, NHID, col, env0, N);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            acc3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a3[q][m], bh[m], acc3[j], 0, 0, 0);
+        }
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int kt = j == 0 ? wave : 4;
-        if (j == 1 && wave != 0) break;
-        const f4 bh = *reinterpret_cast<const f4*>(&sm[DW_H2 + (16 * kt + li) * DW_P + c0]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          acc3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[m], bh[m], acc3[j], 0, 0, 0);
+      if (more) {
+        dw_stage_store(st, sm + (cur ^ 1) * DW_BUF, tid, bf16);
+        A = An;
       }
+      __syncthreads();  // next buffer complete; this buffer free for reuse
     }
   }
-  // Result register r of a tile holds row 4 lg + r, column li.
-  float* gp = gpart + (size_t)blockIdx.x * NW;
+  float* gp = gpart + ((size_t)chunk * S + sg) * NW;
 #pragma unroll
   for (int kt = 0; kt < 10; ++kt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int nrn = 16 * wave + 4 * lg + r, col = 16 * kt + li;
+      const int nrn = 16 * w + 4 * lg + r, col = 16 * kt + li;
       if (col < NO) gp[OFF_W1 + nrn * NO + col] += acc1[kt][r];
       else if (col == NO) gp[OFF_B1 + nrn] += acc1[kt][r];
     }
@@ -444,14 +540,14 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
   for (int kt = 0; kt < 5; ++kt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int nrn = 16 * wave + 4 * lg + r, col = 16 * kt + li;
+      const int nrn = 16 * w + 4 * lg + r, col = 16 * kt + li;
       if (col < NHID) gp[OFF_W2 + nrn * NHID + col] += acc2[kt][r];
       else if (col == NHID) gp[OFF_B2 + nrn] += acc2[kt][r];
     }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (j == 1 && wave != 0) break;
-    const int kt = j == 0 ? wave : 4;
+    if (j == 1 && w != 0) break;
+    const int kt = j == 0 ? w : 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int o = 4 * lg + r, col = 16 * kt + li;
@@ -483,11 +579,24 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   bw.N = N;
   bw.K = K;
   bw.H = H;
-  bw.n_parts = (int)nb(N, 64);
+  // Step groups of the weight-gradient pass: one workgroup per CU (the
+  // double-buffered staging takes most of the LDS), so about n_cu workgroups.
+  const int chunks = (int)nb(N, 64);
+  int n_cu = 256;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  }
+  int S = n_cu / chunks;
+  if (S > K) S = K;
+  if (S < 1) S = 1;
+  bw.dw_groups = S;
+  bw.n_parts = chunks * S;
   hipError_t e;
   for (int i = 0; i < BWD_NBUF; ++i) {
-    if ((e = hipMalloc(&bw.seg[i], (size_t)K * REC_F * N * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * N * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc(&bw.seg[i], (size_t)K * REC_F * rb_pad(N) * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_rec[i], hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_rev[i], hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_dw[i], hipEventDisableTiming)) != hipSuccess) return e;
@@ -509,7 +618,7 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
       hipSuccess)
     return e;
   return hipFuncSetAttribute((const void*)k_bwd_dw, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             DW_TOTAL * 4);
+                             2 * DW_BUF * 4);
 }
 
 void bwd_free(BwdBufs& bw) {
@@ -545,9 +654,9 @@ void bwd_free(BwdBufs& bw) {
 // previous ones overlap the sweep.  The caller's stream finally waits for
 // the last weight-gradient pass before the fixed-order partial sum.
 // Overlap only pays while the sweep leaves compute units idle (fewer
-// workgroups than CUs): a full-chip sweep and the LDS-heavy weight-gradient
-// pass cannot share a CU, so for large batches everything stays on the
-// caller's stream in order.
+// workgroups than CUs); for large batches the sweep (one wave per SIMD, most
+// registers) fills the chip and everything stays on the caller's stream in
+// order.
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
@@ -583,8 +692,9 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
       BWD_TRY(hipEventRecord(bw.e_rev[buf], st));
       BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_rev[buf], 0));
     }
-    hipLaunchKernelGGL(k_bwd_dw, dim3(bw.n_parts), dim3(256), DW_TOTAL * 4, s_dw, N,
-                       bw.seg[buf], bw.dz[buf], n, bw.gpart, (c.flags & F_ACTOR_BF16) ? 1 : 0);
+    hipLaunchKernelGGL(k_bwd_dw, dim3(nb(N, 64), bw.dw_groups), dim3(256), 2 * DW_BUF * 4, s_dw, N,
+                       bw.seg[buf], bw.dz[buf], n, bw.dw_groups, bw.gpart,
+                       (c.flags & F_ACTOR_BF16) ? 1 : 0);
     BWD_TRY(hipGetLastError());
     if (overlap) BWD_TRY(hipEventRecord(bw.e_dw[buf], s_dw));
     last = buf;

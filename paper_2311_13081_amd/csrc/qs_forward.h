@@ -27,10 +27,23 @@ hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st
 hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* act, int a_tstride,
                               int T, float* rewards, uint8_t* dones, float* states,
                               hipStream_t st);
-// Per-step record of the backward recompute, [T][REC_F][N]: x_t (17), a_t (4),
-// layer-1 and layer-2 pre-activations (64 + 64), observation o_t (146).
+// Per-step record of the backward recompute, REC_F rows per env: x_t (17),
+// a_t (4), layer-1 and layer-2 pre-activations (64 + 64), observation o_t
+// (146).
 constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z1 + NHID,
               REC_O = REC_Z2 + NHID, REC_F = REC_O + NO;
+
+// The backward's per-step records (and the layer cotangents) are blocked by
+// 64 envs: within one step, row f of env e sits at rb_at(e, F) + 64 f, F the
+// rows per env.  The rows of a block are 256 B apart and a block's record of
+// a step is one contiguous span, so the readers, which take a few envs of
+// many rows at a time, stay within a few DRAM pages.  A step holds rb_pad(N)
+// env slots; the slots of envs >= N in the last block are never written.
+constexpr int RB = 64;
+__host__ __device__ inline size_t rb_pad(int N) { return (size_t)((N + RB - 1) / RB) * RB; }
+__host__ __device__ inline size_t rb_at(int e, int F) {
+  return (size_t)(e / RB) * F * RB + (size_t)(e % RB);
+}
 
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st);

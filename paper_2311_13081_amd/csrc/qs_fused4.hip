@@ -68,7 +68,8 @@ __device__ inline void stage_q(const float* __restrict__ W, float* lds) {
 
 // Actor for the wave's 16 envs.  F: this lane's 37 layer-1 operands.  Returns
 // z3 (pre-tanh) of this lane's env in every lane.  When rz1/rz2 are given,
-// writes the layer pre-activations ([64][N] rows, env0 + j columns).
+// writes the layer pre-activations (64 rows of the blocked record; the lane
+// offset rec_lane_off addresses row 4 lg of this lane's env).
 __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA],
                                float* __restrict__ rz1, float* __restrict__ rz2, int N,
                                int env0, uint32_t rec_lane_off) {
@@ -100,7 +101,7 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * N + rec_lane_off] = acc1[n][r];
+      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * RB + rec_lane_off] = acc1[n][r];
   }
 #pragma unroll
   for (int n = 0; n < 4; ++n)
@@ -124,7 +125,7 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * N + rec_lane_off] = acc2[n2][r];
+      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * RB + rec_lane_off] = acc2[n2][r];
   }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)
@@ -238,7 +239,7 @@ __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[N
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * N + rec_lane_off] = acc1[n][r];
+      for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * n + r) * RB + rec_lane_off] = acc1[n][r];
   }
   f4q acc2[4];
 #pragma unroll
@@ -259,7 +260,7 @@ __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[N
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * N + rec_lane_off] = acc2[n2][r];
+      for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * RB + rec_lane_off] = acc2[n2][r];
   }
   f4q acc3;
 #pragma unroll
@@ -357,17 +358,18 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
         F[cc] = k == 0 ? sf[4 * cc] : k == 1 ? sf[4 * cc + 1] : k == 2 ? sf[4 * cc + 2]
                                                                         : sf[4 * cc + 3];
     }
-    float* rt = rec_on ? rec + (size_t)t * REC_F * N : nullptr;
+    float* rt = rec_on ? rec + (size_t)t * REC_F * rb_pad(N) : nullptr;
     float z3[NA];
     // per-lane part of record addresses, recomputed every step (see opaque())
-    const uint32_t zoff = opaque((uint32_t)(4 * k * N + env0 + j));
-    const uint32_t koff = opaque((uint32_t)(k * N + e));
+    const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
+    const uint32_t koff = opaque((uint32_t)(rb_at(e, REC_F) + k * RB));
+    const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
     if (BF16)
-      actor_qb(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
-               rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
+      actor_qb(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
+               rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff);
     else
-      actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
-              rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, env0, zoff);
+      actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
+              rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff);
     float a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
@@ -376,12 +378,12 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       for (int cc = 0; cc < Q_C; ++cc) {
         // feature q_phi(cc, k) = base + k for valid slots
         const int base = cc < 5 ? 4 * cc : 18 + 4 * (cc - 5);
-        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + base) * N + koff] = F[cc];
+        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + base) * RB + koff] = F[cc];
       }
 #pragma unroll
       for (int i = 0; i < NS; ++i)
-        if ((i & 3) == k) rt[(size_t)(REC_X + i) * N + eo] = x[i];
-      rt[(size_t)REC_A * N + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+        if ((i & 3) == k) rt[(size_t)(REC_X + i) * RB + roff] = x[i];
+      rt[(size_t)REC_A * RB + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
     }
     float u[NA];
 #pragma unroll
