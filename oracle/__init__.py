@@ -48,6 +48,8 @@ class Cfg(ctypes.Structure):
         ("max_episode_steps", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("dr_enable", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("dr_seed", ctypes.c_uint64),
+        ("dist_force", ctypes.c_double), ("dist_torque", ctypes.c_double),
+        ("obs_noise", ctypes.c_double * 4),
     ]
 
 
@@ -56,8 +58,10 @@ def make_cfg(d: dict) -> Cfg:
     for name, typ in Cfg._fields_:
         if name == "pad_":
             continue
-        v = d[name]
-        if name in ("nominal", "dr_lo", "dr_hi"):
+        v = d.get(name, 0.0 if name in ("dist_force", "dist_torque") else None)
+        if name == "obs_noise":
+            setattr(c, name, (ctypes.c_double * 4)(*[float(x) for x in d.get(name, (0, 0, 0, 0))]))
+        elif name in ("nominal", "dr_lo", "dr_hi"):
             setattr(c, name, (ctypes.c_double * NP)(*[float(x) for x in v]))
         else:
             setattr(c, name, v)
@@ -83,17 +87,21 @@ def lib():
         L.orc_reset_state.argtypes = [P(Cfg), ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_hover_rpm.argtypes = [P(Cfg), vp]
         L.orc_hover_rpm.restype = d
-        L.orc_dynamics.argtypes = [P(Cfg), vp, vp, vp, vp]
-        L.orc_rk4.argtypes = [P(Cfg), vp, vp, vp, vp]
+        L.orc_dynamics.argtypes = [P(Cfg), vp, vp, vp, vp, vp]
+        L.orc_rk4.argtypes = [P(Cfg), vp, vp, vp, vp, vp]
         L.orc_observe.argtypes = [vp, vp, vp]
+        L.orc_disturbance.argtypes = [P(Cfg), u32, u32, vp]
+        L.orc_normals18.argtypes = [P(Cfg), u32, u32, i32, vp]
+        L.orc_observe_noisy.argtypes = [P(Cfg), u32, u32, i32, vp, vp, vp]
+        L.orc_critic_obs.argtypes = [P(Cfg), u32, u32, vp, vp]
         L.orc_actor.argtypes = [vp, vp, vp]
         L.orc_rotmat.argtypes = [vp, vp]
         L.orc_reward.argtypes = [P(Cfg), vp, vp]
         L.orc_reward.restype = d
         L.orc_rollout.argtypes = [P(Cfg), ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp,
                                   vp, vp, vp, vp, vp, ctypes.c_int]
-        L.orc_grad.argtypes = [P(Cfg), ctypes.c_int, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp,
-                               ctypes.c_int]
+        L.orc_grad.argtypes = [P(Cfg), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp,
+                               vp, vp, vp, ctypes.c_int]
         L.orc_grad.restype = d
         _lib = L
     return _lib
@@ -195,8 +203,11 @@ class Batch:
         dSd = None if dS is None else _f64(dS)
         gW = np.zeros(NW) if want_grad else None
         gth = np.zeros((n, NP)) if want_grad else None
-        J = lib().orc_grad(ctypes.byref(self.c), n, _p(Wd), _p(self.theta), _p(self.s),
-                           _p(self.H), T, _p(dRd), _p(dSd), _p(gW), _p(gth), nthreads)
+        t0 = np.ascontiguousarray(self.t_ep, np.int32)
+        ep = np.ascontiguousarray(self.ep, np.int32)
+        J = lib().orc_grad(ctypes.byref(self.c), n, _p(self.ids), _p(t0), _p(ep), _p(Wd),
+                           _p(self.theta), _p(self.s), _p(self.H), T, _p(dRd), _p(dSd), _p(gW),
+                           _p(gth), nthreads)
         return J, gW, gth
 
 
@@ -206,18 +217,49 @@ def hover_rpm(cfg: dict, theta) -> float:
     return lib().orc_hover_rpm(ctypes.byref(c), _p(th))
 
 
-def dynamics(cfg: dict, theta, x, u):
+def dynamics(cfg: dict, theta, x, u, dist=None):
+    """f(x, u; theta) with the episode disturbance dist = {f_r, tau_r} (or none)."""
     c = make_cfg(cfg)
     out = np.zeros(NS)
-    lib().orc_dynamics(ctypes.byref(c), _p(_f64(theta)), _p(_f64(x)), _p(_f64(u)), _p(out))
+    d = None if dist is None else _f64(dist)
+    lib().orc_dynamics(ctypes.byref(c), _p(_f64(theta)), _p(_f64(x)), _p(_f64(u)), _p(d), _p(out))
     return out
 
 
-def rk4(cfg: dict, theta, x, u):
+def rk4(cfg: dict, theta, x, u, dist=None):
     c = make_cfg(cfg)
     out = np.zeros(NS)
-    lib().orc_rk4(ctypes.byref(c), _p(_f64(theta)), _p(_f64(x)), _p(_f64(u)), _p(out))
+    d = None if dist is None else _f64(dist)
+    lib().orc_rk4(ctypes.byref(c), _p(_f64(theta)), _p(_f64(x)), _p(_f64(u)), _p(d), _p(out))
     return out
+
+
+def disturbance(cfg: dict, env: int, episode: int):
+    c = make_cfg(cfg)
+    d = np.zeros(6)
+    lib().orc_disturbance(ctypes.byref(c), env, episode, _p(d))
+    return d
+
+
+def normals18(cfg: dict, env: int, episode: int, t_ep: int):
+    c = make_cfg(cfg)
+    z = np.zeros(18)
+    lib().orc_normals18(ctypes.byref(c), env, episode, t_ep, _p(z))
+    return z
+
+
+def observe_noisy(cfg: dict, env: int, episode: int, t_ep: int, s, H):
+    c = make_cfg(cfg)
+    o = np.zeros(NO)
+    lib().orc_observe_noisy(ctypes.byref(c), env, episode, t_ep, _p(_f64(s)), _p(_f64(H)), _p(o))
+    return o
+
+
+def critic_obs(cfg: dict, env: int, episode: int, s):
+    c = make_cfg(cfg)
+    oc = np.zeros(28)
+    lib().orc_critic_obs(ctypes.byref(c), env, episode, _p(_f64(s)), _p(oc))
+    return oc
 
 
 def observe(s, H):

@@ -16,7 +16,11 @@
  *   - actions = RPM setpoints (Sec. IV);
  *   - reward = negative squared cost plus survival constant (Sec. IV, reward
  *     equation);
- *   - termination when leaving a box around the origin (Sec. V, Training).
+ *   - termination when leaving a box around the origin (Sec. V, Training);
+ *   - the training extras of the asymmetric actor-critic paragraph (Sec. IV):
+ *     a random force and torque disturbance drawn per episode, additive noise
+ *     on the actor's observation, and the 28-value critic observation
+ *     {p, R, v, w, w_m, f_r, tau_r}.
  * The integrator is classical 4-stage Runge-Kutta at 100 Hz (Sec. V,
  * Simulation, gives the 100 Hz rate).  Every choice the paper leaves open
  * (constants, rotor layout, reset distribution, RNG) is a stated reading; the
@@ -56,6 +60,8 @@
 #define F_TERMINATE 1
 #define F_AUTORESET 2
 #define F_RENORM_Q 4
+#define F_DISTURB 32
+#define F_OBS_NOISE 64
 
 /* Mirrors the config the Python side builds; own definition, no shared header. */
 typedef struct {
@@ -66,6 +72,8 @@ typedef struct {
   double C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;
   int32_t max_episode_steps, flags, dr_enable, pad_;
   uint64_t seed, dr_seed;
+  double dist_force, dist_torque; /* per-component bounds of the episode disturbance */
+  double obs_noise[4];            /* noise std on p, R entries, v, w of the actor observation */
 } orc_cfg;
 
 /* ------------------------------------------------------------------------- */
@@ -105,7 +113,56 @@ void orc_uniforms(uint64_t seed, uint32_t env, uint32_t episode, uint32_t block,
   uniforms4(seed, env, episode, block, stream, u4);
 }
 
-enum { STREAM_RESET = 0, STREAM_DR = 1 };
+enum { STREAM_RESET = 0, STREAM_DR = 1, STREAM_DIST = 2, STREAM_NOISE = 3 };
+
+/* Episode disturbance (Sec. IV, asymmetric actor-critic paragraph: a random
+ * force and torque drawn at the start of every episode).  Reading: the force
+ * acts in the world frame and the torque in the body frame, each component
+ * uniform in [-F, F] and [-T, T]; the draw is keyed by (env, episode), so it
+ * holds for the whole episode.  d = {f_r, tau_r}; zero with the flag off. */
+static void disturbance(const orc_cfg* c, uint32_t env, uint32_t episode, double d[6]) {
+  if (!(c->flags & F_DISTURB)) {
+    for (int i = 0; i < 6; ++i) d[i] = 0.0;
+    return;
+  }
+  double u[8];
+  uniforms4(c->seed, env, episode, 0, STREAM_DIST, u);
+  uniforms4(c->seed, env, episode, 1, STREAM_DIST, u + 4);
+  for (int i = 0; i < 3; ++i) {
+    d[i] = c->dist_force * (2.0 * u[i] - 1.0);
+    d[3 + i] = c->dist_torque * (2.0 * u[3 + i] - 1.0);
+  }
+}
+
+/* 18 standard normal draws for the observation of step t_ep of an episode:
+ * Box-Muller (Box and Muller, 1958) on consecutive uniform pairs,
+ * z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2). */
+static void normals18(const orc_cfg* c, uint32_t env, uint32_t episode, int32_t t_ep,
+                      double z[18]) {
+  double u[20];
+  for (int b = 0; b < 5; ++b)
+    uniforms4(c->seed, env, episode, (uint32_t)t_ep * 5u + (uint32_t)b, STREAM_NOISE, u + 4 * b);
+  for (int i = 0; i < 9; ++i) {
+    double r = sqrt(-2.0 * log(u[2 * i]));
+    z[2 * i] = r * cos(2.0 * M_PI * u[2 * i + 1]);
+    z[2 * i + 1] = r * sin(2.0 * M_PI * u[2 * i + 1]);
+  }
+}
+
+/* Sensor noise on the actor observation (Sec. IV; the scales are in the
+ * missing parameter sheet, so they are configuration): o_i += sigma_g z_i on
+ * the 18 state features, groups p, R, v, w; the action history is the agent's
+ * own output and stays clean. */
+static void add_obs_noise(const orc_cfg* c, uint32_t env, uint32_t episode, int32_t t_ep,
+                          double o[NO]) {
+  if (!(c->flags & F_OBS_NOISE)) return;
+  double z[18];
+  normals18(c, env, episode, t_ep, z);
+  for (int i = 0; i < 18; ++i) {
+    const int g = i < 3 ? 0 : i < 12 ? 1 : i < 15 ? 2 : 3;
+    o[i] += c->obs_noise[g] * z[i];
+  }
+}
 
 /* ------------------------------------------------------------------------- */
 /* Parameters, hover point, reset distribution                               */
@@ -188,9 +245,10 @@ static void normalize4(const double q[4], double out[4]) {
   for (int i = 0; i < 4; ++i) out[i] = q[i] / n;
 }
 
-/* Time derivative of the 17-state.  u = RPM setpoints held over the step. */
+/* Time derivative of the 17-state.  u = RPM setpoints held over the step;
+ * d = episode disturbance {f_r (world), tau_r (body)} or NULL. */
 static void dynamics(const orc_cfg* c, const double th[NP], const double x[NS], const double u[4],
-                     double dx[NS]) {
+                     const double* d, double dx[NS]) {
   const double m = th[0], J[3] = {th[1], th[2], th[3]}, c0 = th[4], c1 = th[5], c2 = th[6],
                Tm = th[7];
   const double* q = x + 3;
@@ -218,30 +276,31 @@ static void dynamics(const orc_cfg* c, const double th[NP], const double x[NS], 
   dx[4] = 0.5 * (q[0] * w[0] + q[2] * w[2] - q[3] * w[1]);
   dx[5] = 0.5 * (q[0] * w[1] + q[3] * w[0] - q[1] * w[2]);
   dx[6] = 0.5 * (q[0] * w[2] + q[1] * w[1] - q[2] * w[0]);
-  /* linear velocity: rotated body thrust over mass plus gravity (z up) */
-  for (int i = 0; i < 3; ++i) dx[7 + i] = R[3 * i + 2] * F / m;
+  /* linear velocity: rotated body thrust and disturbance force over mass,
+   * plus gravity (z up) */
+  for (int i = 0; i < 3; ++i) dx[7 + i] = (R[3 * i + 2] * F + (d ? d[i] : 0.0)) / m;
   dx[9] -= c->g;
   /* angular velocity: Euler's equation J wdot = tau - w x (J w) */
   double Jw[3] = {J[0] * w[0], J[1] * w[1], J[2] * w[2]};
   double cr[3] = {w[1] * Jw[2] - w[2] * Jw[1], w[2] * Jw[0] - w[0] * Jw[2],
                   w[0] * Jw[1] - w[1] * Jw[0]};
-  for (int i = 0; i < 3; ++i) dx[10 + i] = (tau[i] - cr[i]) / J[i];
+  for (int i = 0; i < 3; ++i) dx[10 + i] = (tau[i] + (d ? d[3 + i] : 0.0) - cr[i]) / J[i];
   /* motors: first-order low-pass towards the setpoint */
   for (int i = 0; i < 4; ++i) dx[13 + i] = (u[i] - wm[i]) / Tm;
 }
 
 /* One classical RK4 step with the setpoint held (zero-order hold). */
 static void rk4(const orc_cfg* c, const double th[NP], const double x[NS], const double u[4],
-                double xn[NS]) {
+                const double* d, double xn[NS]) {
   const double h = c->dt;
   double k1[NS], k2[NS], k3[NS], k4[NS], t[NS];
-  dynamics(c, th, x, u, k1);
+  dynamics(c, th, x, u, d, k1);
   for (int i = 0; i < NS; ++i) t[i] = x[i] + 0.5 * h * k1[i];
-  dynamics(c, th, t, u, k2);
+  dynamics(c, th, t, u, d, k2);
   for (int i = 0; i < NS; ++i) t[i] = x[i] + 0.5 * h * k2[i];
-  dynamics(c, th, t, u, k3);
+  dynamics(c, th, t, u, d, k3);
   for (int i = 0; i < NS; ++i) t[i] = x[i] + h * k3[i];
-  dynamics(c, th, t, u, k4);
+  dynamics(c, th, t, u, d, k4);
   for (int i = 0; i < NS; ++i) xn[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 }
 
@@ -320,15 +379,17 @@ static double reward(const orc_cfg* c, const double s[NS], const double a[NA]) {
 static void env_step(const orc_cfg* c, const double* W, const double* a_ext, const double th[NP],
                      uint32_t env, double s[NS], double H[NH * NA], int32_t* t_ep, int32_t* ep,
                      double* r_out, uint8_t* done_out, double* a_out) {
-  double o[NO], a[NA], u[NA], sn[NS];
+  double o[NO], a[NA], u[NA], sn[NS], d[6];
+  disturbance(c, env, (uint32_t)*ep, d);
   if (a_ext) {
     memcpy(a, a_ext, sizeof a);
   } else {
     observe(s, H, o);
+    add_obs_noise(c, env, (uint32_t)*ep, *t_ep, o);
     actor(W, o, a, NULL, NULL, NULL);
   }
   action_to_rpm(c, a, u);
-  rk4(c, th, s, u, sn);
+  rk4(c, th, s, u, d, sn);
   if (c->flags & F_RENORM_Q) {
     double qn[4];
     normalize4(sn + 3, qn);
@@ -389,15 +450,48 @@ void orc_reset_state(const orc_cfg* c, int n, const uint32_t* ids, const int32_t
               s + (size_t)i * NS, H + (size_t)i * NH * NA);
 }
 
-void orc_dynamics(const orc_cfg* c, const double* th, const double* x, const double* u, double* dx) {
-  dynamics(c, th, x, u, dx);
+void orc_dynamics(const orc_cfg* c, const double* th, const double* x, const double* u,
+                  const double* d, double* dx) {
+  dynamics(c, th, x, u, d, dx);
 }
 
-void orc_rk4(const orc_cfg* c, const double* th, const double* x, const double* u, double* xn) {
-  rk4(c, th, x, u, xn);
+void orc_rk4(const orc_cfg* c, const double* th, const double* x, const double* u,
+             const double* d, double* xn) {
+  rk4(c, th, x, u, d, xn);
 }
 
 void orc_observe(const double* s, const double* H, double* o) { observe(s, H, o); }
+
+void orc_disturbance(const orc_cfg* c, uint32_t env, uint32_t episode, double* d) {
+  disturbance(c, env, episode, d);
+}
+
+void orc_normals18(const orc_cfg* c, uint32_t env, uint32_t episode, int32_t t_ep, double* z) {
+  normals18(c, env, episode, t_ep, z);
+}
+
+/* Actor observation of an env at step t_ep of its episode: o with noise. */
+void orc_observe_noisy(const orc_cfg* c, uint32_t env, uint32_t episode, int32_t t_ep,
+                       const double* s, const double* H, double* o) {
+  observe(s, H, o);
+  add_obs_noise(c, env, episode, t_ep, o);
+}
+
+/* Critic observation (Sec. IV): {p, R(q) row-major, v, w, w_m, f_r, tau_r},
+ * 3 + 9 + 3 + 3 + 4 + 3 + 3 = 28, ground truth (no noise). */
+void orc_critic_obs(const orc_cfg* c, uint32_t env, uint32_t episode, const double* s,
+                    double* oc) {
+  double qn[4], R[9], d[6];
+  normalize4(s + 3, qn);
+  rotmat(qn, R);
+  disturbance(c, env, episode, d);
+  for (int i = 0; i < 3; ++i) oc[i] = s[i];
+  for (int i = 0; i < 9; ++i) oc[3 + i] = R[i];
+  for (int i = 0; i < 3; ++i) oc[12 + i] = s[7 + i];
+  for (int i = 0; i < 3; ++i) oc[15 + i] = s[10 + i];
+  for (int i = 0; i < 4; ++i) oc[18 + i] = s[13 + i];
+  for (int i = 0; i < 6; ++i) oc[22 + i] = d[i];
+}
 
 void orc_actor(const double* W, const double* o, double* a) { actor(W, o, a, NULL, NULL, NULL); }
 
@@ -498,8 +592,8 @@ static void rotmat_vjp(const double qn[4], const double G[9], double gqn[4]) {
 /* VJP of f at (x, u, theta) with cotangent gd (17): accumulates into gx (17),
  * gu (4) and gth (8). */
 static void dynamics_vjp(const orc_cfg* c, const double th[NP], const double x[NS],
-                         const double u[4], const double gd[NS], double gx[NS], double gu[4],
-                         double gth[NP]) {
+                         const double u[4], const double* d, const double gd[NS], double gx[NS],
+                         double gu[4], double gth[NP]) {
   const double m = th[0], J[3] = {th[1], th[2], th[3]}, c0 = th[4], c1 = th[5], c2 = th[6],
                Tm = th[7];
   const double* q = x + 3;
@@ -535,7 +629,7 @@ static void dynamics_vjp(const orc_cfg* c, const double th[NP], const double x[N
   for (int i = 0; i < 3; ++i) {
     G[3 * i + 2] = gv[i] * F / m;
     gF += gv[i] * R[3 * i + 2] / m;
-    gth[0] += -gv[i] * R[3 * i + 2] * F / (m * m);
+    gth[0] += -gv[i] * (R[3 * i + 2] * F + (d ? d[i] : 0.0)) / (m * m);
   }
   double gqn[4];
   rotmat_vjp(qn, G, gqn);
@@ -558,7 +652,7 @@ static void dynamics_vjp(const orc_cfg* c, const double th[NP], const double x[N
   for (int i = 0; i < 3; ++i) {
     hq[i] = gw[i] / J[i];
     gtau[i] = hq[i];
-    gth[1 + i] += -gw[i] * (tau[i] - cr[i]) / (J[i] * J[i]);
+    gth[1 + i] += -gw[i] * (tau[i] + (d ? d[3 + i] : 0.0) - cr[i]) / (J[i] * J[i]);
   }
   /* cr_x = (Jz - Jy) wy wz, cr_y = (Jx - Jz) wz wx, cr_z = (Jy - Jx) wx wy */
   gx[11] += -hq[0] * (J[2] - J[1]) * w[2];
@@ -597,14 +691,15 @@ static void dynamics_vjp(const orc_cfg* c, const double th[NP], const double x[N
 
 /* VJP of one RK4 step: cotangent g of x_next -> gx, gu, gth (accumulated). */
 static void rk4_vjp(const orc_cfg* c, const double th[NP], const double x[NS], const double u[4],
-                    const double g[NS], double gx[NS], double gu[4], double gth[NP]) {
+                    const double* d, const double g[NS], double gx[NS], double gu[4],
+                    double gth[NP]) {
   const double h = c->dt;
   double k1[NS], k2[NS], k3[NS], x2[NS], x3[NS], x4[NS];
-  dynamics(c, th, x, u, k1);
+  dynamics(c, th, x, u, d, k1);
   for (int i = 0; i < NS; ++i) x2[i] = x[i] + 0.5 * h * k1[i];
-  dynamics(c, th, x2, u, k2);
+  dynamics(c, th, x2, u, d, k2);
   for (int i = 0; i < NS; ++i) x3[i] = x[i] + 0.5 * h * k2[i];
-  dynamics(c, th, x3, u, k3);
+  dynamics(c, th, x3, u, d, k3);
   for (int i = 0; i < NS; ++i) x4[i] = x[i] + h * k3[i];
 
   double gk1[NS], gk2[NS], gk3[NS], gk4[NS], gx2[NS], gx3[NS], gx4[NS];
@@ -616,22 +711,22 @@ static void rk4_vjp(const orc_cfg* c, const double th[NP], const double x[NS], c
     gk4[i] = h / 6.0 * g[i];
     gx2[i] = gx3[i] = gx4[i] = 0.0;
   }
-  dynamics_vjp(c, th, x4, u, gk4, gx4, gu, gth);
+  dynamics_vjp(c, th, x4, u, d, gk4, gx4, gu, gth);
   for (int i = 0; i < NS; ++i) {
     gx[i] += gx4[i];
     gk3[i] += h * gx4[i];
   }
-  dynamics_vjp(c, th, x3, u, gk3, gx3, gu, gth);
+  dynamics_vjp(c, th, x3, u, d, gk3, gx3, gu, gth);
   for (int i = 0; i < NS; ++i) {
     gx[i] += gx3[i];
     gk2[i] += 0.5 * h * gx3[i];
   }
-  dynamics_vjp(c, th, x2, u, gk2, gx2, gu, gth);
+  dynamics_vjp(c, th, x2, u, d, gk2, gx2, gu, gth);
   for (int i = 0; i < NS; ++i) {
     gx[i] += gx2[i];
     gk1[i] += 0.5 * h * gx2[i];
   }
-  dynamics_vjp(c, th, x, u, gk1, gx, gu, gth);
+  dynamics_vjp(c, th, x, u, d, gk1, gx, gu, gth);
 }
 
 /* VJP of the actor at o with cotangent ga of a: accumulates gW, returns go. */
@@ -701,9 +796,12 @@ static void reward_vjp(const orc_cfg* c, const double s[NS], const double a[NA],
  * termination or reset.  Loss J = sum_t dR[t] r_t + sum_{t=0..T} dS[t].s_t.
  * Returns J; if gW / gth are non-NULL, accumulates dJ/dW (13828) into gW and
  * writes dJ/dtheta (8) to gth, holding (s0, H0) fixed. */
-static double env_grad(const orc_cfg* c, const double* W, const double th[NP], const double s0[NS],
+static double env_grad(const orc_cfg* c, const double* W, const double th[NP], uint32_t env,
+                       uint32_t episode, int32_t t_ep0, const double s0[NS],
                        const double H0[NH * NA], int T, const double* dR, size_t dR_stride,
                        const double* dS, size_t dS_stride, double* gW, double* gth) {
+  double d[6];
+  disturbance(c, env, episode, d);
   double* S = (double*)malloc(sizeof(double) * (size_t)(T + 1) * NS);
   double* Hs = (double*)malloc(sizeof(double) * (size_t)(T + 1) * NH * NA);
   double* A = (double*)malloc(sizeof(double) * (size_t)T * NA);
@@ -720,9 +818,10 @@ static double env_grad(const orc_cfg* c, const double* W, const double th[NP], c
     double o[NO], u[NA];
     double* a = A + (size_t)t * NA;
     observe(s, H, o);
+    add_obs_noise(c, env, episode, t_ep0 + t, o);
     actor(W, o, a, NULL, NULL, NULL);
     action_to_rpm(c, a, u);
-    rk4(c, th, s, u, sn);
+    rk4(c, th, s, u, d, sn);
     if (c->flags & F_RENORM_Q) {
       double qn[4];
       normalize4(sn + 3, qn);
@@ -763,16 +862,17 @@ static double env_grad(const orc_cfg* c, const double* W, const double th[NP], c
       action_to_rpm(c, a, u);
       memcpy(graw, gsn, sizeof graw);
       if (c->flags & F_RENORM_Q) {
-        rk4(c, th, s, u, xr);
+        rk4(c, th, s, u, d, xr);
         double gq[4] = {0, 0, 0, 0};
         normalize4_vjp(xr + 3, gsn + 3, gq);
         memcpy(graw + 3, gq, sizeof gq);
       }
       for (int i = 0; i < NS; ++i) gs[i] = 0.0;
-      rk4_vjp(c, th, s, u, graw, gs, gu, gth_loc);
+      rk4_vjp(c, th, s, u, d, graw, gs, gu, gth_loc);
       for (int i = 0; i < NA; ++i) ga[i] += gu[i] * 0.5 * (c->rpm_max - c->rpm_min);
       double o[NO];
       observe(s, H, o);
+      add_obs_noise(c, env, episode, t_ep0 + t, o);  /* additive: the VJP to s is unchanged */
       actor_vjp(W, o, ga, gW_loc, go);
       for (int i = 0; i < NH * NA; ++i) gH[i] = 0.0;
       observe_vjp(s, go, gs, gH);
@@ -793,6 +893,8 @@ static double env_grad(const orc_cfg* c, const double* W, const double th[NP], c
 typedef struct {
   const orc_cfg* c;
   const double *W, *theta, *s0, *H0, *dR, *dS;
+  const uint32_t* ids;
+  const int32_t *t_ep0, *ep;
   int n, T, i0, i1, want_grad;
   double *gW_part, *gth, *J_part;
 } grad_job;
@@ -803,7 +905,9 @@ static void* grad_worker(void* arg) {
   for (int i = j->i0; i < j->i1; ++i) {
     const double* dR = j->dR ? j->dR + i : NULL;
     const double* dS = j->dS ? j->dS + (size_t)i * NS : NULL;
-    Jsum += env_grad(j->c, j->W, j->theta + (size_t)i * NP, j->s0 + (size_t)i * NS,
+    Jsum += env_grad(j->c, j->W, j->theta + (size_t)i * NP, env_id(j->ids, i),
+                     j->ep ? (uint32_t)j->ep[i] : 0u, j->t_ep0 ? j->t_ep0[i] : 0,
+                     j->s0 + (size_t)i * NS,
                      j->H0 + (size_t)i * NH * NA, j->T, dR, (size_t)j->n, dS, (size_t)j->n * NS,
                      j->want_grad ? j->gW_part : NULL,
                      j->want_grad ? j->gth + (size_t)i * NP : NULL);
@@ -814,9 +918,12 @@ static void* grad_worker(void* arg) {
 
 /* Batched loss and gradient.  dR: [T][n] (NULL = all ones); dS: [T+1][n][17]
  * (NULL = zeros).  gW (13828) receives the sum over envs; gth: [n][8]. Either
- * may be NULL only together (loss only).  Returns J.  Thread partial sums of
+ * may be NULL only together (loss only).  ids, t_ep0, ep: env ids, step within
+ * the episode and episode at the start (NULL = i, 0, 0), which key the
+ * disturbance and the observation noise.  Returns J.  Thread partial sums of
  * gW are added in thread order, so results do not depend on scheduling. */
-double orc_grad(const orc_cfg* c, int n, const double* W, const double* theta, const double* s0,
+double orc_grad(const orc_cfg* c, int n, const uint32_t* ids, const int32_t* t_ep0,
+                const int32_t* ep, const double* W, const double* theta, const double* s0,
                 const double* H0, int T, const double* dR, const double* dS, double* gW,
                 double* gth, int nthreads) {
   if (nthreads < 1) nthreads = 1;
@@ -828,7 +935,7 @@ double orc_grad(const orc_cfg* c, int n, const double* W, const double* theta, c
   double Jp[256];
   double* parts = want ? (double*)calloc((size_t)nthreads * NW, sizeof(double)) : NULL;
   for (int k = 0; k < nthreads; ++k) {
-    grad_job j = {c, W, theta, s0, H0, dR, dS, n, T, (int)((long)n * k / nthreads),
+    grad_job j = {c, W, theta, s0, H0, dR, dS, ids, t_ep0, ep, n, T, (int)((long)n * k / nthreads),
                   (int)((long)n * (k + 1) / nthreads), want,
                   want ? parts + (size_t)k * NW : NULL, gth, &Jp[k]};
     jobs[k] = j;

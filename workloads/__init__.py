@@ -33,6 +33,8 @@ F_AUTORESET = 2
 F_RENORM_Q = 4
 F_FP64 = 8
 F_ACTOR_BF16 = 16
+F_DISTURB = 32
+F_OBS_NOISE = 64
 
 PARAM_NAMES = ("m", "Jxx", "Jyy", "Jzz", "c0", "c1", "c2", "Tm")
 
@@ -79,12 +81,34 @@ def crazyflie_config(**overrides) -> dict:
         n_envs=64,
         max_tape_horizon=0,
         ckpt_every=16,
+        # training extras (active only under F_DISTURB / F_OBS_NOISE)
+        dist_force=0.0,
+        dist_torque=0.0,
+        obs_noise=(0.0, 0.0, 0.0, 0.0),
     )
     for k, v in overrides.items():
         if k not in cfg:
             raise KeyError(f"unknown config key {k!r}")
         cfg[k] = v
     return cfg
+
+
+def training_extras(cfg: dict) -> dict:
+    """The training MDP of the paper's asymmetric actor-critic setup on top of
+    cfg: per-episode force/torque disturbances and actor observation noise.
+    The paper's magnitudes are in its missing parameter sheet; these readings
+    are small next to the vehicle's own authority: a force bound of 5 % of the
+    nominal weight per axis (0.0132 N), a torque bound of 1 % of the maximal
+    roll torque arm * T_max (4.2e-5 N m), and noise std 1 mm, 0.01 (rotation
+    entries), 2 cm/s and 0.05 rad/s."""
+    out = dict(cfg)
+    m = cfg["nominal"][0]
+    t_max = cfg["nominal"][6] * cfg["rpm_max"] ** 2
+    out["flags"] = cfg["flags"] | F_DISTURB | F_OBS_NOISE
+    out["dist_force"] = 0.05 * m * cfg["g"]
+    out["dist_torque"] = 0.01 * cfg["arm"] * t_max
+    out["obs_noise"] = (0.001, 0.01, 0.02, 0.05)
+    return out
 
 
 # The five workloads: a small parity case, the plain-vs-fused comparison, the
