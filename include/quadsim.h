@@ -76,7 +76,7 @@ enum {
                            such a handle records no tape; float32 interfaces
                            (states, snapshots, parameters) round on output and
                            widen on input.  Fixed at creation.                  */
-  SIM_F_ACTOR_BF16 = 16 /* actor layers on bf16 matrix cores: weights and layer
+  SIM_F_ACTOR_BF16 = 16, /* actor layers on bf16 matrix cores: weights and layer
                            inputs rounded to bf16 (nearest even), fp32
                            accumulation, biases and activations; the dynamics
                            stay fp32.  Policy steps and rollouts then run on
@@ -88,6 +88,19 @@ enum {
                            at creation.  (A precision option, not the
                            reference arithmetic: the FP64 oracle stays the
                            reference, and the error against it is larger.)   */
+  SIM_F_DISTURB = 32,   /* per-episode disturbance (Sec. IV, asymmetric
+                           actor-critic paragraph): a force in the world frame
+                           and a torque in the body frame, each component
+                           uniform in [-dist_force, dist_force] and
+                           [-dist_torque, dist_torque], drawn at every reset
+                           from the reset seed and the (env, episode) counter
+                           and held for the episode.                          */
+  SIM_F_OBS_NOISE = 64  /* additive Gaussian noise on the actor's observation
+                           (Sec. IV): the 18 state features p, R, v, w get
+                           obs_noise[0..3] times a standard normal drawn per
+                           (env, episode, step); the action history and the
+                           critic observation stay clean.  Noise is additive,
+                           so gradients to the state are unchanged.           */
 };
 
 /* Execution variants of the forward step. */
@@ -116,8 +129,11 @@ typedef struct sim_config {
   double pos_limit, vel_limit;  /* termination box (per axis)                          */
   double init_pos, init_angle, init_vel, init_angvel; /* reset ranges                  */
   double C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;   /* reward constants              */
-  uint64_t seed;             /* reset-state seed                                     */
+  uint64_t seed;             /* reset-state seed (also keys disturbances and noise)  */
   uint64_t dr_seed;          /* domain-randomisation seed                            */
+  double dist_force;         /* N, bound per component (SIM_F_DISTURB)               */
+  double dist_torque;        /* N m, bound per component (SIM_F_DISTURB)             */
+  double obs_noise[4];       /* noise std on p (m), R entries, v (m/s), w (rad/s)    */
 } sim_config;
 
 typedef struct sim_handle sim_handle;
@@ -154,6 +170,15 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
  * SIM_E_STATE / SIM_E_INVAL. */
 int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
                 float* states, int32_t record_tape, void* stream);
+
+/* Observations of the current state, for a caller that runs its own policy
+ * or critic (Sec. IV, asymmetric actor-critic): actor_obs dev [146][N] = {p,
+ * R(q) row-major, v, w, action history oldest first}, with the noise of the
+ * coming step under SIM_F_OBS_NOISE (exactly what the next policy step
+ * feeds the actor); critic_obs dev [28][N] = {p, R, v, w, rotor speeds, f_r,
+ * tau_r}, ground truth.  Either may be NULL.  Not available on SIM_F_FP64
+ * handles. */
+int sim_observe(sim_handle* h, float* actor_obs, float* critic_obs, void* stream);
 
 /* Dynamics-only rollout: T >= 1 steps with the policy replaced by given
  * normalised actions -- the simulator alone, as in the throughput experiment

@@ -18,13 +18,14 @@ SIM_NSTATE, SIM_NHIST, SIM_NACT, SIM_NOBS, SIM_NHID, SIM_NPARAM, SIM_NACTOR = (
     17, 32, 4, 146, 64, 8, 13828)
 SIM_OK, SIM_E_INVAL, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE, SIM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SIM_F_TERMINATE, SIM_F_AUTORESET, SIM_F_RENORM_Q, SIM_F_FP64, SIM_F_ACTOR_BF16 = 1, 2, 4, 8, 16
+SIM_F_DISTURB, SIM_F_OBS_NOISE = 32, 64
 SIM_V_AUTO, SIM_V_PLAIN, SIM_V_FUSED_VALU, SIM_V_FUSED_MFMA, SIM_V_FUSED_MFMA4 = 0, 1, 2, 3, 4
 
 EXPORTS = (
     "sim_create", "sim_destroy", "sim_reset", "sim_step", "sim_rollout", "sim_backward",
     "sim_get_state", "sim_set_state", "sim_get_params", "sim_set_params", "sim_set_variant",
     "sim_get_variant", "sim_autotune", "sim_last_rollout_timing", "sim_n_envs", "sim_last_error",
-    "sim_rollout_actions",
+    "sim_rollout_actions", "sim_observe",
 )
 
 
@@ -45,6 +46,8 @@ class SimConfig(ctypes.Structure):
         ("C_rw", ctypes.c_double), ("C_ra", ctypes.c_double), ("C_rab", ctypes.c_double),
         ("C_rs", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("dr_seed", ctypes.c_uint64),
+        ("dist_force", ctypes.c_double), ("dist_torque", ctypes.c_double),
+        ("obs_noise", ctypes.c_double * 4),
     ]
 
 
@@ -53,7 +56,10 @@ def make_config(d: dict) -> SimConfig:
     for name, _ in SimConfig._fields_:
         if name.startswith("reserved"):
             continue
-        v = d[name]
+        if name == "obs_noise":
+            setattr(c, name, (ctypes.c_double * 4)(*[float(x) for x in d.get(name, (0,) * 4)]))
+            continue
+        v = d.get(name, 0.0) if name in ("dist_force", "dist_torque") else d[name]
         if name in ("nominal", "dr_lo", "dr_hi"):
             setattr(c, name, (ctypes.c_double * 8)(*[float(x) for x in v]))
         else:
@@ -86,6 +92,7 @@ def load(path: str | None = None):
         "sim_rollout": ([H, vp, i32, vp, vp, vp, i32, vp], ctypes.c_int),
         "sim_backward": ([H, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_rollout_actions": ([H, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
+        "sim_observe": ([H, vp, vp, vp], ctypes.c_int),
         "sim_get_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_set_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_get_params": ([H, vp, vp], ctypes.c_int),

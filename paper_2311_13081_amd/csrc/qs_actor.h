@@ -81,9 +81,7 @@ __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
 //           rows.
 //  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
-                                  const float H[NH * NA], float z3out[NA],
-                                  float* __restrict__ rz1 = nullptr,
-                                  float* __restrict__ rz2 = nullptr, int N = 0, int env0 = 0) {
+                                  const float H[NH * NA], float z3out[NA]) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   f16 acc1[4];
@@ -107,17 +105,6 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
           acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], x, acc1[n], 0, 0, 0);
       }
     }
-  }
-  // Optional record of the layer-1 pre-activations: register r of tile n holds
-  // neuron 16n + 4lg + (r&3) of env env0 + 16(r>>2) + li.
-  if (rz1) {
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int env = env0 + 16 * (r >> 2) + li;
-        if (env < N) rz1[(size_t)(16 * n + 4 * lg + (r & 3)) * N + env] = acc1[n][r];
-      }
   }
 #pragma unroll
   for (int n = 0; n < 4; ++n)
@@ -144,17 +131,6 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
           acc2[n2][bb] =
               __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][4 * bb + v], acc2[n2][bb], 0, 0, 0);
     }
-  if (rz2) {
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int env = env0 + 16 * bb + li;
-          if (env < N) rz2[(size_t)(16 * n2 + 4 * lg + r) * N + env] = acc2[n2][bb][r];
-        }
-  }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll

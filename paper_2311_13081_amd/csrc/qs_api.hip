@@ -63,7 +63,10 @@ struct GraphKey {
 
 }  // namespace
 
-static_assert(SIM_F_ACTOR_BF16 == 16, "flag value is read by the quarter-lane kernel");
+static_assert(SIM_F_ACTOR_BF16 == F_ACTOR_BF16 && SIM_F_DISTURB == F_DISTURB &&
+                  SIM_F_OBS_NOISE == F_OBS_NOISE && SIM_F_TERMINATE == F_TERMINATE &&
+                  SIM_F_AUTORESET == F_AUTORESET && SIM_F_RENORM_Q == F_RENORM_Q,
+              "public flag values are read by the kernels");
 
 struct sim_handle {
   sim_config cfg{};
@@ -98,9 +101,15 @@ int check_config(const sim_config* c) {
   if (!c) return fail(SIM_E_INVAL, "config is NULL");
   if (c->n_envs < 1 || c->n_envs > (1 << 24)) return fail(SIM_E_INVAL, "n_envs %d out of range", c->n_envs);
   if (c->max_episode_steps < 0) return fail(SIM_E_INVAL, "max_episode_steps < 0");
-  if (c->flags &
-      ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q | SIM_F_FP64 | SIM_F_ACTOR_BF16))
+  if (c->flags & ~(SIM_F_TERMINATE | SIM_F_AUTORESET | SIM_F_RENORM_Q | SIM_F_FP64 |
+                   SIM_F_ACTOR_BF16 | SIM_F_DISTURB | SIM_F_OBS_NOISE))
     return fail(SIM_E_INVAL, "unknown flags 0x%x", c->flags);
+  if (!(c->dist_force >= 0) || !(c->dist_torque >= 0) || !std::isfinite(c->dist_force) ||
+      !std::isfinite(c->dist_torque))
+    return fail(SIM_E_INVAL, "disturbance bounds must be finite and >= 0");
+  for (int i = 0; i < 4; ++i)
+    if (!(c->obs_noise[i] >= 0) || !std::isfinite(c->obs_noise[i]))
+      return fail(SIM_E_INVAL, "observation noise std must be finite and >= 0");
   if ((c->flags & SIM_F_FP64) && (c->flags & SIM_F_ACTOR_BF16))
     return fail(SIM_E_INVAL, "SIM_F_FP64 and SIM_F_ACTOR_BF16 exclude each other");
   if ((c->flags & SIM_F_FP64) && c->max_tape_horizon > 0)
@@ -166,6 +175,9 @@ DevCfg make_devcfg(const sim_config& c, uint64_t seed) {
   d.seed_hi = (uint32_t)(seed >> 32);
   d.dr_seed_lo = (uint32_t)c.dr_seed;
   d.dr_seed_hi = (uint32_t)(c.dr_seed >> 32);
+  d.dist_force = (float)c.dist_force;
+  d.dist_torque = (float)c.dist_torque;
+  for (int i = 0; i < 4; ++i) d.noise[i] = (float)c.obs_noise[i];
   return d;
 }
 
@@ -203,6 +215,9 @@ PreciseCfg make_precise(const sim_config& c, uint64_t seed) {
   p.seed_hi = (uint32_t)(seed >> 32);
   p.dr_seed_lo = (uint32_t)c.dr_seed;
   p.dr_seed_hi = (uint32_t)(c.dr_seed >> 32);
+  p.dist_force = c.dist_force;
+  p.dist_torque = c.dist_torque;
+  for (int i = 0; i < 4; ++i) p.noise[i] = c.obs_noise[i];
   return p;
 }
 
@@ -238,10 +253,6 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
   if (variant == SIM_V_PLAIN) {
     if (states) HIP_TRY(launch_copy_state(h->b, N, states, st));
     for (int t = 0; t < T; ++t) {
-      if (tape && t % K == 0) {
-        float* ck = tape + (size_t)(t / K) * (NS + NH * NA) * N;
-        HIP_TRY(launch_get_state(h->b, N, ck, ck + (size_t)NS * N, nullptr, nullptr, st));
-      }
       HIP_TRY(launch_plain_step(h->dc, h->b, h->p, W, nullptr, rew ? rew + (size_t)t * N : nullptr,
                                 done ? done + (size_t)t * N : nullptr,
                                 states ? states + (size_t)(t + 1) * NS * N : nullptr, st));
@@ -256,7 +267,7 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
         HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
                               st));
       else
-        HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, tape, K, st));
+        HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
     }
   }
@@ -337,7 +348,7 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   rc = rc ? rc : alloc((void**)&h->p.act, N * NA * 4);
   if (!rc && cfg->max_tape_horizon > 0) {
     h->tape_ckpts = (cfg->max_tape_horizon + cfg->ckpt_every - 1) / cfg->ckpt_every + 1;
-    rc = alloc((void**)&h->tape, (size_t)h->tape_ckpts * (NS + NH * NA) * N * 4);
+    rc = alloc((void**)&h->tape, (size_t)h->tape_ckpts * CK_F * N * 4);
     if (!rc) rc = bwd_alloc(h->bw, h->N, cfg->ckpt_every, cfg->max_tape_horizon) == hipSuccess
                       ? SIM_OK
                       : fail(SIM_E_NOMEM, "backward scratch allocation failed");
@@ -420,7 +431,7 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
     // external actions run on the one-env-per-lane kernel (it has the
     // action-input path); both kernels share the state layout
     HIP_TRY(launch_fused(v != SIM_V_FUSED_VALU, h->dc, h->b, actor, actor ? nullptr : actions, 1,
-                         0, reward, done, nullptr, nullptr, h->cfg.ckpt_every, st));
+                         0, reward, done, nullptr, st));
   }
   return SIM_OK;
 }
@@ -500,6 +511,17 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   h->last_launches = launches;
   h->timing_valid = true;
   if (record_tape) h->tape_T = T;
+  return SIM_OK;
+}
+
+int sim_observe(sim_handle* h, float* actor_obs, float* critic_obs, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (h->fp64) return fail(SIM_E_UNSUPPORTED, "not available on SIM_F_FP64 handles");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  if (!actor_obs && !critic_obs) return SIM_OK;
+  HIP_TRY(launch_observe(h->dc, h->b, actor_obs, critic_obs, (hipStream_t)stream));
   return SIM_OK;
 }
 

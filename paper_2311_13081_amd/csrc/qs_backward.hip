@@ -121,7 +121,8 @@ __device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __res
 
 __global__ void __launch_bounds__(256)
 k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict__ W,
-              const float* __restrict__ rec, int n, int t0, const float* __restrict__ d_rewards,
+              const float* __restrict__ ck, const float* __restrict__ rec, int n, int t0,
+              const float* __restrict__ d_rewards,
               const float* __restrict__ d_states, float* __restrict__ lam,
               float* __restrict__ gth_io, float* __restrict__ dz) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
@@ -138,7 +139,13 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   float th[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) th[i] = theta[(size_t)i * N + e];
-  const Body<float> B = make_body<float>(th);
+  Body<float> B = make_body<float>(th);
+  {
+    // the episode disturbance of the segment (no resets in a taped rollout)
+    float d[6];
+    disturbance(c, (uint32_t)e, (uint32_t)__float_as_int(ck[(size_t)CK_EP * N + e]), d);
+    set_disturbance(B, d);
+  }
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
   const float h = c.dt;
 
@@ -680,13 +687,14 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
     const int n = (T - t0) < K ? (T - t0) : K;
     const int buf = idx % BWD_NBUF;
     if (overlap && idx >= BWD_NBUF) BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_dw[buf], 0));
-    BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * LAM_F * N, bw.seg[buf], s_rec));
+    BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * CK_F * N, bw.seg[buf], s_rec));
     if (overlap) {
       BWD_TRY(hipEventRecord(bw.e_rec[buf], s_rec));
       BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
     }
     hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 64)), dim3(256), R_TOTAL * 4, st, c, b.theta, W,
-                       bw.seg[buf], n, t0, d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf]);
+                       tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0, d_rewards, d_states,
+                       bw.lam, bw.gth, bw.dz[buf]);
     BWD_TRY(hipGetLastError());
     if (overlap) {
       BWD_TRY(hipEventRecord(bw.e_rev[buf], st));

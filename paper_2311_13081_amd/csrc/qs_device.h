@@ -11,8 +11,9 @@ namespace qs {
 constexpr int NS = 17, NH = 32, NA = 4, NO = 146, NHID = 64, NP = 8, NW = 13828;
 constexpr int OFF_W1 = 0, OFF_B1 = NHID * NO, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
               OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NA * NHID;
-constexpr int F_TERMINATE = 1, F_AUTORESET = 2, F_RENORM_Q = 4, F_ACTOR_BF16 = 16;
-constexpr uint32_t STREAM_RESET = 0, STREAM_DR = 1;
+constexpr int F_TERMINATE = 1, F_AUTORESET = 2, F_RENORM_Q = 4, F_ACTOR_BF16 = 16,
+              F_DISTURB = 32, F_OBS_NOISE = 64;
+constexpr uint32_t STREAM_RESET = 0, STREAM_DR = 1, STREAM_DIST = 2, STREAM_NOISE = 3;
 
 // Everything a kernel needs from the configuration, in single precision,
 // passed by value.
@@ -23,6 +24,8 @@ struct DevCfg {
   float C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;
   float nominal[NP], dr_lo[NP], dr_hi[NP];
   uint32_t seed_lo, seed_hi, dr_seed_lo, dr_seed_hi;
+  float dist_force, dist_torque;  // per-component bounds of the episode disturbance
+  float noise[4];                 // observation noise std: p, R entries, v, w
 };
 
 // Device state of the batch, struct-of-arrays, N = n_envs.
@@ -86,6 +89,49 @@ __device__ inline float rpm_to_action(const DevCfg& c, float w) {
   return (w - c.rpm_min) / c.rpm_half_range - 1.0f;
 }
 
+// Episode disturbance {f_r (world frame), tau_r (body frame)} of (env,
+// episode): each component uniform in [-F, F] resp. [-T, T], held for the
+// episode (Sec. IV, asymmetric actor-critic paragraph); zero with the flag off.
+__device__ inline void disturbance(const DevCfg& c, uint32_t env, uint32_t episode, float d[6]) {
+  if (!(c.flags & F_DISTURB)) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d[i] = 0.0f;
+    return;
+  }
+  float u[8];
+  uniforms4(c.seed_lo, c.seed_hi, env, episode, 0, STREAM_DIST, u);
+  uniforms4(c.seed_lo, c.seed_hi, env, episode, 1, STREAM_DIST, u + 4);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    d[i] = c.dist_force * (2.0f * u[i] - 1.0f);
+    d[3 + i] = c.dist_torque * (2.0f * u[3 + i] - 1.0f);
+  }
+}
+
+// Adds the actor's observation noise to the 18 state features f (p, R
+// row-major, v, w) of step t_ep of an episode: f_i += sigma_g z_i, z standard
+// normal by Box-Muller on consecutive uniform pairs of stream STREAM_NOISE,
+// blocks 5 t_ep .. 5 t_ep + 4.  No-op with the flag off.
+__device__ inline void add_obs_noise(const DevCfg& c, uint32_t env, uint32_t episode, int t_ep,
+                                     float f[18]) {
+  if (!(c.flags & F_OBS_NOISE)) return;
+  float u[20];
+#pragma unroll
+  for (int bk = 0; bk < 5; ++bk)
+    uniforms4(c.seed_lo, c.seed_hi, env, episode, (uint32_t)t_ep * 5u + (uint32_t)bk,
+              STREAM_NOISE, u + 4 * bk);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float r = sqrtf(-2.0f * logf(u[2 * i]));
+    float sn, cs;
+    sincosf(6.283185307179586f * u[2 * i + 1], &sn, &cs);
+    const int g0 = (2 * i) < 3 ? 0 : (2 * i) < 12 ? 1 : (2 * i) < 15 ? 2 : 3;
+    const int g1 = (2 * i + 1) < 3 ? 0 : (2 * i + 1) < 12 ? 1 : (2 * i + 1) < 15 ? 2 : 3;
+    f[2 * i] += c.noise[g0] * r * cs;
+    f[2 * i + 1] += c.noise[g1] * r * sn;
+  }
+}
+
 // Episode-start state for (env, episode): p, attitude (angle about a uniform
 // axis), v, w uniform in their ranges, rotors at hover.  Returns the hover
 // action used to fill the history.
@@ -126,6 +172,8 @@ __device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t epis
 template <typename R>
 struct Body {
   R inv_m, Jx, Jy, Jz, inv_Jx, inv_Jy, inv_Jz, c0, c1, c2, inv_Tm;
+  R ax, ay, az;     // episode disturbance force over mass (world frame)
+  R dtx, dty, dtz;  // episode disturbance torque (body frame)
 };
 
 template <typename R>
@@ -142,14 +190,29 @@ __device__ inline Body<R> make_body(const float th[NP]) {
   b.c1 = R(th[5]);
   b.c2 = R(th[6]);
   b.inv_Tm = R(1) / R(th[7]);
+  b.ax = b.ay = b.az = R(0);
+  b.dtx = b.dty = b.dtz = R(0);
   return b;
+}
+
+// Sets the episode disturbance d = {f_r, tau_r} of a body.
+template <typename R>
+__device__ inline void set_disturbance(Body<R>& b, const float d[6]) {
+  b.ax = R(d[0]) * b.inv_m;
+  b.ay = R(d[1]) * b.inv_m;
+  b.az = R(d[2]) * b.inv_m;
+  b.dtx = R(d[3]);
+  b.dty = R(d[4]);
+  b.dtz = R(d[5]);
 }
 
 __device__ inline float rsqrt_r(float x) { return __frsqrt_rn(x); }
 __device__ inline double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 
-// dx = f(x, u) for the 17-state (Newton-Euler with motor lag, z up).
-template <typename R>
+// dx = f(x, u) for the 17-state (Newton-Euler with motor lag, z up).  DIST:
+// include the body's episode disturbance (compile-time, so kernels without
+// the training extras carry no extra arithmetic).
+template <typename R, bool DIST = true>
 __device__ inline void deriv(const Body<R>& B, R arm, R km, R g, const R x[NS], const R u[4],
                              R dx[NS]) {
   const R w0 = x[13], w1 = x[14], w2 = x[15], w3 = x[16];
@@ -173,13 +236,22 @@ __device__ inline void deriv(const Body<R>& B, R arm, R km, R g, const R x[NS], 
   dx[4] = R(0.5) * (qw * ox + qy * oz - qz * oy);
   dx[5] = R(0.5) * (qw * oy + qz * ox - qx * oz);
   dx[6] = R(0.5) * (qw * oz + qx * oy - qy * ox);
+  const R ax = DIST ? B.ax : R(0), ay = DIST ? B.ay : R(0), az = DIST ? B.az : R(0);
   dx[7] = R(2) * (qx * qz + qw * qy) * s;
   dx[8] = R(2) * (qy * qz - qw * qx) * s;
-  dx[9] = (n2 - R(2) * (qx * qx + qy * qy)) * s - g;
-  // Euler: J wdot = tau - w x (J w)
-  dx[10] = (tx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
-  dx[11] = (ty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
-  dx[12] = (tz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
+  dx[9] = (n2 - R(2) * (qx * qx + qy * qy)) * s;
+  if (DIST) {
+    dx[7] += ax;
+    dx[8] += ay;
+    dx[9] += az;
+  }
+  dx[9] -= g;
+  // Euler: J wdot = tau + tau_r - w x (J w)
+  const R ttx = DIST ? tx + B.dtx : tx, tty = DIST ? ty + B.dty : ty,
+          ttz = DIST ? tz + B.dtz : tz;
+  dx[10] = (ttx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
+  dx[11] = (tty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
+  dx[12] = (ttz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
   dx[13] = (u[0] - w0) * B.inv_Tm;
   dx[14] = (u[1] - w1) * B.inv_Tm;
   dx[15] = (u[2] - w2) * B.inv_Tm;
@@ -187,29 +259,29 @@ __device__ inline void deriv(const Body<R>& B, R arm, R km, R g, const R x[NS], 
 }
 
 // One classical RK4 step, set points held.  Optional renormalisation of q.
-template <typename R>
+template <typename R, bool DIST = true>
 __device__ inline void rk4_step(const Body<R>& B, R arm, R km, R g, R h, bool renorm, R x[NS],
                                 const R u[4]) {
   R k[NS], acc[NS], t[NS];
-  deriv<R>(B, arm, km, g, x, u, k);
+  deriv<R, DIST>(B, arm, km, g, x, u, k);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     acc[i] = k[i];
     t[i] = x[i] + R(0.5) * h * k[i];
   }
-  deriv<R>(B, arm, km, g, t, u, k);
+  deriv<R, DIST>(B, arm, km, g, t, u, k);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     acc[i] += R(2) * k[i];
     t[i] = x[i] + R(0.5) * h * k[i];
   }
-  deriv<R>(B, arm, km, g, t, u, k);
+  deriv<R, DIST>(B, arm, km, g, t, u, k);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     acc[i] += R(2) * k[i];
     t[i] = x[i] + h * k[i];
   }
-  deriv<R>(B, arm, km, g, t, u, k);
+  deriv<R, DIST>(B, arm, km, g, t, u, k);
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = x[i] + (h / R(6)) * (acc[i] + k[i]);
   if (renorm) {
@@ -328,12 +400,12 @@ __device__ inline void deriv_vjp(const Body<float>& B, const float th[NP], float
   gx[5] += 2.0f * sc * (g7 * qw + g8 * qz - g9 * qy) - k2 * qy;
   gx[6] += 2.0f * sc * (g7 * qx + g8 * qy + g9 * qz) - k2 * qz;
   const float gF = gsc * B.inv_m * inv_n2;
-  gth[0] += -gsc * sc * B.inv_m;
+  gth[0] += -(gsc * sc + g7 * B.ax + g8 * B.ay + g9 * B.az) * B.inv_m;
   // w' = J^-1 (tau - w x J w)
   const float hx = gd[10] * B.inv_Jx, hy = gd[11] * B.inv_Jy, hz = gd[12] * B.inv_Jz;
-  const float dwx = (tx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
-  const float dwy = (ty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
-  const float dwz = (tz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
+  const float dwx = (tx + B.dtx - (B.Jz - B.Jy) * oy * oz) * B.inv_Jx;
+  const float dwy = (ty + B.dty - (B.Jx - B.Jz) * oz * ox) * B.inv_Jy;
+  const float dwz = (tz + B.dtz - (B.Jy - B.Jx) * ox * oy) * B.inv_Jz;
   gth[1] += -hx * dwx;
   gth[2] += -hy * dwy;
   gth[3] += -hz * dwz;

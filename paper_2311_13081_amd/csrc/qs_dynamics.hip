@@ -22,12 +22,17 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
   float th[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) th[i] = b.theta[(size_t)i * N + e];
-  const Body<float> B = make_body<float>(th);
+  Body<float> B = make_body<float>(th);
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
   float x[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
   int t_ep = b.t_ep[e], ep = b.ep[e];
+  {
+    float d[6];
+    disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+    set_disturbance(B, d);
+  }
   int last_reset = -1;  // step after which the history was refilled
   float ah = 0.0f;
   if (states)
@@ -52,6 +57,9 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
       t_ep = 0;
       last_reset = t;
       ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
+      float d[6];
+      disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+      set_disturbance(B, d);
     }
     if (rewards) rewards[(size_t)t * N + eo] = r;
     if (dones) dones[(size_t)t * N + eo] = (uint8_t)d;

@@ -22,6 +22,11 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
                              const float* W, const float* ext_act, float* reward, uint8_t* done,
                              float* state_out, hipStream_t st);
 hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st);
+// Observations of the current state: actor observation [146][N] (with the
+// noise of the coming step when enabled) and critic observation [28][N];
+// either may be NULL.
+hipError_t launch_observe(const DevCfg& c, const SimBufs& b, float* actor_obs, float* critic_obs,
+                          hipStream_t st);
 // Dynamics-only rollout with given actions ([4][N] constant if a_tstride == 0,
 // [T][4][N] if a_tstride == 4).
 hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* act, int a_tstride,
@@ -32,6 +37,12 @@ hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* ac
 // (146).
 constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z1 + NHID,
               REC_O = REC_Z2 + NHID, REC_F = REC_O + NO;
+
+// Tape checkpoint of a differentiable rollout, CK_F rows of [N]: state (17),
+// history oldest first (128), then the step within the episode and the
+// episode index as int32 bit patterns (they key the observation noise and the
+// episode disturbance of the recompute).
+constexpr int CK_TEP = NS + NH * NA, CK_EP = CK_TEP + 1, CK_F = CK_EP + 1;
 
 // The backward's per-step records (and the layer cotangents) are blocked by
 // 64 envs: within one step, row f of env e sits at rb_at(e, F) + 64 f, F the
@@ -48,12 +59,15 @@ __host__ __device__ inline size_t rb_at(int e, int F) {
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st);
 // Quarter-lane fused kernel (qs_fused4.hip): 16 envs per wave, 4 lanes per
-// env.  With rec != NULL it runs in recompute mode from checkpoint ck_in.
+// env; the kernel of taped rollouts (tape: CK_F-row checkpoints every
+// ckpt_every steps).  With rec != NULL it runs in recompute mode from
+// checkpoint ck_in.
 hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                          float* rewards, uint8_t* dones, float* states, float* tape,
                          int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
+// One-env-per-lane fused kernel (qs_fused.hip), actor on fp32 MFMA or VALU.
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
-                        float* states, float* tape, int ckpt_every, hipStream_t st);
+                        float* states, hipStream_t st);
 
 }  // namespace qs

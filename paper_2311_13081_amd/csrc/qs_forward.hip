@@ -74,21 +74,23 @@ __global__ void k_set_state(SimBufs b, int N, const float* state, const float* h
 // ---------------------------------------------------------------------------
 
 // obs[146][N] = {p, R(q), v, w, H oldest..newest}
-__global__ void __launch_bounds__(256) k_plain_obs(SimBufs b, int N, float* __restrict__ obs) {
+__global__ void __launch_bounds__(256) k_plain_obs(DevCfg c, SimBufs b, float* __restrict__ obs) {
+  const int N = c.n_envs;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
-  float q[4], Rm[9];
+  float q[4], f[18];
 #pragma unroll
   for (int i = 0; i < 4; ++i) q[i] = b.state[(3 + i) * N + e];
-  rotmat(q, Rm);
+  rotmat(q, f + 3);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) obs[i * N + e] = b.state[i * N + e];
+  for (int i = 0; i < 3; ++i) {
+    f[i] = b.state[i * N + e];
+    f[12 + i] = b.state[(7 + i) * N + e];
+    f[15 + i] = b.state[(10 + i) * N + e];
+  }
+  add_obs_noise(c, (uint32_t)e, (uint32_t)b.ep[e], b.t_ep[e], f);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) obs[(3 + i) * N + e] = Rm[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) obs[(12 + i) * N + e] = b.state[(7 + i) * N + e];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) obs[(15 + i) * N + e] = b.state[(10 + i) * N + e];
+  for (int i = 0; i < 18; ++i) obs[i * N + e] = f[i];
   const int h = b.head[e];
   for (int s = 0; s < NH; ++s) {
     const int slot = (h + s) & (NH - 1);
@@ -146,7 +148,10 @@ __global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
     a[i] = act[i * N + e];
     u[i] = action_to_rpm(c, a[i]);
   }
-  const Body<float> B = make_body<float>(th);
+  Body<float> B = make_body<float>(th);
+  float dist[6];
+  disturbance(c, (uint32_t)e, (uint32_t)b.ep[e], dist);
+  set_disturbance(B, dist);
   rk4_step<float>(B, c.arm, c.km, c.g, c.dt, (c.flags & F_RENORM_Q) != 0, x, u);
   const float r = reward(c, x, a);
   int h = b.head[e];
@@ -172,6 +177,49 @@ __global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
   if (state_out)
 #pragma unroll
     for (int i = 0; i < NS; ++i) state_out[i * N + e] = x[i];
+}
+
+// Observations of the current state (for a caller that runs its own policy
+// or critic): the actor observation with the noise of the coming step, and
+// the critic's privileged observation {p, R, v, w, w_m, f_r, tau_r} (Sec. IV).
+__global__ void __launch_bounds__(256) k_observe(DevCfg c, SimBufs b, float* __restrict__ aobs,
+                                                 float* __restrict__ cobs) {
+  const int N = c.n_envs;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  float x[NS], f[18];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+  rotmat(x + 3, f + 3);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    f[i] = x[i];
+    f[12 + i] = x[7 + i];
+    f[15 + i] = x[10 + i];
+  }
+  const uint32_t ep = (uint32_t)b.ep[e];
+  if (cobs) {
+    float d[6];
+    disturbance(c, (uint32_t)e, ep, d);
+#pragma unroll
+    for (int i = 0; i < 18; ++i) cobs[i * N + e] = f[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cobs[(18 + i) * N + e] = x[13 + i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cobs[(22 + i) * N + e] = d[i];
+  }
+  if (aobs) {
+    add_obs_noise(c, (uint32_t)e, ep, b.t_ep[e], f);
+#pragma unroll
+    for (int i = 0; i < 18; ++i) aobs[i * N + e] = f[i];
+    const int h = b.head[e];
+    for (int s = 0; s < NH; ++s) {
+      const int slot = (h + s) & (NH - 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        aobs[(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+    }
+  }
 }
 
 // Copies the state to a [17][N] slice (start state of a recorded rollout).
@@ -215,7 +263,7 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
   const dim3 g(nblk(N, 256)), blk(256);
   const float* act = ext_act;
   if (!ext_act) {
-    hipLaunchKernelGGL(k_plain_obs, g, blk, 0, st, b, N, p.obs);
+    hipLaunchKernelGGL(k_plain_obs, g, blk, 0, st, c, b, p.obs);
     hipLaunchKernelGGL((k_plain_dense<NO, NHID, false>), g, blk, 0, st, N, W + OFF_W1, W + OFF_B1,
                        p.obs, p.h1);
     hipLaunchKernelGGL((k_plain_dense<NHID, NHID, false>), g, blk, 0, st, N, W + OFF_W2,
@@ -228,6 +276,13 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
   return hipGetLastError();
 }
 
+
+hipError_t launch_observe(const DevCfg& c, const SimBufs& b, float* actor_obs, float* critic_obs,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_observe, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, actor_obs,
+                     critic_obs);
+  return hipGetLastError();
+}
 
 hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, out);

@@ -17,19 +17,15 @@ namespace qs {
 // history push, termination, truncation, reset) with state and history kept
 // in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
 // the actor when non-NULL.  Inactive lanes of the last wave shadow the wave's
-// first env (read only) so every MFMA operand is finite.
-// Recompute mode of the backward pass (rec != NULL): the start state and
-// history come from checkpoint ck_in ([145][N], history oldest first); each
-// step records x_t, a_t, z1, z2 and o_t into rec ([T][REC_F][N]); nothing
-// else is written.  Record mode is a run-time switch rather than a template
-// parameter so that the taped forward and the recompute execute the same
-// machine code and produce bit-identical trajectories.
-template <bool MFMA>
+// first env (read only) so every MFMA operand is finite.  EXTRAS (the
+// training extras are on): the episode disturbance enters the dynamics and
+// the actor sees its observation with noise; without them the kernel carries
+// none of that code.
+template <bool MFMA, bool EXTRAS>
 __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
-        float* __restrict__ states, float* __restrict__ tape, int ckpt_every,
-        const float* __restrict__ ck_in, float* __restrict__ rec) {
+        float* __restrict__ states) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
   if (ext_act == nullptr) stage_actor<MFMA>(W, lds);
@@ -39,34 +35,29 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   if (first >= N) return;  // whole wave past the end
   const bool active = env < N;
   const int e = active ? env : first;
-  const bool REC = MFMA && rec != nullptr;
 
   float th[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) th[i] = b.theta[i * N + e];
-  const Body<float> B = make_body<float>(th);
+  Body<float> B = make_body<float>(th);
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
 
   float x[NS];
   float H[NH * NA];
-  int head0 = 0, t_ep = 0, ep = 0;
-  if (REC) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
+  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+  const int head0 = b.head[e];
 #pragma unroll
-    for (int i = 0; i < NH * NA; ++i) H[i] = ck_in[(size_t)(NS + i) * N + e];
-  } else {
+  for (int sl = 0; sl < NH; ++sl) {
+    const int slot = (head0 + sl) & (NH - 1);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
-    head0 = b.head[e];
-#pragma unroll
-    for (int sl = 0; sl < NH; ++sl) {
-      const int slot = (head0 + sl) & (NH - 1);
-#pragma unroll
-      for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
-    }
-    t_ep = b.t_ep[e];
-    ep = b.ep[e];
+    for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
+  }
+  int t_ep = b.t_ep[e], ep = b.ep[e];
+  if (EXTRAS) {
+    float d[6];
+    disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+    set_disturbance(B, d);
   }
   bool was_reset = false;
 
@@ -79,55 +70,41 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     // loop would pin thousands of loop-invariant values in registers.
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
-    // Re-read each step through an opaque copy so the optimiser cannot split
-    // the loop into separate record and no-record versions.
-    const bool rec_on = opaque(REC ? 1u : 0u) != 0u;
     const int gt = t_base + t;
-    if (tape && (gt % ckpt_every) == 0 && active) {
-      float* ck = tape + (size_t)(gt / ckpt_every) * (NS + NH * NA) * N;
-#pragma unroll
-      for (int i = 0; i < NS; ++i) ck[(size_t)i * N + eo] = x[i];
-#pragma unroll
-      for (int i = 0; i < NH * NA; ++i) ck[(size_t)(NS + i) * N + eo] = H[i];
-    }
     float a[NA];
-    float* rt = rec_on ? rec + (size_t)t * REC_F * N : nullptr;
     if (ext_act) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = ext_act[((size_t)t * NA + i) * N + eo];
     } else {
-      float Rm[9];
+      float Rm[9], so[NS];
       rotmat(x + 3, Rm);
-      const float* s = x;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) so[i] = x[i];
+      if (EXTRAS && (c.flags & F_OBS_NOISE)) {
+        float f[18] = {x[0],  x[1],  x[2],  Rm[0], Rm[1], Rm[2], Rm[3], Rm[4],  Rm[5],
+                       Rm[6], Rm[7], Rm[8], x[7],  x[8],  x[9],  x[10], x[11], x[12]};
+        add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, f);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          so[i] = f[i];
+          so[7 + i] = f[12 + i];
+          so[10 + i] = f[15 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
+      }
       float z3[NA];
       if (MFMA)
-        actor_mfma(lds, s, Rm, H, z3, rec_on ? rt + (size_t)REC_Z1 * N : nullptr,
-                   rec_on ? rt + (size_t)REC_Z2 * N : nullptr, N, first);
+        actor_mfma(lds, so, Rm, H, z3);
       else
-        actor_valu(lds, s, Rm, H, z3);
+        actor_valu(lds, so, Rm, H, z3);
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
-      if (rec_on && active) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) rt[(size_t)(REC_O + i) * N + eo] = s[i];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) rt[(size_t)(REC_O + 3 + i) * N + eo] = Rm[i];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) rt[(size_t)(REC_O + 12 + i) * N + eo] = s[7 + i];
-#pragma unroll
-        for (int i = 0; i < NH * NA; ++i) rt[(size_t)(REC_O + 18 + i) * N + eo] = H[i];
-      }
-    }
-    if (rec_on && active) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) rt[(size_t)(REC_X + i) * N + eo] = x[i];
-#pragma unroll
-      for (int i = 0; i < NA; ++i) rt[(size_t)(REC_A + i) * N + eo] = a[i];
     }
     float u[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
-    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    rk4_step<float, EXTRAS>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
     const float r = reward(c, x, a);
 #pragma unroll
     for (int i = 0; i < (NH - 1) * NA; ++i) H[i] = H[i + NA];
@@ -142,6 +119,11 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
 #pragma unroll
       for (int i = 0; i < NH * NA; ++i) H[i] = ah;
+      if (EXTRAS) {
+        float dd[6];
+        disturbance(c, (uint32_t)e, (uint32_t)ep, dd);
+        set_disturbance(B, dd);
+      }
     }
     if (active) {
       if (rewards) rewards[(size_t)gt * N + eo] = r;
@@ -151,7 +133,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
         for (int i = 0; i < NS; ++i) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
     }
   }
-  if (!active || REC) return;
+  if (!active) return;
   const uint32_t ef = opaque((uint32_t)e);
 #pragma unroll
   for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + ef] = x[i];
@@ -175,14 +157,21 @@ static inline unsigned nblk(int n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
-                        float* states, float* tape, int ckpt_every, hipStream_t st) {
+                        float* states, hipStream_t st) {
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
-  if (mfma)
-    hipLaunchKernelGGL(k_fused<true>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
-                       states, tape, ckpt_every, nullptr, nullptr);
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
+  if (mfma && !ex)
+    hipLaunchKernelGGL((k_fused<true, false>), g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards,
+                       dones, states);
+  else if (mfma)
+    hipLaunchKernelGGL((k_fused<true, true>), g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards,
+                       dones, states);
+  else if (!ex)
+    hipLaunchKernelGGL((k_fused<false, false>), g, blk, 0, st, c, b, W, ext_act, T, t_base,
+                       rewards, dones, states);
   else
-    hipLaunchKernelGGL(k_fused<false>, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones,
-                       states, tape, ckpt_every, nullptr, nullptr);
+    hipLaunchKernelGGL((k_fused<false, true>), g, blk, 0, st, c, b, W, ext_act, T, t_base,
+                       rewards, dones, states);
   return hipGetLastError();
 }
 

@@ -279,7 +279,7 @@ __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[N
 
 // Two waves per SIMD (256 registers each) so one wave's vector work overlaps
 // the other's matrix-core work.
-template <bool BF16>
+template <bool BF16, bool EXTRAS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
          float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states,
@@ -303,7 +303,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
   float th[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) th[i] = b.theta[(size_t)i * N + e];
-  const Body<float> B = make_body<float>(th);
+  Body<float> B = make_body<float>(th);
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
 
   float x[NS];
@@ -314,6 +314,8 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
 #pragma unroll
     for (int s = 0; s < NH; ++s) F[5 + s] = ck_in[(size_t)(NS + s * NA + k) * N + e];
+    t_ep = __float_as_int(ck_in[(size_t)CK_TEP * N + e]);
+    ep = __float_as_int(ck_in[(size_t)CK_EP * N + e]);
   } else {
 #pragma unroll
     for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
@@ -327,6 +329,11 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     ep = b.ep[e];
   }
   bool was_reset = false;
+  if (EXTRAS) {
+    float d[6];
+    disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+    set_disturbance(B, d);
+  }
 
   if (states && t_base == 0 && active)
 #pragma unroll
@@ -339,20 +346,25 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     const bool rec_on = opaque(REC ? 1u : 0u) != 0u;
     const int gt = t_base + t;
     if (tape && (gt % ckpt_every) == 0 && active) {
-      float* ck = tape + (size_t)(gt / ckpt_every) * (NS + NH * NA) * N;
+      float* ck = tape + (size_t)(gt / ckpt_every) * CK_F * N;
 #pragma unroll
       for (int i = 0; i < NS; ++i)
         if ((i & 3) == k) ck[(size_t)i * N + eo] = x[i];
       const uint32_t kc = opaque((uint32_t)(k * N + e));
 #pragma unroll
       for (int s = 0; s < NH; ++s) ck[(size_t)(NS + s * NA) * N + kc] = F[5 + s];
+      if (k == 0) {
+        ck[(size_t)CK_TEP * N + eo] = __int_as_float(t_ep);
+        ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
+      }
     }
     // observation state part: 18 features, this quarter keeps 4c + k
     float Rm[9];
     rotmat(x + 3, Rm);
     {
-      const float sf[20] = {x[0], x[1], x[2], Rm[0], Rm[1], Rm[2], Rm[3], Rm[4], Rm[5], Rm[6],
-                            Rm[7], Rm[8], x[7], x[8], x[9], x[10], x[11], x[12], 0.0f, 0.0f};
+      float sf[20] = {x[0], x[1], x[2], Rm[0], Rm[1], Rm[2], Rm[3], Rm[4], Rm[5], Rm[6],
+                      Rm[7], Rm[8], x[7], x[8], x[9], x[10], x[11], x[12], 0.0f, 0.0f};
+      if (EXTRAS) add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, sf);
 #pragma unroll
       for (int cc = 0; cc < 5; ++cc)
         F[cc] = k == 0 ? sf[4 * cc] : k == 1 ? sf[4 * cc + 1] : k == 2 ? sf[4 * cc + 2]
@@ -388,7 +400,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     float u[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
-    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    rk4_step<float, EXTRAS>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
     const float r = reward(c, x, a);
 #pragma unroll
     for (int s = 5; s < Q_C - 1; ++s) F[s] = F[s + 1];
@@ -402,6 +414,11 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
 #pragma unroll
       for (int s = 5; s < Q_C; ++s) F[s] = ah;
+      if (EXTRAS) {
+        float d[6];
+        disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+        set_disturbance(B, d);
+      }
     }
     if (active) {
       if (k == 0 && rewards) rewards[(size_t)gt * N + eo] = r;
@@ -436,12 +453,12 @@ hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int 
                          float* rewards, uint8_t* dones, float* states, float* tape,
                          int ckpt_every, const float* ck_in, float* rec, hipStream_t st) {
   const unsigned grid = (unsigned)((c.n_envs + 63) / 64);
-  if (c.flags & F_ACTOR_BF16)
-    hipLaunchKernelGGL(k_fused4<true>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards,
-                       dones, states, tape, ckpt_every, ck_in, rec);
-  else
-    hipLaunchKernelGGL(k_fused4<false>, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base,
-                       rewards, dones, states, tape, ckpt_every, ck_in, rec);
+  const bool bf = (c.flags & F_ACTOR_BF16) != 0;
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
+  auto k = bf ? (ex ? k_fused4<true, true> : k_fused4<true, false>)
+              : (ex ? k_fused4<false, true> : k_fused4<false, false>);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states,
+                     tape, ckpt_every, ck_in, rec);
   return hipGetLastError();
 }
 

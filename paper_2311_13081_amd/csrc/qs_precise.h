@@ -12,6 +12,7 @@ struct PreciseCfg {
   double C_rp, C_rq, C_rv, C_rw, C_ra, C_rab, C_rs;
   double nominal[8], dr_lo[8], dr_hi[8];
   uint32_t seed_lo, seed_hi, dr_seed_lo, dr_seed_hi;
+  double dist_force, dist_torque, noise[4];
 };
 
 struct PreciseBufs {

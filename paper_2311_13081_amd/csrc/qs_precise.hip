@@ -41,6 +41,46 @@ __device__ inline void env_params64(const PreciseCfg& p, uint32_t env, double th
   }
 }
 
+// Episode disturbance and observation noise, as in the float path, in double.
+__device__ inline void disturbance64(const PreciseCfg& p, uint32_t env, uint32_t episode,
+                                     double d[6]) {
+  for (int i = 0; i < 6; ++i) d[i] = 0.0;
+  if (!(p.flags & F_DISTURB)) return;
+  double u[8];
+  uniforms4_f64(p.seed_lo, p.seed_hi, env, episode, 0, STREAM_DIST, u);
+  uniforms4_f64(p.seed_lo, p.seed_hi, env, episode, 1, STREAM_DIST, u + 4);
+  for (int i = 0; i < 3; ++i) {
+    d[i] = p.dist_force * (2.0 * u[i] - 1.0);
+    d[3 + i] = p.dist_torque * (2.0 * u[3 + i] - 1.0);
+  }
+}
+
+__device__ inline void add_obs_noise64(const PreciseCfg& p, uint32_t env, uint32_t episode,
+                                       int t_ep, double f[18]) {
+  if (!(p.flags & F_OBS_NOISE)) return;
+  double u[20];
+  for (int bk = 0; bk < 5; ++bk)
+    uniforms4_f64(p.seed_lo, p.seed_hi, env, episode, (uint32_t)t_ep * 5u + (uint32_t)bk,
+                  STREAM_NOISE, u + 4 * bk);
+  for (int i = 0; i < 18; i += 2) {
+    const double r = sqrt(-2.0 * log(u[i]));
+    const double ph = 2.0 * 3.141592653589793 * u[i + 1];
+    const int g0 = i < 3 ? 0 : i < 12 ? 1 : i < 15 ? 2 : 3;
+    const int g1 = (i + 1) < 3 ? 0 : (i + 1) < 12 ? 1 : (i + 1) < 15 ? 2 : 3;
+    f[i] += p.noise[g0] * r * cos(ph);
+    f[i + 1] += p.noise[g1] * r * sin(ph);
+  }
+}
+
+__device__ inline void set_disturbance64(Body<double>& B, const double d[6]) {
+  B.ax = d[0] * B.inv_m;
+  B.ay = d[1] * B.inv_m;
+  B.az = d[2] * B.inv_m;
+  B.dtx = d[3];
+  B.dty = d[4];
+  B.dtz = d[5];
+}
+
 __device__ inline double hover_rpm64(const PreciseCfg& p, const double th[NP]) {
   const double need = th[0] * p.g / 4.0 - th[4];
   if (th[6] == 0.0) return need / th[5];
@@ -135,6 +175,11 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
   B.c2 = th[6];
   B.inv_Tm = 1.0 / th[7];
   int head = b.head[e], t_ep = b.t_ep[e], ep = b.ep[e];
+  {
+    double d[6];
+    disturbance64(p, (uint32_t)e, (uint32_t)ep, d);
+    set_disturbance64(B, d);
+  }
   const bool renorm = (p.flags & F_RENORM_Q) != 0;
   if (states && t_base == 0)
     for (int i = 0; i < NS; ++i) states[(size_t)i * N + e] = (float)x[i];
@@ -166,6 +211,7 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
           o18[12 + i] = x[7 + i];
           o18[15 + i] = x[10 + i];
         }
+        add_obs_noise64(p, (uint32_t)e, (uint32_t)ep, t_ep, o18);
       }
       double z1[NHID];
 #pragma unroll
@@ -238,6 +284,9 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
       const double ah = reset64(p, th, (uint32_t)e, (uint32_t)ep, x);
       for (int i = 0; i < NH * NA; ++i) b.ring[(size_t)i * N + e] = ah;
       head = 0;
+      double d[6];
+      disturbance64(p, (uint32_t)e, (uint32_t)ep, d);
+      set_disturbance64(B, d);
     }
     if (rewards) rewards[(size_t)gt * N + e] = (float)r;
     if (dones) dones[(size_t)gt * N + e] = (uint8_t)d;

@@ -88,6 +88,18 @@ class QuadSim:
                                  1 if record_tape else 0, _stream()), "sim_rollout")
         return out
 
+    def observe(self, actor=True, critic=True):
+        """Current observations: actor [146][N] (with the coming step's noise)
+        and critic [28][N] {p, R, v, w, rotor speeds, f_r, tau_r}."""
+        out = {}
+        if actor:
+            out["actor"] = self._f32(146, self.N)
+        if critic:
+            out["critic"] = self._f32(28, self.N)
+        check(self.L.sim_observe(self.h, _ptr(out.get("actor")), _ptr(out.get("critic")),
+                                 _stream()), "sim_observe")
+        return out
+
     def rollout_actions(self, actions: torch.Tensor, T: int, rewards=True, dones=True,
                         states=False):
         """Dynamics-only rollout: actions [4][N] held constant, or [T][4][N]."""
