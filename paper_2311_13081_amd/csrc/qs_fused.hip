@@ -76,28 +76,37 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = ext_act[((size_t)t * NA + i) * N + eo];
     } else {
-      float Rm[9], so[NS];
+      float Rm[9];
       rotmat(x + 3, Rm);
-#pragma unroll
-      for (int i = 0; i < NS; ++i) so[i] = x[i];
-      if (EXTRAS && (c.flags & F_OBS_NOISE)) {
-        float f[18] = {x[0],  x[1],  x[2],  Rm[0], Rm[1], Rm[2], Rm[3], Rm[4],  Rm[5],
-                       Rm[6], Rm[7], Rm[8], x[7],  x[8],  x[9],  x[10], x[11], x[12]};
-        add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, f);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          so[i] = f[i];
-          so[7 + i] = f[12 + i];
-          so[10 + i] = f[15 + i];
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
-      }
       float z3[NA];
-      if (MFMA)
-        actor_mfma(lds, so, Rm, H, z3);
-      else
-        actor_valu(lds, so, Rm, H, z3);
+      if constexpr (EXTRAS) {
+        // noisy copy of the observed state features
+        float so[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) so[i] = x[i];
+        if (c.flags & F_OBS_NOISE) {
+          float f[18] = {x[0],  x[1],  x[2],  Rm[0], Rm[1], Rm[2], Rm[3], Rm[4],  Rm[5],
+                         Rm[6], Rm[7], Rm[8], x[7],  x[8],  x[9],  x[10], x[11], x[12]};
+          add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, f);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            so[i] = f[i];
+            so[7 + i] = f[12 + i];
+            so[10 + i] = f[15 + i];
+          }
+#pragma unroll
+          for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
+        }
+        if (MFMA)
+          actor_mfma(lds, so, Rm, H, z3);
+        else
+          actor_valu(lds, so, Rm, H, z3);
+      } else {
+        if (MFMA)
+          actor_mfma(lds, x, Rm, H, z3);
+        else
+          actor_valu(lds, x, Rm, H, z3);
+      }
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
     }
