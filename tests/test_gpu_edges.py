@@ -1,0 +1,120 @@
+"""Edge sizes on the GPU against the FP64 oracle: a single env, batches that
+leave the last wave (16 envs per wave in the quarter-lane kernel, 64 in the
+one-lane kernel) or the last 64-env record block partly empty, one-step
+rollouts, and the backward at those sizes."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from parity import STEP_TOL, TRAJ_TOL, max_state_err, state_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 17, 63, 65]
+PATHS = {"plain": (1, 0), "valu": (2, 0), "mfma": (3, 0), "mfma4": (4, 0),
+         "fp64": (0, wl.F_FP64)}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2311_13081_amd as p
+    p.load()
+    return p
+
+
+def np_(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+@pytest.mark.parametrize("n", SIZES)
+def test_short_rollout_at_edge_sizes(pkg, oracle_lib, path, n):
+    variant, extra = PATHS[path]
+    T = 5
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0,
+                              flags=wl.F_RENORM_Q | extra)
+    sim = pkg.QuadSim(cfg)
+    if variant:
+        sim.set_variant(variant)
+    W = wl.random_actor(7)
+    s, h = wl.random_states(n, seed=40 + n)
+    sim.set_state(state=s, hist=h)
+    th = np_(sim.get_params())
+    if path == "fp64":
+        sim.set_params(th)
+    out = sim.rollout(sim.actor_tensor(W), T, states=True)
+    ref = oracle_lib.Batch(cfg, n)
+    ref.set_soa(s, h, theta_soa=th)
+    ro = ref.rollout(W, T, record=True)
+    e = state_err(np_(out["states"]), ro["states"]).max(axis=(1, 2))
+    assert e[1] < STEP_TOL and e.max() < TRAJ_TOL
+    assert np.array_equal(np_(sim.get_state()["t_ep"]), np.full(n, T, np.int32))
+    sim.close()
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_one_step_rollout_equals_step(pkg, n):
+    for variant in (3, 4):
+        cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0)
+        a, b = pkg.QuadSim(cfg), pkg.QuadSim(cfg)
+        a.set_variant(variant)
+        b.set_variant(variant)
+        W = wl.random_actor(8)
+        r1 = a.rollout(a.actor_tensor(W), 1)["rewards"][0]
+        r2, _ = b.step(actor=b.actor_tensor(W))
+        assert np.array_equal(np_(r1), np_(r2))
+        assert np.array_equal(np_(a.get_state()["state"]), np_(b.get_state()["state"]))
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("n", [1, 17, 65])
+def test_backward_at_edge_sizes(pkg, oracle_lib, n):
+    T, K = 6, 4
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0, max_tape_horizon=T,
+                              ckpt_every=K)
+    ob = oracle_lib.Batch.init(cfg, n)
+    s32, h32 = (x.astype(np.float32) for x in ob.soa())
+    sim = pkg.QuadSim(cfg)
+    sim.set_state(state=s32, hist=h32)
+    th = np_(sim.get_params())
+    W = wl.random_actor(9)
+    a = sim.actor_tensor(W)
+    sim.rollout(a, T, record_tape=True)
+    ga, gp = sim.backward(a)
+    ref = oracle_lib.Batch(cfg, n)
+    ref.set_soa(s32, h32, theta_soa=th)
+    _, gW, gth = ref.grad(W, T)
+    ga = np_(ga).astype(np.float64)
+    gp = np_(gp).astype(np.float64).T
+    assert np.linalg.norm(ga - gW) / np.linalg.norm(gW) < 1e-3
+    sc = np.abs(th.T).astype(np.float64)
+    sc[:, 4] = th[0] * cfg["g"] / 4
+    sc[:, 5] = sc[:, 4] / 14000.0
+    ep = np.linalg.norm((gp - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
+    assert ep.max() < 1e-3
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [1, 17, 65])
+def test_dynamics_only_and_observe_at_edge_sizes(pkg, oracle_lib, n):
+    T = 4
+    cfg = wl.training_extras(wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0))
+    sim = pkg.QuadSim(cfg)
+    s, h = wl.random_states(n, seed=60 + n)
+    sim.set_state(state=s, hist=h)
+    th = np_(sim.get_params())
+    o = sim.observe()
+    co = np_(o["critic"]).T
+    for e in range(n):
+        ref = oracle_lib.critic_obs(cfg, e, 0, s[:, e].astype(np.float64))
+        assert np.allclose(co[e], ref, rtol=2e-6, atol=2e-6)
+    A = np.stack([wl.random_actions(n, seed=70 + t) for t in range(T)])
+    out = sim.rollout_actions(torch.as_tensor(A).cuda(), T, states=True)
+    ref = oracle_lib.Batch(cfg, n)
+    ref.set_soa(s, h, theta_soa=th)
+    ro = ref.rollout(None, T, actions=np.transpose(A, (0, 2, 1)).astype(np.float64), record=True)
+    assert state_err(np_(out["states"]), ro["states"]).max() < TRAJ_TOL
+    sim.close()
