@@ -338,6 +338,19 @@ def main():
         extras["headline_bf16_actor"] = {"env_steps_per_s": N * T * 2 / w5,
                                          "kernel_ms": d5 / (2 * l5)}
         s5.close()
+        # the headline workload with the training extras (per-episode
+        # disturbance and actor observation noise), and the FP64 path
+        for label, flags, steps in (("headline_training_extras", wl.F_DISTURB | wl.F_OBS_NOISE, T),
+                                    ("headline_fp64_100_steps", wl.F_FP64, 100)):
+            cfg_x = wl.training_extras(cfg) if flags != wl.F_FP64 else dict(cfg)
+            cfg_x["flags"] = cfg["flags"] | flags
+            s6 = pkg.QuadSim(cfg_x)
+            if flags != wl.F_FP64:
+                s6.set_variant(v, spl, graph)
+            w6, d6, l6 = time_rollouts(torch, s6, actor, steps, 2, 1)
+            extras[label] = {"env_steps_per_s": N * steps * 2 / w6, "kernel_ms": d6 / (2 * l6),
+                             "rollout_steps": steps}
+            s6.close()
         res["comparison"] = extras
         res["fixed_episodes_4096"] = fixed_episodes(torch, pkg, actor)
     sim.close()

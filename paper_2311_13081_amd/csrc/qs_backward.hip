@@ -503,19 +503,21 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int col = 16 * q + 4 * lg;
+        // independent accumulators innermost, so consecutive MFMAs never
+        // wait on each other's results
+        f4 bo[10], bh[5];
 #pragma unroll
-        for (int kt = 0; kt < 10; ++kt) {
-          const f4 bo = dw_b(buf, 0, 16 * kt + li, NO, col, env0, N);
+        for (int kt = 0; kt < 10; ++kt) bo[kt] = dw_b(buf, 0, 16 * kt + li, NO, col, env0, N);
 #pragma unroll
-          for (int m = 0; m < 4; ++m)
-            acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a1[q][m], bo[m], acc1[kt], 0, 0, 0);
-        }
+        for (int kt = 0; kt < 5; ++kt) bh[kt] = dw_b(buf, NO, 16 * kt + li, NHID, col, env0, N);
 #pragma unroll
-        for (int kt = 0; kt < 5; ++kt) {
-          const f4 bh = dw_b(buf, NO, 16 * kt + li, NHID, col, env0, N);
+        for (int m = 0; m < 4; ++m) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m)
-            acc2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a2[q][m], bh[m], acc2[kt], 0, 0, 0);
+          for (int kt = 0; kt < 10; ++kt)
+            acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a1[q][m], bo[kt][m], acc1[kt], 0, 0, 0);
+#pragma unroll
+          for (int kt = 0; kt < 5; ++kt)
+            acc2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a2[q][m], bh[kt][m], acc2[kt], 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
