@@ -33,7 +33,8 @@ typedef __bf16 bf8q __attribute__((ext_vector_type(8)));
 
 constexpr int Q_C = 37;          // K-chunks of layer 1
 constexpr int Q_CP = 40;         // padded to whole float4s
-constexpr int Q_W1_P = 44;       // LDS pitch of one (neuron, quarter) row
+constexpr int Q_W1_P = 44;       // LDS pitch of one (quarter, neuron) row: 8 consecutive
+                                 // lanes' 16-byte reads land on distinct banks
 constexpr int Q_W1 = 0, Q_B1 = Q_W1 + NHID * 4 * Q_W1_P, Q_W2 = Q_B1 + NHID,
               Q_B2 = Q_W2 + NHID * 68, Q_W3 = Q_B2 + NHID, Q_B3 = Q_W3 + 16 * 68,
               Q_TOTAL = Q_B3 + 4;
@@ -45,9 +46,9 @@ __host__ __device__ constexpr int q_phi(int c, int k) {
 
 __device__ inline void stage_q(const float* __restrict__ W, float* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  // W1 in PHI order: [neuron][quarter][chunk], pitch Q_W1_P
+  // W1 in PHI order: [quarter][neuron][chunk], pitch Q_W1_P
   for (int idx = tid; idx < NHID * 4 * Q_W1_P; idx += nt) {
-    const int c = idx % Q_W1_P, rest = idx / Q_W1_P, k = rest & 3, nrn = rest >> 2;
+    const int c = idx % Q_W1_P, rest = idx / Q_W1_P, nrn = rest % NHID, k = rest / NHID;
     const int f = c < Q_C ? q_phi(c, k) : -1;
     lds[Q_W1 + idx] = f >= 0 ? W[OFF_W1 + nrn * NO + f] : 0.0f;
   }
@@ -85,7 +86,7 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       w[n] = *reinterpret_cast<const f4q*>(
-          &lds[Q_W1 + ((16 * n + li) * 4 + lg) * Q_W1_P + 4 * cc]);
+          &lds[Q_W1 + (lg * NHID + 16 * n + li) * Q_W1_P + 4 * cc]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = 4 * cc + q;
