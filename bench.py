@@ -33,6 +33,13 @@ METRIC = "env-steps/s @65536 envs (fused vs plain) + fwd+bwd steps/s; err vs FP6
 # observation, action map, four dynamics evaluations, RK4 combination,
 # renormalisation and reward.
 FLOP_PER_ENV_STEP = 28_500
+# Algorithmic HBM bytes of one env step of the plain five-kernel path: the
+# observation kernel reads p, q, v, w (52 B), head, counters and the ring
+# (524 B) and writes the observation (584 B); the three dense layers read
+# their inputs and write their outputs (584+256, 256+256, 256+16 B); the
+# dynamics kernel reads parameters, state, action and counters (128 B) and
+# writes a ring slot, counters, state, reward and done (97 B).
+PLAIN_BYTES_PER_ENV_STEP = 1160 + 840 + 512 + 272 + 225
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
 PEAK_HBM = 8.0e12
 
@@ -311,8 +318,14 @@ def main():
             s2 = pkg.QuadSim(cfg)
             s2.set_variant(pkg.SIM_V_PLAIN, 0, use_graph)
             w2, d2, _ = time_rollouts(torch, s2, actor, args.plain_steps, 2, 1)
-            extras[label] = {"env_steps_per_s": N * args.plain_steps * 2 / w2,
-                             "ms_per_env_step": w2 * 1e3 / (2 * args.plain_steps)}
+            rate = N * args.plain_steps * 2 / w2
+            gbs = rate * PLAIN_BYTES_PER_ENV_STEP / 1e9
+            extras[label] = {"env_steps_per_s": rate,
+                             "ms_per_env_step": w2 * 1e3 / (2 * args.plain_steps),
+                             "roofline": {"bound": "hbm", "achieved": gbs,
+                                          "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                          "frac": gbs * 1e9 / PEAK_HBM,
+                                          "bytes_per_env_step": PLAIN_BYTES_PER_ENV_STEP}}
             s2.close()
         # fused kernel launched once per env step
         s3 = pkg.QuadSim(cfg)

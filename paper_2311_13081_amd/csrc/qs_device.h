@@ -348,6 +348,15 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// tanh of the actor output without branches: tanh|x| = (1 - e) / (1 + e),
+// e = exp(-2|x|), on the hardware exponential and reciprocal; absolute error
+// about 2e-7 over the whole range.
+__device__ inline float tanh_act(float x) {
+  const float e = __expf(-2.0f * fabsf(x));
+  const float t = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+  return copysignf(t, x);
+}
+
 __device__ inline float action_to_rpm(const DevCfg& c, float a) {
   return c.rpm_min + (a + 1.0f) * c.rpm_half_range;
 }

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) k_plain_dense(int N, const float* __restr
     for (int n = 0; n < NOUT; ++n) acc[n] = fmaf(sW[k * NOUT + n], x, acc[n]);
   }
 #pragma unroll
-  for (int n = 0; n < NOUT; ++n) out[n * N + e] = TANH ? tanhf(acc[n]) : fmaxf(acc[n], 0.0f);
+  for (int n = 0; n < NOUT; ++n) out[n * N + e] = TANH ? tanh_act(acc[n]) : fmaxf(acc[n], 0.0f);
 }
 
 // Dynamics, reward, history push, episode bookkeeping and reset.

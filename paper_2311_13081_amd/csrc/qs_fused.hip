@@ -108,7 +108,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
           actor_valu(lds, x, Rm, H, z3);
       }
 #pragma unroll
-      for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
+      for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
     }
     float u[NA];
 #pragma unroll

@@ -385,7 +385,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
               rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff);
     float a[NA];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) a[i] = tanhf(z3[i]);
+    for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
     if (rec_on && active) {
 #pragma unroll
       for (int cc = 0; cc < Q_C; ++cc) {
