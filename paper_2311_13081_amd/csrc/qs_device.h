@@ -133,10 +133,10 @@ __device__ inline void add_obs_noise(const DevCfg& c, uint32_t env, uint32_t epi
 }
 
 // Episode-start state for (env, episode): p, attitude (angle about a uniform
-// axis), v, w uniform in their ranges, rotors at hover.  Returns the hover
-// action used to fill the history.
-__device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t episode, float m,
-                                    float c0, float c1, float c2, float s[NS]) {
+// axis), v, w uniform in their ranges, rotors at the env's hover speed wh
+// (constant per env, so loops compute it once).
+__device__ inline void reset_draw(const DevCfg& c, uint32_t env, uint32_t episode, float wh,
+                                  float s[NS]) {
   float u[12];
   uniforms4(c.seed_lo, c.seed_hi, env, episode, 0, STREAM_RESET, u);
   uniforms4(c.seed_lo, c.seed_hi, env, episode, 1, STREAM_RESET, u + 4);
@@ -158,9 +158,16 @@ __device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t epis
   for (int i = 0; i < 3; ++i) s[7 + i] = c.init_vel * (2.0f * u[6 + i] - 1.0f);
 #pragma unroll
   for (int i = 0; i < 3; ++i) s[10 + i] = c.init_angvel * (2.0f * u[9 + i] - 1.0f);
-  const float wh = hover_rpm(c, m, c0, c1, c2);
 #pragma unroll
   for (int i = 0; i < 4; ++i) s[13 + i] = wh;
+}
+
+// reset_draw with the hover speed of parameters (m, c0, c1, c2); returns the
+// hover action that fills the history.
+__device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t episode, float m,
+                                    float c0, float c1, float c2, float s[NS]) {
+  const float wh = hover_rpm(c, m, c0, c1, c2);
+  reset_draw(c, env, episode, wh, s);
   return rpm_to_action(c, wh);
 }
 

@@ -60,6 +60,8 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     set_disturbance(B, d);
   }
   bool was_reset = false;
+  const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
+  const float ah = rpm_to_action(c, wh);
 
   if (states && t_base == 0 && active)
 #pragma unroll
@@ -115,19 +117,19 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
     rk4_step<float, EXTRAS>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
     const float r = reward(c, x, a);
-#pragma unroll
-    for (int i = 0; i < (NH - 1) * NA; ++i) H[i] = H[i + NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) H[(NH - 1) * NA + i] = a[i];
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
-    if (d && (c.flags & F_AUTORESET)) {
+    const bool rst = d && (c.flags & F_AUTORESET);
+    // history push and the reset fill in one pass: one select per slot
+#pragma unroll
+    for (int i = 0; i < (NH - 1) * NA; ++i) H[i] = rst ? ah : H[i + NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) H[(NH - 1) * NA + i] = rst ? ah : a[i];
+    if (rst) {
       ++ep;
       t_ep = 0;
       was_reset = true;
-      const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
-#pragma unroll
-      for (int i = 0; i < NH * NA; ++i) H[i] = ah;
+      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
       if (EXTRAS) {
         float dd[6];
         disturbance(c, (uint32_t)e, (uint32_t)ep, dd);

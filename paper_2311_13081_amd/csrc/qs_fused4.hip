@@ -330,6 +330,8 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     ep = b.ep[e];
   }
   bool was_reset = false;
+  const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
+  const float ah = rpm_to_action(c, wh);
   if (EXTRAS) {
     float d[6];
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
@@ -403,18 +405,18 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
     rk4_step<float, EXTRAS>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
     const float r = reward(c, x, a);
-#pragma unroll
-    for (int s = 5; s < Q_C - 1; ++s) F[s] = F[s + 1];
-    F[Q_C - 1] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
-    if (d && (c.flags & F_AUTORESET)) {
+    const bool rst = d && (c.flags & F_AUTORESET);
+    // history push and the reset fill in one pass: one select per slot
+#pragma unroll
+    for (int s = 5; s < Q_C - 1; ++s) F[s] = rst ? ah : F[s + 1];
+    F[Q_C - 1] = rst ? ah : k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+    if (rst) {
       ++ep;
       t_ep = 0;
       was_reset = true;
-      const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
-#pragma unroll
-      for (int s = 5; s < Q_C; ++s) F[s] = ah;
+      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
       if (EXTRAS) {
         float d[6];
         disturbance(c, (uint32_t)e, (uint32_t)ep, d);
