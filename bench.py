@@ -145,6 +145,42 @@ def cpu_baseline(cfg, W, seconds):
                       f"{dt:.1f} s"}
 
 
+# Error norm per state component group (p, q, v, w, rotor speeds): the
+# difference relative to the larger of the reference's magnitude and the
+# group's floor (1 m, 1, 1 m/s, 1 rad/s, 1000 RPM).
+_FLOORS = np.array([1.0] * 3 + [1.0] * 4 + [1.0] * 3 + [1.0] * 3 + [1000.0] * 4)
+
+
+def oracle_step_error(torch, pkg, cfg, W, variant, warm_steps=250, n_sample=2048):
+    """The headline kernel's one-step error against the FP64 oracle on a
+    sample of envs of the headline batch, from the GPU's own state after
+    `warm_steps` steps (a mix of episode ages, some just reset)."""
+    import oracle
+    N = cfg["n_envs"]
+    sim = pkg.QuadSim(cfg)
+    sim.set_variant(*variant)
+    a = sim.actor_tensor(W)
+    sim.rollout(a, warm_steps, rewards=False, dones=False)
+    st = {k: v.cpu().numpy() for k, v in sim.get_state().items()}
+    th = sim.get_params().cpu().numpy()
+    r, d = sim.step(actor=a)
+    s1 = sim.get_state()["state"].cpu().numpy()
+    r = r.cpu().numpy()
+    d = d.cpu().numpy()
+    sim.close()
+    ids = np.linspace(0, N - 1, n_sample).astype(np.uint32)
+    ref = oracle.Batch(cfg, n_sample, ids=ids)
+    ref.set_soa(st["state"][:, ids], st["hist"][:, :, ids], t_ep=st["t_ep"][ids],
+                ep=st["episode"][ids], theta_soa=th[:, ids])
+    out = ref.rollout(W, 1, nthreads=min(os.cpu_count() or 1, 64))
+    same = d[ids] == out["dones"][0]
+    err = np.abs(s1[:, ids].T - ref.s) / np.maximum(np.abs(ref.s), _FLOORS)
+    rerr = np.abs(r[ids] - out["rewards"][0]) / np.maximum(np.abs(out["rewards"][0]), 1.0)
+    return {"one_step_state_max": float(err[same].max()), "one_step_reward_max":
+            float(rerr[same].max()), "done_flags_equal": int(same.sum()), "envs": n_sample,
+            "after_steps": warm_steps, "bar": 1e-5}
+
+
 def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
     """Forward rollout with tape + discrete adjoint on a differentiable
     workload; returns env-steps/s of the pair (N x H per fwd+bwd).  bf16:
@@ -376,6 +412,7 @@ def main():
                                 "n65536_T1000": dynamics_only(torch, pkg, 65536, 1000)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, W, args.cpu_seconds)
+        res["err_vs_oracle"] = oracle_step_error(torch, pkg, cfg, W, (v, spl, graph))
     print(json.dumps(res), flush=True)
 
 

@@ -3,6 +3,8 @@ with torch's current HIP stream; torch only supplies memory and streams."""
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 
 import torch
 
@@ -161,10 +163,33 @@ class QuadSim:
               "sim_get_variant")
         return v.value, s.value, g.value
 
-    def autotune(self, actor: torch.Tensor, T: int):
+    def autotune(self, actor: torch.Tensor, T: int, cache: str | None = None):
+        """Times the variants on a T-step rollout and keeps the fastest.  With
+        `cache` (a JSON file path), a result stored for the same (N, flags, T,
+        device architecture) is reused instead of timing again, and new
+        results are added to the file."""
+        key = None
+        if cache is not None:
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+            key = f"N={self.N} flags={int(self.cfg['flags'])} T={int(T)} arch={arch}"
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            hit = table.get(key)
+            if hit is not None:
+                self.set_variant(int(hit["variant"]), int(hit["steps_per_launch"]), True)
+                return int(hit["variant"]), float(hit["ms"])
         v, ms = ctypes.c_int(), ctypes.c_float()
         check(self.L.sim_autotune(self.h, _ptr(actor), T, _stream(), ctypes.byref(v),
                                   ctypes.byref(ms)), "sim_autotune")
+        if key is not None:
+            _, spl, _ = self.get_variant()
+            table[key] = {"variant": v.value, "steps_per_launch": spl, "ms": ms.value}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return v.value, ms.value
 
     def last_rollout_timing(self):

@@ -118,3 +118,24 @@ def test_dynamics_only_and_observe_at_edge_sizes(pkg, oracle_lib, n):
     ro = ref.rollout(None, T, actions=np.transpose(A, (0, 2, 1)).astype(np.float64), record=True)
     assert state_err(np_(out["states"]), ro["states"]).max() < TRAJ_TOL
     sim.close()
+
+
+def test_autotune_cache_round_trip(pkg, tmp_path):
+    """The autotuner's choice is stored per (N, flags, T, arch) and reused."""
+    import json
+    cfg = wl.crazyflie_config(n_envs=4096, max_episode_steps=500,
+                              flags=wl.F_RENORM_Q | wl.F_AUTORESET)
+    path = str(tmp_path / "tune.json")
+    sim = pkg.QuadSim(cfg)
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    v1, ms1 = sim.autotune(a, 200, cache=path)
+    table = json.load(open(path))
+    assert len(table) == 1
+    (key, val), = table.items()
+    assert "N=4096" in key and "T=200" in key and val["variant"] == v1
+    sim.close()
+    sim = pkg.QuadSim(cfg)
+    v2, ms2 = sim.autotune(a, 200, cache=path)
+    assert (v2, ms2) == (v1, ms1)
+    assert sim.get_variant()[0] == v1
+    sim.close()
