@@ -215,6 +215,10 @@ __device__ inline void set_disturbance(Body<R>& b, const float d[6]) {
 
 __device__ inline float rsqrt_r(float x) { return __frsqrt_rn(x); }
 __device__ inline double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+// 1/x: the hardware reciprocal (within 1 ulp) in single precision, a
+// correctly rounded division in double precision.
+__device__ inline float recip_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip_r(double x) { return 1.0 / x; }
 
 // dx = f(x, u) for the 17-state (Newton-Euler with motor lag, z up).  DIST:
 // include the body's episode disturbance (compile-time, so kernels without
@@ -234,7 +238,7 @@ __device__ inline void deriv(const Body<R>& B, R arm, R km, R g, const R x[NS], 
   const R qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   // third column of R(q/|q|) times F/m: (2(xz+wy), 2(yz-wx), 1-2(x^2+y^2)) / |q|^2
   const R n2 = qw * qw + qx * qx + qy * qy + qz * qz;
-  const R s = F * B.inv_m / n2;
+  const R s = F * B.inv_m * recip_r(n2);
   dx[0] = x[7];
   dx[1] = x[8];
   dx[2] = x[9];
@@ -291,19 +295,20 @@ __device__ inline void rk4_step(const Body<R>& B, R arm, R km, R g, R h, bool re
   deriv<R, DIST>(B, arm, km, g, t, u, k);
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = x[i] + (h / R(6)) * (acc[i] + k[i]);
-  if (renorm) {
-    const R r = rsqrt_r(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
-    x[3] *= r;
-    x[4] *= r;
-    x[5] *= r;
-    x[6] *= r;
-  }
+  // a select rather than a branch: multiplying by exactly 1 leaves q as it
+  // is, and the state stays in the same registers on both sides
+  const R rq = rsqrt_r(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+  const R r = renorm ? rq : R(1);
+  x[3] *= r;
+  x[4] *= r;
+  x[5] *= r;
+  x[6] *= r;
 }
 
 // Row-major rotation matrix of q/|q| (Hamilton, body to world).
 __device__ inline void rotmat(const float q[4], float Rm[9]) {
   const float n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-  const float s = 2.0f / n2;
+  const float s = 2.0f * recip_r(n2);
   const float w = q[0], x = q[1], y = q[2], z = q[3];
   Rm[0] = 1.0f - s * (y * y + z * z);
   Rm[1] = s * (x * y - w * z);
@@ -337,9 +342,12 @@ __device__ inline uint32_t episode_end(const DevCfg& c, const float s[NS], int t
       out |= fabsf(s[i]) > c.pos_limit;
       out |= fabsf(s[7 + i]) > c.vel_limit;
     }
-    bool finite = true;
+    // s*0 is NaN exactly when s is infinite or NaN, else a zero: the sum
+    // stays zero only when every state value is finite
+    float z = 0.0f;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) finite &= isfinite(s[i]);
+    for (int i = 0; i < NS; ++i) z = fmaf(s[i], 0.0f, z);
+    const bool finite = z == 0.0f;
     term = (out || !finite) ? 1u : 0u;
   }
   const uint32_t trunc = (!term && c.max_steps > 0 && t_ep >= c.max_steps) ? 2u : 0u;
@@ -390,7 +398,7 @@ __device__ inline void deriv_vjp(const Body<float>& B, const float th[NP], float
   const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const float ox = x[10], oy = x[11], oz = x[12];
   const float n2 = qw * qw + qx * qx + qy * qy + qz * qz;
-  const float inv_n2 = 1.0f / n2;
+  const float inv_n2 = recip_r(n2);
   const float sc = F * B.inv_m * inv_n2;
   // p' = v
   gx[7] += gd[0];
@@ -461,7 +469,8 @@ __device__ inline void deriv_vjp(const Body<float>& B, const float th[NP], float
 __device__ inline void rotmat_vjp(const float q[4], const float G[9], float gq[4]) {
   const float w = q[0], x = q[1], y = q[2], z = q[3];
   const float n2 = w * w + x * x + y * y + z * z;
-  const float s = 2.0f / n2;
+  const float inv_n2 = recip_r(n2);
+  const float s = 2.0f * inv_n2;
   const float dw = -z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7];
   const float dx = y * G[1] + z * G[2] + y * G[3] - 2.0f * x * G[4] - w * G[5] + z * G[6] +
                    w * G[7] - 2.0f * x * G[8];
@@ -472,7 +481,7 @@ __device__ inline void rotmat_vjp(const float q[4], const float G[9], float gq[4
   const float GP = -(y * y + z * z) * G[0] + (x * y - w * z) * G[1] + (x * z + w * y) * G[2] +
                    (x * y + w * z) * G[3] - (x * x + z * z) * G[4] + (y * z - w * x) * G[5] +
                    (x * z - w * y) * G[6] + (y * z + w * x) * G[7] - (x * x + y * y) * G[8];
-  const float k = 2.0f * s * GP / n2;
+  const float k = 2.0f * s * GP * inv_n2;
   gq[0] += s * dw - k * w;
   gq[1] += s * dx - k * x;
   gq[2] += s * dy - k * y;

@@ -12,6 +12,7 @@ namespace qs {
 // applied actions, or the reset fill after a reset), so a later policy step
 // observes exactly what it would have after stepping one by one.
 // ---------------------------------------------------------------------------
+template <bool DIST, bool HELD>
 __global__ void __launch_bounds__(256)
 k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride, int T,
               float* __restrict__ rewards, uint8_t* __restrict__ dones,
@@ -28,16 +29,23 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
   int t_ep = b.t_ep[e], ep = b.ep[e];
-  {
+  if (DIST) {
     float d[6];
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
     set_disturbance(B, d);
   }
+  const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
+  const float ah0 = rpm_to_action(c, wh);
   int last_reset = -1;  // step after which the history was refilled
   float ah = 0.0f;
   if (states)
 #pragma unroll
     for (int i = 0; i < NS; ++i) states[(size_t)i * N + e] = x[i];
+  // the action of the step is loaded one step ahead (held actions: once)
+  if (HELD) a_tstride = 0;
+  float an[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) an[i] = act[(size_t)i * N + e];
   for (int t = 0; t < T; ++t) {
     // per-step opaque env index: keeps the 64-bit output addresses from being
     // hoisted out of the loop and held in registers
@@ -45,10 +53,14 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
     float a[NA], u[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      a[i] = act[((size_t)t * a_tstride + i) * N + eo];
+      a[i] = an[i];
       u[i] = action_to_rpm(c, a[i]);
     }
-    rk4_step<float>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
+    if (!HELD && t + 1 < T) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) an[i] = act[((size_t)(t + 1) * a_tstride + i) * N + eo];
+    }
+    rk4_step<float, DIST>(B, c.arm, c.km, c.g, c.dt, renorm, x, u);
     const float r = reward(c, x, a);
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
@@ -56,10 +68,13 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
       ++ep;
       t_ep = 0;
       last_reset = t;
-      ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], x);
-      float d[6];
-      disturbance(c, (uint32_t)e, (uint32_t)ep, d);
-      set_disturbance(B, d);
+      ah = ah0;
+      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
+      if (DIST) {
+        float d[6];
+        disturbance(c, (uint32_t)e, (uint32_t)ep, d);
+        set_disturbance(B, d);
+      }
     }
     if (rewards) rewards[(size_t)t * N + eo] = r;
     if (dones) dones[(size_t)t * N + eo] = (uint8_t)d;
@@ -94,8 +109,12 @@ static inline unsigned nblk(int n, int bs) { return (unsigned)((n + bs - 1) / bs
 hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* act, int a_tstride,
                               int T, float* rewards, uint8_t* dones, float* states,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_dyn_rollout, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, act,
-                     a_tstride, T, rewards, dones, states);
+  auto k = (c.flags & F_DISTURB) ? (a_tstride ? k_dyn_rollout<true, false>
+                                               : k_dyn_rollout<true, true>)
+                                  : (a_tstride ? k_dyn_rollout<false, false>
+                                               : k_dyn_rollout<false, true>);
+  hipLaunchKernelGGL(k, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, act, a_tstride, T,
+                     rewards, dones, states);
   return hipGetLastError();
 }
 
