@@ -10,9 +10,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f16 __attribute__((ext_vector_type(16)));
 
 // LDS layouts (floats).
-// MFMA: W1 row-major [64][148] (k padded), b1, W2 [64][68], b2, W3 [16][68]
-// (rows 4..15 zero), b3.  Row pitches keep 16-byte alignment and spread the
-// 16 rows one 16-lane group reads over distinct banks.
+// MFMA: W1 row-major [64][148] with b1 in column 0 and feature k in column
+// k + 1 (column 147 zero), b1, W2 [64][68], b2, W3 [16][68] (rows 4..15
+// zero), b3.  Row pitches keep 16-byte alignment and spread the 16 rows one
+// 16-lane group reads over distinct banks.
 constexpr int M_W1_LD = 148, M_W2_LD = 68;
 constexpr int M_W1 = 0, M_B1 = M_W1 + NHID * M_W1_LD, M_W2 = M_B1 + NHID,
               M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + 16 * M_W2_LD,
@@ -29,7 +30,7 @@ __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
   if (MFMA) {
     for (int i = tid; i < NHID * M_W1_LD; i += nt) {
       const int r = i / M_W1_LD, k = i % M_W1_LD;
-      lds[M_W1 + i] = k < NO ? W[OFF_W1 + r * NO + k] : 0.0f;
+      lds[M_W1 + i] = k == 0 ? W[OFF_B1 + r] : k <= NO ? W[OFF_W1 + r * NO + k - 1] : 0.0f;
     }
     for (int i = tid; i < NHID * M_W2_LD; i += nt) {
       const int r = i / M_W2_LD, k = i % M_W2_LD;
@@ -70,36 +71,47 @@ __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
   ((k) < 3 ? s[(k)] : (k) < 12 ? Rm[(k)-3] : (k) < 15 ? s[(k)-12 + 7] : (k) < 18 ? \
    s[(k)-15 + 10] : H[(k)-18])
 
+// ReLU as a signed-integer maximum of the bit pattern: negative floats (and
+// -0) are negative integers, so they become +0 and the rest pass through.
+// One instruction; the float maximum would first quieten its operand.
+__device__ __forceinline__ float relu_bits(float x) {
+  return __int_as_float(max(__float_as_int(x), 0));
+}
+
 // Actor on matrix cores.  Each wave evaluates its 64 envs together:
-//  layer 1: 146 rank-1 updates per 16-neuron tile with the 4-block
-//           16x16x1 fp32 MFMA; B = feature k of the 64 envs (one per lane,
-//           4 blocks of 16 envs), A = weights of 16 neurons broadcast to the
-//           4 blocks.  The result registers hold (neuron, env) tiles.
+//  layer 1: 147 rank-1 updates per 16-neuron tile with the 4-block
+//           16x16x1 fp32 MFMA, the first one the bias (a constant feature
+//           1 on a zero accumulator, so the bias is added first as in the
+//           plain evaluation); B = feature k of the 64 envs (one per lane,
+//           4 blocks of 16 envs), A = weights of 16 neurons broadcast to
+//           the 4 blocks.  The result registers hold (neuron, env) tiles.
 //  layer 2/3: 16x16x4 fp32 MFMA.  A result register of the previous layer is
 //           directly a B operand whose K-chunk is 4 neurons {4g+v}; the
-//           weights are read in the matching order.  Layer 3 uses 4 of 16
-//           rows.
+//           weights are read in the matching order.  The bias tile is the
+//           accumulator input of each chain's first product.  Layer 3 uses
+//           4 of 16 rows.
 //  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
                                   const float H[NH * NA], float z3out[NA]) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
+  const f16 zero16 = {};
   f16 acc1[4];
 #pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc1[n][r] = lds[M_B1 + 16 * n + 4 * lg + (r & 3)];
-#pragma unroll
-  for (int kc = 0; kc < (NO + 3) / 4; ++kc) {
+  for (int kc = 0; kc < M_W1_LD / 4; ++kc) {
     f4 w[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       w[n] = *reinterpret_cast<const f4*>(&lds[M_W1 + (16 * n + li) * M_W1_LD + 4 * kc]);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kc + kk;
-      if (k < NO) {
-        const float x = QS_FEAT(k);
+      const int col = 4 * kc + kk;  // 0: bias, k + 1: feature k
+      if (col == 0) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][0], 1.0f, zero16, 0, 0, 0);
+      } else if (col <= NO) {
+        const float x = QS_FEAT(col - 1);
 #pragma unroll
         for (int n = 0; n < 4; ++n)
           acc1[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], x, acc1[n], 0, 0, 0);
@@ -109,40 +121,34 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
 #pragma unroll
   for (int n = 0; n < 4; ++n)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
+    for (int r = 0; r < 16; ++r) acc1[n][r] = relu_bits(acc1[n][r]);
 
   f4 acc2[4][4];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2)
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = lds[M_B2 + 16 * n2 + 4 * lg + r];
 #pragma unroll
   for (int n = 0; n < 4; ++n)
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2) {
       const f4 w =
           *reinterpret_cast<const f4*>(&lds[M_W2 + (16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
+      const f4 b2 = *reinterpret_cast<const f4*>(&lds[M_B2 + 16 * n2 + 4 * lg]);
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb)
-          acc2[n2][bb] =
-              __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][4 * bb + v], acc2[n2][bb], 0, 0, 0);
+          acc2[n2][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              w[v], acc1[n][4 * bb + v], (n == 0 && v == 0) ? b2 : acc2[n2][bb], 0, 0, 0);
     }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = fmaxf(acc2[n2][bb][r], 0.0f);
+      for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = relu_bits(acc2[n2][bb][r]);
 
+  f4 b3;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) b3[r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
   f4 acc3[4];
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc3[bb][r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) {
     const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + li * M_W2_LD + 16 * n2 + 4 * lg]);
@@ -150,7 +156,8 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
-        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][bb][v], acc3[bb], 0, 0, 0);
+        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            w[v], acc2[n2][bb][v], (n2 == 0 && v == 0) ? b3 : acc3[bb], 0, 0, 0);
   }
   // lanes 0..15 of block bb hold z3[o] of env 16 bb + lane in register o.
   const int src = li << 2;

@@ -162,6 +162,40 @@ __device__ inline void reset_draw(const DevCfg& c, uint32_t env, uint32_t episod
   for (int i = 0; i < 4; ++i) s[13 + i] = wh;
 }
 
+// Start states drawn ahead.  In a wave of many envs, drawing at the moment
+// of a reset runs the draw in every step in which any of the envs resets
+// (most steps).  The fused kernels instead keep each env's next start state
+// (all but the rotor speeds, which start at the hover speed) in registers:
+// a reset takes it, and the envs that used theirs draw the following one
+// together every RESERVE_PERIOD steps.  An env that resets again before its
+// refill draws in place.  The draws are the same counter-based ones either
+// way, so results do not depend on when they are made.
+constexpr int RESERVE_PERIOD = 8;  // power of 2
+constexpr int NRES = NS - NA;      // drawn-ahead state values
+
+__device__ inline void draw_ahead(const DevCfg& c, uint32_t env, uint32_t episode, float wh,
+                                  float nx[NRES]) {
+  float s0[NS];
+  reset_draw(c, env, episode, wh, s0);
+#pragma unroll
+  for (int i = 0; i < NRES; ++i) nx[i] = s0[i];
+}
+
+// Start state of episode `episode`: the reserve if there is one, else drawn.
+__device__ inline void reset_from_reserve(const DevCfg& c, uint32_t env, uint32_t episode,
+                                          float wh, const float nx[NRES], bool& have,
+                                          float s[NS]) {
+  if (have) {
+#pragma unroll
+    for (int i = 0; i < NRES; ++i) s[i] = nx[i];
+#pragma unroll
+    for (int i = NRES; i < NS; ++i) s[i] = wh;
+    have = false;
+  } else {
+    reset_draw(c, env, episode, wh, s);
+  }
+}
+
 // reset_draw with the hover speed of parameters (m, c0, c1, c2); returns the
 // hover action that fills the history.
 __device__ inline float reset_state(const DevCfg& c, uint32_t env, uint32_t episode, float m,

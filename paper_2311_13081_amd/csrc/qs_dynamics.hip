@@ -36,6 +36,11 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
   }
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah0 = rpm_to_action(c, wh);
+  // next episode's start state drawn ahead (long launches only)
+  const bool ahead = T >= 2 * RESERVE_PERIOD;
+  float nx[NRES];
+  bool have = ahead;
+  if (ahead) draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
   int last_reset = -1;  // step after which the history was refilled
   float ah = 0.0f;
   if (states)
@@ -69,12 +74,16 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
       t_ep = 0;
       last_reset = t;
       ah = ah0;
-      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
+      reset_from_reserve(c, (uint32_t)e, (uint32_t)ep, wh, nx, have, x);
       if (DIST) {
         float d[6];
         disturbance(c, (uint32_t)e, (uint32_t)ep, d);
         set_disturbance(B, d);
       }
+    }
+    if (ahead && (t & (RESERVE_PERIOD - 1)) == RESERVE_PERIOD - 1 && !have) {
+      draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
+      have = true;
     }
     if (rewards) rewards[(size_t)t * N + eo] = r;
     if (dones) dones[(size_t)t * N + eo] = (uint8_t)d;

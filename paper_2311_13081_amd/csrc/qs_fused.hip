@@ -62,6 +62,11 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   bool was_reset = false;
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah = rpm_to_action(c, wh);
+  // next episode's start state drawn ahead (long launches only)
+  const bool ahead = T >= 2 * RESERVE_PERIOD;
+  float nx[NRES];
+  bool have = ahead;
+  if (ahead) draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
 
   if (states && t_base == 0 && active)
 #pragma unroll
@@ -129,12 +134,16 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       ++ep;
       t_ep = 0;
       was_reset = true;
-      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
+      reset_from_reserve(c, (uint32_t)e, (uint32_t)ep, wh, nx, have, x);
       if (EXTRAS) {
         float dd[6];
         disturbance(c, (uint32_t)e, (uint32_t)ep, dd);
         set_disturbance(B, dd);
       }
+    }
+    if (ahead && (t & (RESERVE_PERIOD - 1)) == RESERVE_PERIOD - 1 && !have) {
+      draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
+      have = true;
     }
     if (active) {
       if (rewards) rewards[(size_t)gt * N + eo] = r;

@@ -337,6 +337,11 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
     set_disturbance(B, d);
   }
+  // next episode's start state drawn ahead (long launches only)
+  const bool ahead = T >= 2 * RESERVE_PERIOD;
+  float nx[NRES];
+  bool have = ahead;
+  if (ahead) draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
 
   if (states && t_base == 0 && active)
 #pragma unroll
@@ -416,12 +421,16 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       ++ep;
       t_ep = 0;
       was_reset = true;
-      reset_draw(c, (uint32_t)e, (uint32_t)ep, wh, x);
+      reset_from_reserve(c, (uint32_t)e, (uint32_t)ep, wh, nx, have, x);
       if (EXTRAS) {
         float d[6];
         disturbance(c, (uint32_t)e, (uint32_t)ep, d);
         set_disturbance(B, d);
       }
+    }
+    if (ahead && (t & (RESERVE_PERIOD - 1)) == RESERVE_PERIOD - 1 && !have) {
+      draw_ahead(c, (uint32_t)e, (uint32_t)(ep + 1), wh, nx);
+      have = true;
     }
     if (active) {
       if (k == 0 && rewards) rewards[(size_t)gt * N + eo] = r;

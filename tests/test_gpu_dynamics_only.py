@@ -99,3 +99,31 @@ def test_constant_actions_short_rollout_keeps_old_history(pkg):
     for s in range(32 - T, 32):
         assert np.array_equal(hg[s], np_(a))
     sim.close()
+
+
+@pytest.mark.parametrize("max_steps", [1, 3, 9])
+def test_short_episodes_long_launch_equals_single_steps(pkg, max_steps):
+    """Episodes of 1, 3 or 9 steps inside one 96-step launch (envs reset
+    again before the drawn-ahead start states are refilled) against 96
+    one-step launches of the same kernel, which draw in place: bitwise."""
+    n, T = 999, 96
+    flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, flags=flags, max_episode_steps=max_steps)
+    A = torch.as_tensor(np.stack([wl.random_actions(n, seed=300 + t) for t in range(T)])).cuda()
+    sim = pkg.QuadSim(cfg)
+    st0 = {k: v.clone() for k, v in sim.get_state().items()}
+    out = sim.rollout_actions(A, T)
+    one = {k: np_(v) for k, v in sim.get_state().items()}
+    one.update({k: np_(v) for k, v in out.items()})
+    assert (one["dones"] != 0).sum() >= n * (T // max_steps) // 2
+    sim.set_state(**st0)
+    r, d = [], []
+    for t in range(T):
+        o = sim.rollout_actions(A[t:t + 1], 1)   # per-step form, as above
+        r.append(np_(o["rewards"])[0])
+        d.append(np_(o["dones"])[0])
+    many = {k: np_(v) for k, v in sim.get_state().items()}
+    many.update(rewards=np.stack(r), dones=np.stack(d))
+    for k in one:
+        assert np.array_equal(one[k], many[k], equal_nan=True), (max_steps, k)
+    sim.close()

@@ -319,6 +319,24 @@ def test_chunked_and_graph_launches_are_bitwise_equal(pkg, variant):
             assert np.array_equal(base[k], other[k], equal_nan=True), (spl, graph, k)
 
 
+@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4"])
+@pytest.mark.parametrize("max_steps", [1, 3, 9])
+def test_short_episodes_long_launch_equals_single_steps(pkg, variant, max_steps):
+    """Episodes of 1, 3 or 9 steps (truncation) reset every env again and
+    again inside one long launch, also twice between two refills of the
+    drawn-ahead start states: bitwise equal to one launch per step, which
+    draws every start state in place."""
+    n, T = 777, 96
+    flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, flags=flags, max_episode_steps=max_steps)
+    W = wl.xavier_actor(0)
+    base = _run(pkg, cfg, variant, 1, False, T, W)
+    assert (base["dones"] & 2).sum() >= n * (T // max_steps) // 2
+    one = _run(pkg, cfg, variant, 0, True, T, W)
+    for k in base:
+        assert np.array_equal(base[k], one[k], equal_nan=True), (max_steps, k)
+
+
 def test_plain_graph_equals_eager(pkg):
     n, T = 500, 40
     cfg = wl.crazyflie_config(n_envs=n, flags=wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET)
