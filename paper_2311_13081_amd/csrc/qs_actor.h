@@ -11,12 +11,11 @@ typedef float f16 __attribute__((ext_vector_type(16)));
 
 // LDS layouts (floats).
 // MFMA: W1 row-major [64][148] with b1 in column 0 and feature k in column
-// k + 1 (column 147 zero), b1, W2 [64][68], b2, W3 [16][68] (rows 4..15
-// zero), b3.  Row pitches keep 16-byte alignment and spread the 16 rows one
+// k + 1 (column 147 zero), b1, W2 [64][68], b2, W3 [4][68], b3.  Row pitches keep 16-byte alignment and spread the 16 rows one
 // 16-lane group reads over distinct banks.
 constexpr int M_W1_LD = 148, M_W2_LD = 68;
 constexpr int M_W1 = 0, M_B1 = M_W1 + NHID * M_W1_LD, M_W2 = M_B1 + NHID,
-              M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + 16 * M_W2_LD,
+              M_B2 = M_W2 + NHID * M_W2_LD, M_W3 = M_B2 + NHID, M_B3 = M_W3 + NA * M_W2_LD,
               M_TOTAL = M_B3 + 4;
 // VALU: transposed weights so consecutive outputs are consecutive floats.
 constexpr int V_W1T = 0, V_B1 = V_W1T + NO * NHID, V_W2T = V_B1 + NHID,
@@ -36,9 +35,9 @@ __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
       const int r = i / M_W2_LD, k = i % M_W2_LD;
       lds[M_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
     }
-    for (int i = tid; i < 16 * M_W2_LD; i += nt) {
+    for (int i = tid; i < NA * M_W2_LD; i += nt) {
       const int r = i / M_W2_LD, k = i % M_W2_LD;
-      lds[M_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
+      lds[M_W3 + i] = k < NHID ? W[OFF_W3 + r * NHID + k] : 0.0f;
     }
     for (int i = tid; i < NHID; i += nt) {
       lds[M_B1 + i] = W[OFF_B1 + i];
@@ -85,12 +84,17 @@ __device__ __forceinline__ float relu_bits(float x) {
 //           plain evaluation); B = feature k of the 64 envs (one per lane,
 //           4 blocks of 16 envs), A = weights of 16 neurons broadcast to
 //           the 4 blocks.  The result registers hold (neuron, env) tiles.
-//  layer 2/3: 16x16x4 fp32 MFMA.  A result register of the previous layer is
-//           directly a B operand whose K-chunk is 4 neurons {4g+v}; the
-//           weights are read in the matching order.  The bias tile is the
-//           accumulator input of each chain's first product.  Layer 3 uses
-//           4 of 16 rows.
-//  The 4 outputs are moved back to one env per lane with 16 lane shuffles.
+//  layer 2:  16x16x4 fp32 MFMA.  A result register of layer 1 is directly a
+//           B operand whose K-chunk is 4 neurons {4g+v}; the weights are
+//           read in the matching order.  The bias tile is the accumulator
+//           input of each chain's first product.
+//  layer 3:  16-block 4x4x1 fp32 MFMA, one per layer-2 result register:
+//           block b (lanes 4b..4b+3) takes that register's neuron for its
+//           lane group g = b/4 and its 4 envs as B, the 4 output weights of
+//           that neuron as A (row o = lane & 3), so no product is padding.
+//           Each lane group ends with a partial sum over its quarter of the
+//           neurons; two swap-and-add rounds across 32 and 16 lanes add the
+//           quarters and leave output o of env (lane) in every lane.
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
                                   const float H[NH * NA], float z3out[NA]) {
   const int lane = threadIdx.x & 63;
@@ -145,29 +149,38 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc2[n2][bb][r] = relu_bits(acc2[n2][bb][r]);
 
+  // the bias enters once, in lane group 0's partial sums
   f4 b3;
 #pragma unroll
   for (int r = 0; r < 4; ++r) b3[r] = lg == 0 ? lds[M_B3 + r] : 0.0f;
-  f4 acc3[4];
+  f4 acc3[4];  // [bb]: register o = output o, partial over lane group lg
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) {
-    const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + li * M_W2_LD + 16 * n2 + 4 * lg]);
+    const f4 w = *reinterpret_cast<const f4*>(&lds[M_W3 + (lane & 3) * M_W2_LD + 16 * n2 + 4 * lg]);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
-        acc3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+        acc3[bb] = __builtin_amdgcn_mfma_f32_4x4x1f32(
             w[v], acc2[n2][bb][v], (n2 == 0 && v == 0) ? b3 : acc3[bb], 0, 0, 0);
   }
-  // lanes 0..15 of block bb hold z3[o] of env 16 bb + lane in register o.
-  const int src = li << 2;
+  // Lane 16 g + i holds, for each bb, output o of env 16 bb + i summed over
+  // the neurons of lane group g.  Swapping the upper 32 lanes of bb with the
+  // lower 32 of bb + 2 and adding gives groups {0,2} and {1,3} of bb in the
+  // lower half and of bb + 2 in the upper half; swapping the odd 16-lane rows
+  // of (0,2) with the even rows of (1,3) and adding completes the sums with
+  // row g holding bb = g, the env of the lane itself.
 #pragma unroll
   for (int o = 0; o < NA; ++o) {
-    float v[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-      v[bb] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[bb][o])));
-    z3out[o] = lg == 0 ? v[0] : lg == 1 ? v[1] : lg == 2 ? v[2] : v[3];
+    const auto p02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc3[0][o]),
+                                                      __float_as_uint(acc3[2][o]), false, false);
+    const auto p13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc3[1][o]),
+                                                      __float_as_uint(acc3[3][o]), false, false);
+    const float z02 = __uint_as_float(p02[0]) + __uint_as_float(p02[1]);
+    const float z13 = __uint_as_float(p13[0]) + __uint_as_float(p13[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(z02), __float_as_uint(z13),
+                                                    false, false);
+    z3out[o] = __uint_as_float(q[0]) + __uint_as_float(q[1]);
   }
 }
 
