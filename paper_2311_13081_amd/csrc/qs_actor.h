@@ -70,13 +70,6 @@ __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
   ((k) < 3 ? s[(k)] : (k) < 12 ? Rm[(k)-3] : (k) < 15 ? s[(k)-12 + 7] : (k) < 18 ? \
    s[(k)-15 + 10] : H[(k)-18])
 
-// ReLU as a signed-integer maximum of the bit pattern: negative floats (and
-// -0) are negative integers, so they become +0 and the rest pass through.
-// One instruction; the float maximum would first quieten its operand.
-__device__ __forceinline__ float relu_bits(float x) {
-  return __int_as_float(max(__float_as_int(x), 0));
-}
-
 // Actor on matrix cores.  Each wave evaluates its 64 envs together:
 //  layer 1: 147 rank-1 updates per 16-neuron tile with the 4-block
 //           16x16x1 fp32 MFMA, the first one the bias (a constant feature

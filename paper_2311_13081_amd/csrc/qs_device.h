@@ -406,6 +406,13 @@ __device__ inline float tanh_act(float x) {
   return copysignf(t, x);
 }
 
+// ReLU as a signed-integer maximum of the bit pattern: negative floats (and
+// -0) are negative integers, so they become +0 and the rest pass through.
+// One instruction; the float maximum would first quieten its operand.
+__device__ __forceinline__ float relu_bits(float x) {
+  return __int_as_float(max(__float_as_int(x), 0));
+}
+
 __device__ inline float action_to_rpm(const DevCfg& c, float a) {
   return c.rpm_min + (a + 1.0f) * c.rpm_half_range;
 }

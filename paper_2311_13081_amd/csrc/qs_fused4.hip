@@ -2,7 +2,7 @@
 // and each env occupies 4 lanes (lane L = j + 16 k: env j of the wave,
 // quarter k).  Compared with the one-env-per-lane kernel this quadruples the
 // number of waves for a given batch (so small batches fill the chip and large
-// ones keep two waves per SIMD to overlap matrix-core and vector work) and
+// ones keep two waves per SIMD, whose vector instructions interleave) and
 // cuts the per-lane history from 128 to 32 registers.
 //
 // Observation layout across the 4 lanes of an env: register c of quarter k
@@ -12,9 +12,11 @@
 //   c = 5..36: action history slot c-5 (oldest first), component k.
 // This is exactly the B operand of v_mfma_f32_16x16x4f32 for 16 envs with
 // K-chunk c, so layer 1 is 37 x 4 MFMAs against W1 columns read in PHI order
-// (zeros for padding).  Layers 2 and 3 chain through the result registers as
-// in the one-env-per-lane kernel; the 4 actions of env j are broadcast to its
-// 4 lanes with 4 lane shuffles.  The dynamics run replicated on the 4 lanes
+// (zeros for padding).  Layer 2 chains through the result registers as in
+// the one-env-per-lane kernel; layer 3 is one 16-block 4x4x1 MFMA per layer-2
+// result register, and two swap-and-add rounds across 32 and 16 lanes add
+// the lane groups' partial sums and leave the 4 actions of env j in all 4 of
+// its lanes.  The dynamics run replicated on the 4 lanes
 // (identical inputs, identical arithmetic, identical results); memory writes
 // are split among the lanes.
 //
@@ -36,7 +38,7 @@ constexpr int Q_CP = 40;         // padded to whole float4s
 constexpr int Q_W1_P = 44;       // LDS pitch of one (quarter, neuron) row: 8 consecutive
                                  // lanes' 16-byte reads land on distinct banks
 constexpr int Q_W1 = 0, Q_B1 = Q_W1 + NHID * 4 * Q_W1_P, Q_W2 = Q_B1 + NHID,
-              Q_B2 = Q_W2 + NHID * 68, Q_W3 = Q_B2 + NHID, Q_B3 = Q_W3 + 16 * 68,
+              Q_B2 = Q_W2 + NHID * 68, Q_W3 = Q_B2 + NHID, Q_B3 = Q_W3 + NA * 68,
               Q_TOTAL = Q_B3 + 4;
 
 // Observation feature of chunk c, quarter k (or -1 for padding).
@@ -56,9 +58,9 @@ __device__ inline void stage_q(const float* __restrict__ W, float* lds) {
     const int r = i / 68, k = i % 68;
     lds[Q_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
   }
-  for (int i = tid; i < 16 * 68; i += nt) {
+  for (int i = tid; i < NA * 68; i += nt) {
     const int r = i / 68, k = i % 68;
-    lds[Q_W3 + i] = (r < NA && k < NHID) ? W[OFF_W3 + r * NHID + k] : 0.0f;
+    lds[Q_W3 + i] = k < NHID ? W[OFF_W3 + r * NHID + k] : 0.0f;
   }
   for (int i = tid; i < NHID; i += nt) {
     lds[Q_B1 + i] = W[OFF_B1 + i];
@@ -75,11 +77,8 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
                                float* __restrict__ rz1, float* __restrict__ rz2, int N,
                                int env0, uint32_t rec_lane_off) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  // bias tiles enter as the accumulator input of each chain's first product
   f4q acc1[4];
-#pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc1[n][r] = lds[Q_B1 + 16 * n + 4 * lg + r];
 #pragma unroll
   for (int cc = 0; cc < Q_CP / 4; ++cc) {
     f4q w[4];
@@ -93,7 +92,10 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
       if (c < Q_C) {
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[n][q], F[c], acc1[n], 0, 0, 0);
+          acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              w[n][q], F[c],
+              c == 0 ? *reinterpret_cast<const f4q*>(&lds[Q_B1 + 16 * n + 4 * lg]) : acc1[n], 0,
+              0, 0);
       }
     }
   }
@@ -107,20 +109,18 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
 #pragma unroll
   for (int n = 0; n < 4; ++n)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc1[n][r] = fmaxf(acc1[n][r], 0.0f);
+    for (int r = 0; r < 4; ++r) acc1[n][r] = relu_bits(acc1[n][r]);
   f4q acc2[4];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc2[n2][r] = lds[Q_B2 + 16 * n2 + 4 * lg + r];
 #pragma unroll
   for (int n = 0; n < 4; ++n)
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2) {
       const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W2 + (16 * n2 + li) * 68 + 16 * n + 4 * lg]);
+      const f4q b2 = *reinterpret_cast<const f4q*>(&lds[Q_B2 + 16 * n2 + 4 * lg]);
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        acc2[n2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][v], acc2[n2], 0, 0, 0);
+        acc2[n2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc1[n][v],
+                                                        (n == 0 && v == 0) ? b2 : acc2[n2], 0, 0, 0);
     }
   if (rz2 && env < N) {
 #pragma unroll
@@ -131,22 +131,35 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc2[n2][r] = fmaxf(acc2[n2][r], 0.0f);
+    for (int r = 0; r < 4; ++r) acc2[n2][r] = relu_bits(acc2[n2][r]);
+  // layer 3: block b (lanes 4b..4b+3) takes the neuron of lane group b/4 and
+  // envs 4(b%4)..+3, A = that neuron's 4 output weights (row o = lane & 3);
+  // the bias enters once, in lane group 0's partial sums
+  f4q b3;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) b3[r] = lg == 0 ? lds[Q_B3 + r] : 0.0f;
   f4q acc3;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) acc3[r] = lg == 0 ? lds[Q_B3 + r] : 0.0f;
-#pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) {
-    const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W3 + li * 68 + 16 * n2 + 4 * lg]);
+    const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W3 + (lane & 3) * 68 + 16 * n2 + 4 * lg]);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], acc2[n2][v], acc3, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_4x4x1f32(w[v], acc2[n2][v],
+                                                (n2 == 0 && v == 0) ? b3 : acc3, 0, 0, 0);
   }
-  // lane li of quarter 0 holds z3[o] of env li in register o
-  const int src = li << 2;
+  // Lane li + 16 g holds output o of env li summed over lane group g's
+  // neurons.  A swap of the register with itself across 32 lanes and an add
+  // sum groups {0,2} and {1,3}; the same across 16 lanes completes the sum,
+  // the same value (same operands, same order) in all 4 lanes of env li.
 #pragma unroll
-  for (int o = 0; o < NA; ++o)
-    z3[o] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[o])));
+  for (int o = 0; o < NA; ++o) {
+    const uint32_t x = __float_as_uint(acc3[o]);
+    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    const float z = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(z), __float_as_uint(z),
+                                                    false, false);
+    z3[o] = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -278,8 +291,10 @@ __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[N
     z3[o] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc3[o])));
 }
 
-// Two waves per SIMD (256 registers each) so one wave's vector work overlaps
-// the other's matrix-core work.
+// Two waves per SIMD (256 registers each): one wave alone issues vector
+// instructions at about half the rate the SIMD can execute them, two
+// interleave theirs (matrix-core and vector instructions do not overlap,
+// within a wave or across the two).
 template <bool BF16, bool EXTRAS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
