@@ -41,7 +41,21 @@ FLOP_PER_ENV_STEP = 28_500
 # writes a ring slot, counters, state, reward and done (97 B).
 PLAIN_BYTES_PER_ENV_STEP = 1160 + 840 + 512 + 272 + 225
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
+PEAK_BF16_MFMA = 2.5e15        # dense bf16 matrix FLOP/s
+PEAK_FP32_VALU = 78.6e12       # fp32 vector FLOP/s without packed instructions
 PEAK_HBM = 8.0e12
+ACTOR_GEMM_FLOP = 27_392      # the forward actor's three GEMMs, per env step
+# Dynamics-only env step: four right-hand sides (about 103 FLOP each: rotor
+# thrusts, force and torques, quaternion rate, acceleration, Euler, motor
+# lag), the RK4 combinations (221), renormalisation (12), action map (8) and
+# reward (35).
+DYN_FLOP_PER_ENV_STEP = 700
+# Algorithmic work per env step of forward + backward (no recompute counted):
+# the forward (28.5 kFLOP), the actor's input VJP and weight gradient (27392
+# FLOP each) and the dynamics VJP (about 2.4 kFLOP).  Of it, the actor's
+# three GEMMs (3 x 27392) run on matrix cores; the rest is scalar fp32.
+FLOP_FWD_BWD_ENV_STEP = 28_500 + 2 * 27_392 + 2_400
+ACTOR_GEMM_FLOP_FWD_BWD = 3 * 27_392
 
 
 TRAFFIC_PROFILES = {
@@ -92,7 +106,7 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (3 times): the "
                          "reference for scaling HBM traffic counters")
-    ap.add_argument("--variant", default="auto", choices=["auto", "mfma4", "mfma", "valu"],
+    ap.add_argument("--variant", default="auto", choices=["auto", "mfma4", "mfma", "valu", "split"],
                     help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
                          "per rollout (used for profiling so only timed launches appear)")
     return ap.parse_args()
@@ -229,8 +243,21 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     sim.close()
-    return {"env_steps_per_s": N * H / dt, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
-            "horizon": H, "ckpt_every": cfg["ckpt_every"], "actor": "bf16" if bf16 else "f32"}
+    rate = N * H / dt
+    if bf16:
+        # actor GEMMs on bf16 matrix cores, the scalar rest on fp32 vector ALUs
+        t_roof = (ACTOR_GEMM_FLOP_FWD_BWD / PEAK_BF16_MFMA
+                  + (FLOP_FWD_BWD_ENV_STEP - ACTOR_GEMM_FLOP_FWD_BWD) / PEAK_FP32_VALU)
+        roof = {"bound": "bf16 mfma + fp32 valu", "roof_env_steps_per_s": 1.0 / t_roof,
+                "frac": rate * t_roof}
+    else:
+        ach = rate * FLOP_FWD_BWD_ENV_STEP / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA}
+    roof["flop_per_env_step"] = FLOP_FWD_BWD_ENV_STEP
+    return {"env_steps_per_s": rate, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
+            "horizon": H, "ckpt_every": cfg["ckpt_every"], "actor": "bf16" if bf16 else "f32",
+            "roofline": roof}
 
 
 def fixed_episodes(torch, pkg, actor):
@@ -255,7 +282,7 @@ def fixed_episodes(torch, pkg, actor):
         if variant is None:
             v, s, g = sim.get_variant()
             res[label]["variant"] = {1: "plain", 2: "fused_valu", 3: "fused_mfma",
-                                     4: "fused_mfma4"}[v]
+                                     4: "fused_mfma4", 5: "fused_split"}[v]
             res[label]["steps_per_launch"] = s
         sim.close()
     return res
@@ -279,8 +306,13 @@ def dynamics_only(torch, pkg, n_envs, T, reps=3):
     dt = (time.perf_counter() - t0) / reps
     kernel_ms, _ = sim.last_rollout_timing()
     sim.close()
+    rate = n_envs * T / (kernel_ms * 1e-3)
     return {"env_steps_per_s": n_envs * T / dt, "n_envs": n_envs, "rollout_steps": T,
-            "ms_per_rollout": dt * 1e3, "kernel_ms": kernel_ms}
+            "ms_per_rollout": dt * 1e3, "kernel_ms": kernel_ms,
+            "roofline": {"bound": "valu", "achieved": rate * DYN_FLOP_PER_ENV_STEP / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": rate * DYN_FLOP_PER_ENV_STEP / PEAK_FP32_VALU,
+                         "waves": (n_envs + 63) // 64, "simds": 1024}}
 
 
 def main():
@@ -313,7 +345,8 @@ def main():
         sim.autotune(actor, T)
     else:
         sim.set_variant({"mfma4": pkg.SIM_V_FUSED_MFMA4, "mfma": pkg.SIM_V_FUSED_MFMA,
-                         "valu": pkg.SIM_V_FUSED_VALU}[args.variant], 0, True)
+                         "valu": pkg.SIM_V_FUSED_VALU, "split": pkg.SIM_V_FUSED_SPLIT}[args.variant],
+                        0, True)
     v, spl, graph = sim.get_variant()
     wall, dev_ms, launches = time_rollouts(torch, sim, actor, T, args.steps, args.warmup)
     env_steps = N * T * args.steps
@@ -322,9 +355,9 @@ def main():
     kernel_ms = dev_ms / (args.steps * launches)
     flop_per_launch = FLOP_PER_ENV_STEP * N * (T / launches)
     achieved = flop_per_launch / (kernel_ms * 1e-3)
-    vname = {1: "plain", 2: "fused_valu", 3: "fused_mfma", 4: "fused_mfma4"}[v]
+    vname = {1: "plain", 2: "fused_valu", 3: "fused_mfma", 4: "fused_mfma4", 5: "fused_split"}[v]
     kname = {1: "plain (5 kernels)", 2: "k_fused<VALU>", 3: "k_fused<MFMA>",
-             4: "k_fused4<MFMA>"}[v]
+             4: "k_fused4<MFMA>", 5: "k_split<MFMA>"}[v]
     res = {
         "metric": METRIC,
         "value": value,
@@ -384,8 +417,11 @@ def main():
         s5 = pkg.QuadSim(cfg_b)
         s5.autotune(actor, T)
         w5, d5, l5 = time_rollouts(torch, s5, actor, T, 2, 1)
-        extras["headline_bf16_actor"] = {"env_steps_per_s": N * T * 2 / w5,
-                                         "kernel_ms": d5 / (2 * l5)}
+        t_roof = ACTOR_GEMM_FLOP / PEAK_BF16_MFMA + (FLOP_PER_ENV_STEP - ACTOR_GEMM_FLOP) / PEAK_FP32_VALU
+        extras["headline_bf16_actor"] = {
+            "env_steps_per_s": N * T * 2 / w5, "kernel_ms": d5 / (2 * l5),
+            "roofline": {"bound": "bf16 mfma + fp32 valu", "roof_env_steps_per_s": 1.0 / t_roof,
+                         "frac": N * T * 2 / w5 * t_roof}}
         s5.close()
         # the headline workload with the training extras (per-episode
         # disturbance and actor observation noise), and the FP64 path

@@ -110,9 +110,14 @@ enum {
   SIM_V_FUSED_VALU = 2,  /* one fused kernel, actor on the vector ALUs            */
   SIM_V_FUSED_MFMA = 3,  /* one fused kernel, actor on fp32 matrix cores, one env
                             per lane (64 envs per wave)                           */
-  SIM_V_FUSED_MFMA4 = 4  /* one fused kernel, actor on fp32 matrix cores, four
+  SIM_V_FUSED_MFMA4 = 4, /* one fused kernel, actor on fp32 matrix cores, four
                             lanes per env (16 envs per wave); also the kernel of
                             taped rollouts and of the backward recompute          */
+  SIM_V_FUSED_SPLIT = 5  /* one fused kernel, the quarter-lane actor split by
+                            neuron tile over the 4 waves of a workgroup (16 envs
+                            per workgroup, 16 lanes per env): four times the
+                            waves of SIM_V_FUSED_MFMA4 for small batches; fp32
+                            actor only, untaped rollouts and steps           */
 };
 
 typedef struct sim_config {

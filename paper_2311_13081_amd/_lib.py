@@ -20,6 +20,7 @@ SIM_OK, SIM_E_INVAL, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE, SIM_E_UNSUPPORTED =
 SIM_F_TERMINATE, SIM_F_AUTORESET, SIM_F_RENORM_Q, SIM_F_FP64, SIM_F_ACTOR_BF16 = 1, 2, 4, 8, 16
 SIM_F_DISTURB, SIM_F_OBS_NOISE = 32, 64
 SIM_V_AUTO, SIM_V_PLAIN, SIM_V_FUSED_VALU, SIM_V_FUSED_MFMA, SIM_V_FUSED_MFMA4 = 0, 1, 2, 3, 4
+SIM_V_FUSED_SPLIT = 5
 
 EXPORTS = (
     "sim_create", "sim_destroy", "sim_reset", "sim_step", "sim_rollout", "sim_backward",

@@ -266,6 +266,8 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
       if (variant == SIM_V_FUSED_MFMA4)
         HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
                               st));
+      else if (variant == SIM_V_FUSED_SPLIT)
+        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, st));
       else
         HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
@@ -427,6 +429,8 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
   } else if (v == SIM_V_FUSED_MFMA4 && actor) {
     HIP_TRY(launch_fused4(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr,
                           h->cfg.ckpt_every, nullptr, nullptr, st));
+  } else if (v == SIM_V_FUSED_SPLIT && actor) {
+    HIP_TRY(launch_split(h->dc, h->b, actor, 1, 0, reward, done, nullptr, st));
   } else {
     // external actions run on the one-env-per-lane kernel (it has the
     // action-input path); both kernels share the state layout
@@ -632,7 +636,7 @@ int sim_set_params(sim_handle* h, const float* theta, void* stream) {
 
 int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
-  if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_MFMA4)
+  if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_SPLIT)
     return fail(SIM_E_INVAL, "unknown variant %d", variant);
   if (steps_per_launch < 0) return fail(SIM_E_INVAL, "steps_per_launch < 0");
   if (h->bf16 && variant != SIM_V_AUTO && variant != SIM_V_FUSED_MFMA4)
@@ -674,7 +678,8 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   HIP_TRY(launch_get_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
   struct Cand { int v, spl; };
   std::vector<Cand> cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0},
-                             {SIM_V_FUSED_MFMA4, 100}, {SIM_V_FUSED_MFMA, 100},
+                             {SIM_V_FUSED_SPLIT, 0}, {SIM_V_FUSED_MFMA4, 100},
+                             {SIM_V_FUSED_MFMA, 100}, {SIM_V_FUSED_SPLIT, 100},
                              {SIM_V_FUSED_VALU, 0},  {SIM_V_PLAIN, 0}};
   if (h->bf16) cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA4, 100}};
   const int save_v = h->variant, save_spl = h->spl;

@@ -65,6 +65,10 @@ hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, i
 hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                          float* rewards, uint8_t* dones, float* states, float* tape,
                          int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
+// Split-actor fused kernel (qs_split.hip): 16 envs per workgroup of 4 waves,
+// wave w evaluating neuron tile w of layers 1 and 2; no tape or record mode.
+hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
+                        float* rewards, uint8_t* dones, float* states, hipStream_t st);
 // One-env-per-lane fused kernel (qs_fused.hip), actor on fp32 MFMA or VALU.
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,

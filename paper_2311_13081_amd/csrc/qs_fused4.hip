@@ -25,49 +25,12 @@
 // v_mfma_f32_16x16x32_bf16; accumulation, biases, activations and the whole
 // dynamics stay fp32.  The same quarter layout serves: one bf16 instruction
 // takes 8 consecutive chunks of the lane's quarter as its 8 K-elements.
-#include "qs_device.h"
 #include "qs_forward.h"
+#include "qs_quarter.h"
 
 namespace qs {
 
-typedef float f4q __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8q __attribute__((ext_vector_type(8)));
-
-constexpr int Q_C = 37;          // K-chunks of layer 1
-constexpr int Q_CP = 40;         // padded to whole float4s
-constexpr int Q_W1_P = 44;       // LDS pitch of one (quarter, neuron) row: 8 consecutive
-                                 // lanes' 16-byte reads land on distinct banks
-constexpr int Q_W1 = 0, Q_B1 = Q_W1 + NHID * 4 * Q_W1_P, Q_W2 = Q_B1 + NHID,
-              Q_B2 = Q_W2 + NHID * 68, Q_W3 = Q_B2 + NHID, Q_B3 = Q_W3 + NA * 68,
-              Q_TOTAL = Q_B3 + 4;
-
-// Observation feature of chunk c, quarter k (or -1 for padding).
-__host__ __device__ constexpr int q_phi(int c, int k) {
-  return c < 5 ? (4 * c + k < 18 ? 4 * c + k : -1) : 18 + 4 * (c - 5) + k;
-}
-
-__device__ inline void stage_q(const float* __restrict__ W, float* lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  // W1 in PHI order: [quarter][neuron][chunk], pitch Q_W1_P
-  for (int idx = tid; idx < NHID * 4 * Q_W1_P; idx += nt) {
-    const int c = idx % Q_W1_P, rest = idx / Q_W1_P, nrn = rest % NHID, k = rest / NHID;
-    const int f = c < Q_C ? q_phi(c, k) : -1;
-    lds[Q_W1 + idx] = f >= 0 ? W[OFF_W1 + nrn * NO + f] : 0.0f;
-  }
-  for (int i = tid; i < NHID * 68; i += nt) {
-    const int r = i / 68, k = i % 68;
-    lds[Q_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
-  }
-  for (int i = tid; i < NA * 68; i += nt) {
-    const int r = i / 68, k = i % 68;
-    lds[Q_W3 + i] = k < NHID ? W[OFF_W3 + r * NHID + k] : 0.0f;
-  }
-  for (int i = tid; i < NHID; i += nt) {
-    lds[Q_B1 + i] = W[OFF_B1 + i];
-    lds[Q_B2 + i] = W[OFF_B2 + i];
-  }
-  for (int i = tid; i < NA; i += nt) lds[Q_B3 + i] = W[OFF_B3 + i];
-}
 
 // Actor for the wave's 16 envs.  F: this lane's 37 layer-1 operands.  Returns
 // z3 (pre-tanh) of this lane's env in every lane.  When rz1/rz2 are given,
@@ -132,34 +95,7 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc2[n2][r] = relu_bits(acc2[n2][r]);
-  // layer 3: block b (lanes 4b..4b+3) takes the neuron of lane group b/4 and
-  // envs 4(b%4)..+3, A = that neuron's 4 output weights (row o = lane & 3);
-  // the bias enters once, in lane group 0's partial sums
-  f4q b3;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) b3[r] = lg == 0 ? lds[Q_B3 + r] : 0.0f;
-  f4q acc3;
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) {
-    const f4q w = *reinterpret_cast<const f4q*>(&lds[Q_W3 + (lane & 3) * 68 + 16 * n2 + 4 * lg]);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      acc3 = __builtin_amdgcn_mfma_f32_4x4x1f32(w[v], acc2[n2][v],
-                                                (n2 == 0 && v == 0) ? b3 : acc3, 0, 0, 0);
-  }
-  // Lane li + 16 g holds output o of env li summed over lane group g's
-  // neurons.  A swap of the register with itself across 32 lanes and an add
-  // sum groups {0,2} and {1,3}; the same across 16 lanes completes the sum,
-  // the same value (same operands, same order) in all 4 lanes of env li.
-#pragma unroll
-  for (int o = 0; o < NA; ++o) {
-    const uint32_t x = __float_as_uint(acc3[o]);
-    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    const float z = __uint_as_float(p[0]) + __uint_as_float(p[1]);
-    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(z), __float_as_uint(z),
-                                                    false, false);
-    z3[o] = __uint_as_float(q[0]) + __uint_as_float(q[1]);
-  }
+  layer3_q(lds, acc2, z3);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,17 +318,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       }
     }
     // observation state part: 18 features, this quarter keeps 4c + k
-    float Rm[9];
-    rotmat(x + 3, Rm);
-    {
-      float sf[20] = {x[0], x[1], x[2], Rm[0], Rm[1], Rm[2], Rm[3], Rm[4], Rm[5], Rm[6],
-                      Rm[7], Rm[8], x[7], x[8], x[9], x[10], x[11], x[12], 0.0f, 0.0f};
-      if (EXTRAS) add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, sf);
-#pragma unroll
-      for (int cc = 0; cc < 5; ++cc)
-        F[cc] = k == 0 ? sf[4 * cc] : k == 1 ? sf[4 * cc + 1] : k == 2 ? sf[4 * cc + 2]
-                                                                        : sf[4 * cc + 3];
-    }
+    quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F);
     float* rt = rec_on ? rec + (size_t)t * REC_F * rb_pad(N) : nullptr;
     float z3[NA];
     // per-lane part of record addresses, recomputed every step (see opaque())

@@ -15,7 +15,7 @@ from parity import STEP_TOL, TRAJ_TOL, max_state_err, reward_err, state_err
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-VARIANTS = {"plain": 1, "valu": 2, "mfma": 3, "mfma4": 4}
+VARIANTS = {"plain": 1, "valu": 2, "mfma": 3, "mfma4": 4, "split": 5}
 
 
 @pytest.fixture(scope="module")
@@ -113,7 +113,7 @@ def test_fp64_trajectory_with_extras_and_resets(pkg, oracle_lib):
     sim.close()
 
 
-@pytest.mark.parametrize("variant", ["mfma", "mfma4"])
+@pytest.mark.parametrize("variant", ["mfma", "mfma4", "split"])
 def test_fp32_episodes_with_extras(pkg, oracle_lib, variant):
     """Fused kernels over 150 steps with resets: per-step parity from the
     GPU's own snapshots (the fp32 bar), done flags bit-exact."""

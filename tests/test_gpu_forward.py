@@ -16,7 +16,7 @@ from parity import (ENVELOPE_FACTOR, STEP_TOL, TRAJ_TOL, box_margin, max_state_e
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-VARIANTS = {"plain": 1, "valu": 2, "mfma": 3, "mfma4": 4}
+VARIANTS = {"plain": 1, "valu": 2, "mfma": 3, "mfma4": 4, "split": 5}
 
 
 @pytest.fixture(scope="module")
@@ -305,7 +305,7 @@ def _run(pkg, cfg, variant, spl, graph, T, W):
     return res
 
 
-@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4"])
+@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4", "split"])
 def test_chunked_and_graph_launches_are_bitwise_equal(pkg, variant):
     n, T = 1000, 300
     flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
@@ -319,7 +319,7 @@ def test_chunked_and_graph_launches_are_bitwise_equal(pkg, variant):
             assert np.array_equal(base[k], other[k], equal_nan=True), (spl, graph, k)
 
 
-@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4"])
+@pytest.mark.parametrize("variant", ["mfma", "valu", "mfma4", "split"])
 @pytest.mark.parametrize("max_steps", [1, 3, 9])
 def test_short_episodes_long_launch_equals_single_steps(pkg, variant, max_steps):
     """Episodes of 1, 3 or 9 steps (truncation) reset every env again and
@@ -436,3 +436,26 @@ def test_fwd65536_dr_full_size(pkg, orc):
     assert max_state_err(sg[:, ok], one.s[ok]) < STEP_TOL
     assert reward_err(np_(r1)[ids][ok], o1["rewards"][0][ok]) < STEP_TOL
     sim.close()
+
+
+@pytest.mark.parametrize("n", [16, 777, 4096])
+def test_split_actor_equals_quarter_lane_bitwise(pkg, n):
+    """The split-actor kernel runs the quarter-lane kernel's MFMA chains tile
+    by tile, so whole rollouts (resets, DR, recorded rewards, dones and
+    states) agree bit for bit, also with a ragged last workgroup."""
+    T = 120
+    flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, flags=flags, max_episode_steps=40)
+    W = wl.xavier_actor(0)
+    out = {}
+    for v in ("mfma4", "split"):
+        sim = make_sim(pkg, cfg, v)
+        a = sim.actor_tensor(W)
+        o = sim.rollout(a, T, rewards=True, dones=True, states=True)
+        res = {k: np_(x) for k, x in o.items()}
+        res.update({k: np_(x) for k, x in sim.get_state().items()})
+        out[v] = res
+        sim.close()
+    assert out["split"]["dones"].any()
+    for k in out["mfma4"]:
+        assert np.array_equal(out["mfma4"][k], out["split"][k], equal_nan=True), k
