@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (3 times): the "
                          "reference for scaling HBM traffic counters")
+    ap.add_argument("--only-fwd-bwd", action="store_true",
+                    help="run only the forward+backward legs and print them (for profiling "
+                         "the backward kernels)")
     ap.add_argument("--variant", default="auto", choices=["auto", "mfma4", "mfma", "valu", "split"],
                     help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
                          "per rollout (used for profiling so only timed launches appear)")
@@ -260,6 +263,16 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
             "roofline": roof}
 
 
+def fwd_bwd_legs(torch, pkg, W):
+    """The differentiable workloads: the policy gradient on 1024 nominal envs
+    over 64 steps, and system identification on 16384 randomised envs over
+    256 steps (fp32 and bf16 actor), checkpoints every 16 steps."""
+    return {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
+            "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0)),
+            "sysid16384_bf16": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0),
+                                       bf16=True)}
+
+
 def fixed_episodes(torch, pkg, actor):
     """4096 nominal envs x 1000 steps with every episode truncated at 500
     steps: the plain five-kernel step launched from the host, the same
@@ -330,6 +343,9 @@ def main():
     T = wl.workload_steps(name)
     N = cfg["n_envs"]
     W = wl.xavier_actor(0)
+    if args.only_fwd_bwd:
+        print(json.dumps({"fwd_bwd": fwd_bwd_legs(torch, pkg, W)}), flush=True)
+        return
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -440,10 +456,7 @@ def main():
         res["fixed_episodes_4096"] = fixed_episodes(torch, pkg, actor)
     sim.close()
     if not args.no_extras:
-        res["fwd_bwd"] = {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
-                          "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0)),
-                          "sysid16384_bf16": fwd_bwd(torch, pkg, "sysid16384", 16,
-                                                     wl.sysid_actor(0), bf16=True)}
+        res["fwd_bwd"] = fwd_bwd_legs(torch, pkg, W)
         res["dynamics_only"] = {"n8192_T2000": dynamics_only(torch, pkg, 8192, 2000),
                                 "n65536_T1000": dynamics_only(torch, pkg, 65536, 1000)}
     if not args.no_cpu_baseline:

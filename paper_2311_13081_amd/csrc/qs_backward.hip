@@ -204,7 +204,8 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + kd[i]);
     float rn = 1.0f;
     if (renorm) {
-      rn = 1.0f / sqrtf(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
+      // the forward's reciprocal square root (rk4_step)
+      rn = rsqrt_r(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) sn[3 + i] *= rn;
     }
