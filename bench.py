@@ -157,9 +157,18 @@ def cpu_baseline(cfg, W, seconds):
     t0 = time.perf_counter()
     b.rollout(W, steps, nthreads=nthreads)
     dt = time.perf_counter() - t0
+    # one thread, on a tenth of the time budget
+    n1 = len(probe_ids)
+    steps1 = int(max(20, min(1000, n * steps / dt / nthreads * seconds / 10 / n1)))
+    b1 = oracle.Batch.init(cfg, n1, ids=probe_ids)
+    t1 = time.perf_counter()
+    b1.rollout(W, steps1, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": n * steps / dt, "unit": "env-steps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} of {N} envs x {steps} steps (same config, seeds, env ids), "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_thread": {"value": n1 * steps1 / dt1,
+                              "sample": f"{n1} envs x {steps1} steps, {dt1:.1f} s"}}
 
 
 # Error norm per state component group (p, q, v, w, rotor speeds): the
