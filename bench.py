@@ -216,7 +216,11 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
         cfg["flags"] |= wl.F_ACTOR_BF16
     H = wl.workload_steps(name)
     N = cfg["n_envs"]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     sim = pkg.QuadSim(cfg)
+    torch.cuda.synchronize()
+    handle_bytes = free0 - torch.cuda.mem_get_info()[0]
     sim.set_variant(pkg.SIM_V_FUSED_MFMA4)   # the kernel taped rollouts use
     a = sim.actor_tensor(W)
     snap = {k: v.clone() for k, v in sim.get_state().items()}
@@ -267,9 +271,15 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA}
     roof["flop_per_env_step"] = FLOP_FWD_BWD_ENV_STEP
+    K = cfg["ckpt_every"]
+    # checkpoints of (state, history, counters): 147 floats per env; one
+    # step's backward record: 295 floats per env
+    mem = {"device_bytes_of_handle": handle_bytes,
+           "tape_bytes": (H // K + 1) * 147 * N * 4,
+           "records_of_whole_horizon_bytes": H * 295 * N * 4}
     return {"env_steps_per_s": rate, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
-            "horizon": H, "ckpt_every": cfg["ckpt_every"], "actor": "bf16" if bf16 else "f32",
-            "roofline": roof}
+            "horizon": H, "ckpt_every": K, "actor": "bf16" if bf16 else "f32",
+            "roofline": roof, "memory": mem}
 
 
 def fwd_bwd_legs(torch, pkg, W):
@@ -291,22 +301,26 @@ def fixed_episodes(torch, pkg, actor):
     T = wl.workload_steps("fwd4096")
     N = cfg["n_envs"]
     res = {"n_envs": N, "rollout_steps": T}
+    names = {1: "plain", 2: "fused_valu", 3: "fused_mfma", 4: "fused_mfma4", 5: "fused_split"}
     for label, variant, spl, use_graph in (
             ("plain_eager", pkg.SIM_V_PLAIN, 0, False), ("plain_graph", pkg.SIM_V_PLAIN, 0, True),
-            ("fused_per_step_launch", pkg.SIM_V_FUSED_MFMA, 1, True), ("persistent", None, 0, True)):
+            ("fused_per_step_launch", pkg.SIM_V_FUSED_MFMA, 1, True),
+            ("fused_per_step_launch", pkg.SIM_V_FUSED_MFMA4, 1, True),
+            ("fused_per_step_launch", pkg.SIM_V_FUSED_SPLIT, 1, True),
+            ("persistent", None, 0, True)):
         sim = pkg.QuadSim(cfg)
         if variant is None:
             sim.autotune(actor, T)
         else:
             sim.set_variant(variant, spl, use_graph)
         w, _, _ = time_rollouts(torch, sim, actor, T, 2, 1)
-        res[label] = {"env_steps_per_s": N * T * 2 / w, "ms_per_env_step": w * 1e3 / (2 * T)}
-        if variant is None:
-            v, s, g = sim.get_variant()
-            res[label]["variant"] = {1: "plain", 2: "fused_valu", 3: "fused_mfma",
-                                     4: "fused_mfma4", 5: "fused_split"}[v]
-            res[label]["steps_per_launch"] = s
+        v, s, g = sim.get_variant()
+        r = {"env_steps_per_s": N * T * 2 / w, "ms_per_env_step": w * 1e3 / (2 * T),
+             "variant": names[v], "steps_per_launch": s}
         sim.close()
+        # the per-step launch leg keeps the fastest fused kernel
+        if label not in res or r["env_steps_per_s"] > res[label]["env_steps_per_s"]:
+            res[label] = r
     return res
 
 
