@@ -170,7 +170,7 @@ __device__ inline void reset_draw(const DevCfg& c, uint32_t env, uint32_t episod
 // together every RESERVE_PERIOD steps.  An env that resets again before its
 // refill draws in place.  The draws are the same counter-based ones either
 // way, so results do not depend on when they are made.
-constexpr int RESERVE_PERIOD = 8;  // power of 2
+constexpr int RESERVE_PERIOD = 16;  // power of 2
 constexpr int NRES = NS - NA;      // drawn-ahead state values
 
 __device__ inline void draw_ahead(const DevCfg& c, uint32_t env, uint32_t episode, float wh,
