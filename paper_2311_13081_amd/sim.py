@@ -55,6 +55,16 @@ class QuadSim:
     def _f32(self, *shape):
         return torch.empty(*shape, dtype=torch.float32, device=self.device)
 
+    def _need(self, t, shape, dtype, name):
+        """The library takes plain pointers: refuse a tensor it would read or
+        write out of bounds."""
+        if t is None:
+            return
+        if (t.dtype != dtype or not t.is_contiguous() or t.device.type != "cuda"
+                or tuple(t.shape) != tuple(shape)):
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape "
+                             f"{tuple(shape)}, got {tuple(t.shape)} {t.dtype} on {t.device}")
+
     def actor_tensor(self, w) -> torch.Tensor:
         t = torch.as_tensor(w, dtype=torch.float32).to(self.device).contiguous()
         if t.numel() != _lib.SIM_NACTOR:
@@ -68,6 +78,8 @@ class QuadSim:
 
     def step(self, actor: torch.Tensor | None = None, actions: torch.Tensor | None = None):
         """One step; returns (reward [N], done [N] uint8)."""
+        self._need(actor, (_lib.SIM_NACTOR,), torch.float32, "actor")
+        self._need(actions, (4, self.N), torch.float32, "actions")
         r = self._f32(self.N)
         d = torch.empty(self.N, dtype=torch.uint8, device=self.device)
         check(self.L.sim_step(self.h, _ptr(actor), _ptr(actions), _ptr(r), _ptr(d), _stream()),
@@ -79,12 +91,18 @@ class QuadSim:
         """T steps.  Returns dict with rewards [T][N], dones [T][N], states
         [T+1][17][N] (each only when requested).  out= reuses tensors."""
         out = {} if out is None else out
+        n = max(int(T), 0)  # the library rejects T < 1 itself
+        self._need(actor, (_lib.SIM_NACTOR,), torch.float32, "actor")
+        for k, shape, dt in (("rewards", (n, self.N), torch.float32),
+                             ("dones", (n, self.N), torch.uint8),
+                             ("states", (n + 1, 17, self.N), torch.float32)):
+            self._need(out.get(k), shape, dt, k)
         if rewards and "rewards" not in out:
-            out["rewards"] = self._f32(T, self.N)
+            out["rewards"] = self._f32(n, self.N)
         if dones and "dones" not in out:
-            out["dones"] = torch.empty(T, self.N, dtype=torch.uint8, device=self.device)
+            out["dones"] = torch.empty(n, self.N, dtype=torch.uint8, device=self.device)
         if states and "states" not in out:
-            out["states"] = self._f32(T + 1, 17, self.N)
+            out["states"] = self._f32(n + 1, 17, self.N)
         check(self.L.sim_rollout(self.h, _ptr(actor), T, _ptr(out.get("rewards")),
                                  _ptr(out.get("dones")), _ptr(out.get("states")),
                                  1 if record_tape else 0, _stream()), "sim_rollout")
@@ -106,13 +124,20 @@ class QuadSim:
                         states=False):
         """Dynamics-only rollout: actions [4][N] held constant, or [T][4][N]."""
         per_step = actions.dim() == 3
+        n = max(int(T), 0)  # the library rejects T < 1 itself
+        want = (n, 4, self.N) if per_step else (4, self.N)
+        if (actions.dtype != torch.float32 or not actions.is_contiguous()
+                or tuple(actions.shape[-2:]) != want[-2:]
+                or (per_step and actions.shape[0] < n)):
+            raise ValueError(f"actions must be contiguous float32 [4][N] or [>=T][4][N], "
+                             f"got {tuple(actions.shape)} {actions.dtype} for T={T}, N={self.N}")
         out = {}
         if rewards:
-            out["rewards"] = self._f32(T, self.N)
+            out["rewards"] = self._f32(n, self.N)
         if dones:
-            out["dones"] = torch.empty(T, self.N, dtype=torch.uint8, device=self.device)
+            out["dones"] = torch.empty(n, self.N, dtype=torch.uint8, device=self.device)
         if states:
-            out["states"] = self._f32(T + 1, 17, self.N)
+            out["states"] = self._f32(n + 1, 17, self.N)
         check(self.L.sim_rollout_actions(self.h, _ptr(actions), 1 if per_step else 0, T,
                                          _ptr(out.get("rewards")), _ptr(out.get("dones")),
                                          _ptr(out.get("states")), _stream()),

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SIZES = [1, 17, 63, 65]
-PATHS = {"plain": (1, 0), "valu": (2, 0), "mfma": (3, 0), "mfma4": (4, 0),
+PATHS = {"plain": (1, 0), "valu": (2, 0), "mfma": (3, 0), "mfma4": (4, 0), "split": (5, 0),
          "fp64": (0, wl.F_FP64)}
 
 
@@ -56,7 +56,7 @@ def test_short_rollout_at_edge_sizes(pkg, oracle_lib, path, n):
 
 @pytest.mark.parametrize("n", SIZES)
 def test_one_step_rollout_equals_step(pkg, n):
-    for variant in (3, 4):
+    for variant in (3, 4, 5):
         cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0)
         a, b = pkg.QuadSim(cfg), pkg.QuadSim(cfg)
         a.set_variant(variant)
@@ -138,4 +138,45 @@ def test_autotune_cache_round_trip(pkg, tmp_path):
     v2, ms2 = sim.autotune(a, 200, cache=path)
     assert (v2, ms2) == (v1, ms1)
     assert sim.get_variant()[0] == v1
+    sim.close()
+
+
+def test_empty_rollouts_are_rejected(pkg):
+    """T < 1 is an argument error for rollouts, action rollouts and the
+    autotuner; the state is left as it was."""
+    from paper_2311_13081_amd import SimError
+    cfg = wl.crazyflie_config(n_envs=33)
+    sim = pkg.QuadSim(cfg)
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    before = {k: np_(v) for k, v in sim.get_state().items()}
+    for call in (lambda: sim.rollout(a, 0), lambda: sim.rollout(a, -3),
+                 lambda: sim.rollout_actions(torch.zeros(4, 33, device="cuda"), 0),
+                 lambda: sim.autotune(a, 0)):
+        with pytest.raises(SimError) as ei:
+            call()
+        assert ei.value.code == -1
+    after = {k: np_(v) for k, v in sim.get_state().items()}
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    sim.close()
+
+
+def test_binding_refuses_tensors_of_the_wrong_shape(pkg):
+    """The library takes plain pointers, so the binding checks every tensor
+    it hands over; too short a per-step action array or output buffer is a
+    ValueError before anything reaches the device."""
+    n = 40
+    sim = pkg.QuadSim(wl.crazyflie_config(n_envs=n))
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    bad = [
+        lambda: sim.rollout_actions(torch.zeros(3, 4, n, device="cuda"), 5),
+        lambda: sim.rollout_actions(torch.zeros(4, n - 1, device="cuda"), 5),
+        lambda: sim.rollout_actions(torch.zeros(4, n, dtype=torch.float64, device="cuda"), 5),
+        lambda: sim.step(actions=torch.zeros(4, n + 1, device="cuda")),
+        lambda: sim.step(actor=a[:-1]),
+        lambda: sim.rollout(a, 8, out={"rewards": torch.zeros(7, n, device="cuda")}),
+    ]
+    for call in bad:
+        with pytest.raises(ValueError):
+            call()
     sim.close()
