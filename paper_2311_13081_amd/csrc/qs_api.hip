@@ -323,7 +323,6 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
     rc = rc ? rc : alloc((void**)&h->pb.t_ep, N * 4);
     rc = rc ? rc : alloc((void**)&h->pb.ep, N * 4);
     rc = rc ? rc : alloc((void**)&h->pb.theta, N * NP * 8);
-    rc = rc ? rc : alloc((void**)&h->pb.wd, (size_t)SIM_NACTOR * 8);
     if (!rc && precise_prepare() != hipSuccess) rc = fail(SIM_E_DEVICE, "fp64 kernel setup failed");
     if (!rc && hipEventCreate(&h->ev0) == hipSuccess && hipEventCreate(&h->ev1) == hipSuccess) {
       hipError_t e = precise_init(h->pc, h->pb, 1, nullptr);
@@ -380,7 +379,7 @@ int sim_destroy(sim_handle* h) {
   drop_graph(h);
   void* ptrs[] = {h->b.state, h->b.ring, h->b.head,  h->b.t_ep,  h->b.ep,    h->b.theta,
                   h->p.obs,   h->p.h1,   h->p.h2,    h->p.act,   h->tape,    h->pb.state,
-                  h->pb.ring, h->pb.head, h->pb.t_ep, h->pb.ep,  h->pb.theta, h->pb.wd};
+                  h->pb.ring, h->pb.head, h->pb.t_ep, h->pb.ep,  h->pb.theta};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   bwd_free(h->bw);

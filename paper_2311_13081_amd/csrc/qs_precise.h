@@ -22,8 +22,9 @@ struct PreciseBufs {
   int32_t* t_ep;   // [N]
   int32_t* ep;     // [N]
   double* theta;   // [8][N]
-  double* wd;      // [13828] actor weights in double, transposed (qs_precise.hip)
 };
+
+constexpr int PRECISE_LDS_BYTES = 13828 * 8;
 
 hipError_t precise_prepare();
 hipError_t precise_init(const PreciseCfg& p, const PreciseBufs& b, int params, hipStream_t st);

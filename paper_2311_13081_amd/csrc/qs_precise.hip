@@ -5,18 +5,13 @@
 // -- evaluated in double precision throughout, with the state, the action
 // history and the per-env parameters stored in double.  The only float32
 // decision is the termination box test, taken on the state rounded to float32
-// (the precision the single-precision path decides in).  MI355X issues fp64
-// vector FMAs at about the fp32 rate and its fp64 matrix instructions give
-// no more multiply-adds per cycle than that, so the actor runs on the vector
-// ALUs.
+// (the precision the single-precision path decides in).  MI355X runs fp64
+// vector FMAs at the fp32 rate, so the integrator costs about the same; the
+// actor runs on the vector ALUs (no fp64 matrix-core path here).
 //
 // One env per lane; history ring in HBM (it does not fit in registers in
-// double).  Every lane multiplies by the same weight at the same time, so
-// the weights come through the scalar data cache: a double-precision copy in
-// global memory (converted and transposed once per launch) read with uniform
-// addresses, which the compiler turns into scalar loads feeding the FMAs'
-// scalar operand.  (Staged in LDS instead, each broadcast read costs a full
-// LDS transaction per FMA pair and bounds the kernel.)
+// double); weights staged in LDS as doubles, transposed so that every lane
+// reads the same address.
 #include <hip/hip_runtime.h>
 
 #include "qs_device.h"
@@ -135,35 +130,32 @@ __global__ void k_precise_init(PreciseCfg p, PreciseBufs b, int params) {
   b.ep[e] = 0;
 }
 
-// The actor weights in double, transposed so that consecutive outputs of a
-// layer are consecutive (P_* layout).
-__global__ void k_precise_weights(const float* __restrict__ W, double* __restrict__ wd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < NO * NHID) {
-    const int k = i / NHID, n = i % NHID;
-    wd[P_W1T + i] = (double)W[OFF_W1 + n * NO + k];
-  }
-  if (i < NHID * NHID) {
-    const int k = i / NHID, n = i % NHID;
-    wd[P_W2T + i] = (double)W[OFF_W2 + n * NHID + k];
-  }
-  if (i < NHID * NA) {
-    const int k = i / NA, n = i % NA;
-    wd[P_W3T + i] = (double)W[OFF_W3 + n * NHID + k];
-  }
-  if (i < NHID) {
-    wd[P_B1 + i] = (double)W[OFF_B1 + i];
-    wd[P_B2 + i] = (double)W[OFF_B2 + i];
-  }
-  if (i < NA) wd[P_B3 + i] = (double)W[OFF_B3 + i];
-}
-
-// T steps; outputs indexed by t_base + t, states rounded to float.  wd: the
-// weights from k_precise_weights (unused when ext gives the actions).
+// T steps; outputs indexed by t_base + t, states rounded to float.
 __global__ void __launch_bounds__(256)
-k_precise(PreciseCfg p, PreciseBufs b, const double* __restrict__ wd,
-          const float* __restrict__ ext, int T, int t_base, float* __restrict__ rewards,
-          uint8_t* __restrict__ dones, float* __restrict__ states) {
+k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float* __restrict__ ext,
+          int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
+          float* __restrict__ states) {
+  extern __shared__ double lds[];
+  if (W) {
+    for (int i = threadIdx.x; i < NO * NHID; i += blockDim.x) {
+      const int k = i / NHID, n = i % NHID;
+      lds[P_W1T + i] = (double)W[OFF_W1 + n * NO + k];
+    }
+    for (int i = threadIdx.x; i < NHID * NHID; i += blockDim.x) {
+      const int k = i / NHID, n = i % NHID;
+      lds[P_W2T + i] = (double)W[OFF_W2 + n * NHID + k];
+    }
+    for (int i = threadIdx.x; i < NHID * NA; i += blockDim.x) {
+      const int k = i / NA, n = i % NA;
+      lds[P_W3T + i] = (double)W[OFF_W3 + n * NHID + k];
+    }
+    for (int i = threadIdx.x; i < NHID; i += blockDim.x) {
+      lds[P_B1 + i] = (double)W[OFF_B1 + i];
+      lds[P_B2 + i] = (double)W[OFF_B2 + i];
+    }
+    for (int i = threadIdx.x; i < NA; i += blockDim.x) lds[P_B3 + i] = (double)W[OFF_B3 + i];
+  }
+  __syncthreads();
   const int N = p.n_envs;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
@@ -223,37 +215,37 @@ k_precise(PreciseCfg p, PreciseBufs b, const double* __restrict__ wd,
       }
       double z1[NHID];
 #pragma unroll
-      for (int n = 0; n < NHID; ++n) z1[n] = wd[P_B1 + n];
+      for (int n = 0; n < NHID; ++n) z1[n] = lds[P_B1 + n];
 #pragma unroll
       for (int k = 0; k < 18; ++k)
 #pragma unroll
-        for (int n = 0; n < NHID; ++n) z1[n] = fma(wd[P_W1T + k * NHID + n], o18[k], z1[n]);
+        for (int n = 0; n < NHID; ++n) z1[n] = fma(lds[P_W1T + k * NHID + n], o18[k], z1[n]);
       for (int k = 18; k < NO; ++k) {
         const int sl = (k - 18) >> 2, c = (k - 18) & 3;
         const double v = b.ring[(size_t)((((head + sl) & (NH - 1)) * NA) + c) * N + e];
 #pragma unroll
-        for (int n = 0; n < NHID; ++n) z1[n] = fma(wd[P_W1T + k * NHID + n], v, z1[n]);
+        for (int n = 0; n < NHID; ++n) z1[n] = fma(lds[P_W1T + k * NHID + n], v, z1[n]);
       }
       // layers 2 and 3 in chunks of 16 hidden units, so only one chunk of the
       // second hidden layer is live next to the first
 #pragma unroll
-      for (int n = 0; n < NA; ++n) a[n] = wd[P_B3 + n];
+      for (int n = 0; n < NA; ++n) a[n] = lds[P_B3 + n];
 #pragma unroll
       for (int cb = 0; cb < NHID; cb += 16) {
         double z2[16];
 #pragma unroll
-        for (int n = 0; n < 16; ++n) z2[n] = wd[P_B2 + cb + n];
+        for (int n = 0; n < 16; ++n) z2[n] = lds[P_B2 + cb + n];
 #pragma unroll
         for (int k = 0; k < NHID; ++k) {
           const double v = z1[k] > 0.0 ? z1[k] : 0.0;
 #pragma unroll
-          for (int n = 0; n < 16; ++n) z2[n] = fma(wd[P_W2T + k * NHID + cb + n], v, z2[n]);
+          for (int n = 0; n < 16; ++n) z2[n] = fma(lds[P_W2T + k * NHID + cb + n], v, z2[n]);
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const double v = z2[k] > 0.0 ? z2[k] : 0.0;
 #pragma unroll
-          for (int n = 0; n < NA; ++n) a[n] = fma(wd[P_W3T + (cb + k) * NA + n], v, a[n]);
+          for (int n = 0; n < NA; ++n) a[n] = fma(lds[P_W3T + (cb + k) * NA + n], v, a[n]);
         }
       }
       for (int n = 0; n < NA; ++n) a[n] = tanh(a[n]);
@@ -345,7 +337,10 @@ __global__ void k_precise_set(PreciseBufs b, int N, const float* state, const fl
 
 static inline unsigned pb(int n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t precise_prepare() { return hipSuccess; }
+hipError_t precise_prepare() {
+  return hipFuncSetAttribute((const void*)k_precise, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             PRECISE_LDS_BYTES);
+}
 
 hipError_t precise_init(const PreciseCfg& p, const PreciseBufs& b, int params, hipStream_t st) {
   hipLaunchKernelGGL(k_precise_init, dim3(pb(p.n_envs)), dim3(256), 0, st, p, b, params);
@@ -355,11 +350,8 @@ hipError_t precise_init(const PreciseCfg& p, const PreciseBufs& b, int params, h
 hipError_t precise_run(const PreciseCfg& p, const PreciseBufs& b, const float* W,
                        const float* ext, int T, int t_base, float* rewards, uint8_t* dones,
                        float* states, hipStream_t st) {
-  if (!ext) {
-    hipLaunchKernelGGL(k_precise_weights, dim3(pb(NO * NHID)), dim3(256), 0, st, W, b.wd);
-  }
-  hipLaunchKernelGGL(k_precise, dim3(pb(p.n_envs)), dim3(256), 0, st, p, b,
-                     (const double*)b.wd, ext, T, t_base, rewards, dones, states);
+  hipLaunchKernelGGL(k_precise, dim3(pb(p.n_envs)), dim3(256), PRECISE_LDS_BYTES, st, p, b, W,
+                     ext, T, t_base, rewards, dones, states);
   return hipGetLastError();
 }
 
