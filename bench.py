@@ -43,6 +43,7 @@ PLAIN_BYTES_PER_ENV_STEP = 1160 + 840 + 512 + 272 + 225
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense fp32 matrix FLOP/s
 PEAK_BF16_MFMA = 2.5e15        # dense bf16 matrix FLOP/s
 PEAK_FP32_VALU = 78.6e12       # fp32 vector FLOP/s without packed instructions
+PEAK_FP64 = 78.6e12            # fp64 vector and matrix FLOP/s
 PEAK_HBM = 8.0e12
 ACTOR_GEMM_FLOP = 27_392      # the forward actor's three GEMMs, per env step
 # Dynamics-only env step: four right-hand sides (about 103 FLOP each: rotor
@@ -474,6 +475,11 @@ def main():
             w6, d6, l6 = time_rollouts(torch, s6, actor, steps, 2, 1)
             extras[label] = {"env_steps_per_s": N * steps * 2 / w6, "kernel_ms": d6 / (2 * l6),
                              "rollout_steps": steps}
+            if flags == wl.F_FP64:
+                ach = FLOP_PER_ENV_STEP * N * steps / (d6 / (2 * l6) * 1e-3)
+                extras[label]["roofline"] = {
+                    "bound": "fp64 mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / PEAK_FP64}
             s6.close()
         res["comparison"] = extras
         res["fixed_episodes_4096"] = fixed_episodes(torch, pkg, actor)
