@@ -80,11 +80,13 @@ enum {
                            inputs rounded to bf16 (nearest even), fp32
                            accumulation, biases and activations; the dynamics
                            stay fp32.  Policy steps and rollouts then run on
-                           the quarter-lane kernel only (SIM_V_AUTO or
-                           SIM_V_FUSED_MFMA4); taped rollouts and their
-                           backward recompute use the same bf16 forward, the
-                           reverse sweep differentiates it with bf16-rounded
-                           weights.  Not combinable with SIM_F_FP64.  Fixed
+                           the matrix-core kernels only (SIM_V_AUTO,
+                           SIM_V_FUSED_MFMA4 -- the default until tuned -- or
+                           SIM_V_FUSED_MFMA; the two sum the bf16 products
+                           in different orders); taped rollouts and their
+                           backward recompute use the quarter-lane bf16
+                           forward, the reverse sweep differentiates it with
+                           bf16-rounded weights.  Not combinable with SIM_F_FP64.  Fixed
                            at creation.  (A precision option, not the
                            reference arithmetic: the FP64 oracle stays the
                            reference, and the error against it is larger.)   */

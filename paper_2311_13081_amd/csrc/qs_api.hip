@@ -314,7 +314,7 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   rc = SIM_OK;
   h->fp64 = (cfg->flags & SIM_F_FP64) != 0;
   h->bf16 = (cfg->flags & SIM_F_ACTOR_BF16) != 0;
-  if (h->bf16) h->tuned_variant = SIM_V_FUSED_MFMA4;  // the only kernel with the bf16 actor
+  if (h->bf16) h->tuned_variant = SIM_V_FUSED_MFMA4;  // the taped rollouts' kernel
   if (h->fp64) {
     h->pc = make_precise(*cfg, cfg->seed);
     rc = rc ? rc : alloc((void**)&h->pb.state, N * NS * 8);
@@ -639,8 +639,11 @@ int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_gr
   if (variant < SIM_V_AUTO || variant > SIM_V_FUSED_SPLIT)
     return fail(SIM_E_INVAL, "unknown variant %d", variant);
   if (steps_per_launch < 0) return fail(SIM_E_INVAL, "steps_per_launch < 0");
-  if (h->bf16 && variant != SIM_V_AUTO && variant != SIM_V_FUSED_MFMA4)
-    return fail(SIM_E_UNSUPPORTED, "SIM_F_ACTOR_BF16 handles run the quarter-lane kernel only");
+  if (h->bf16 && variant != SIM_V_AUTO && variant != SIM_V_FUSED_MFMA4 &&
+      variant != SIM_V_FUSED_MFMA)
+    return fail(SIM_E_UNSUPPORTED,
+                "SIM_F_ACTOR_BF16 handles run the matrix-core kernels (SIM_V_FUSED_MFMA, "
+                "SIM_V_FUSED_MFMA4) only");
   h->variant = variant;
   h->spl = steps_per_launch;
   h->use_graph = use_graph ? 1 : 0;
@@ -681,7 +684,9 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
                              {SIM_V_FUSED_SPLIT, 0}, {SIM_V_FUSED_MFMA4, 100},
                              {SIM_V_FUSED_MFMA, 100}, {SIM_V_FUSED_SPLIT, 100},
                              {SIM_V_FUSED_VALU, 0},  {SIM_V_PLAIN, 0}};
-  if (h->bf16) cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA4, 100}};
+  if (h->bf16)
+    cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0}, {SIM_V_FUSED_MFMA4, 100},
+             {SIM_V_FUSED_MFMA, 100}};
   const int save_v = h->variant, save_spl = h->spl;
   float best = 1e30f;
   Cand bestc = cands[0];

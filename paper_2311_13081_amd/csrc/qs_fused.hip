@@ -21,14 +21,19 @@ namespace qs {
 // training extras are on): the episode disturbance enters the dynamics and
 // the actor sees its observation with noise; without them the kernel carries
 // none of that code.
-template <bool MFMA, bool EXTRAS>
+template <bool MFMA, bool EXTRAS, bool BF16>
 __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
         float* __restrict__ states) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
-  if (ext_act == nullptr) stage_actor<MFMA>(W, lds);
+  if (ext_act == nullptr) {
+    if constexpr (BF16)
+      stage_actor_bf16(W, lds);
+    else
+      stage_actor<MFMA>(W, lds);
+  }
   __syncthreads();
   const int env = blockIdx.x * blockDim.x + threadIdx.x;
   const int first = env - (threadIdx.x & 63);
@@ -104,12 +109,16 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
 #pragma unroll
           for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
         }
-        if (MFMA)
+        if constexpr (BF16)
+          actor_mfma_bf16(lds, so, Rm, H, z3);
+        else if (MFMA)
           actor_mfma(lds, so, Rm, H, z3);
         else
           actor_valu(lds, so, Rm, H, z3);
       } else {
-        if (MFMA)
+        if constexpr (BF16)
+          actor_mfma_bf16(lds, x, Rm, H, z3);
+        else if (MFMA)
           actor_mfma(lds, x, Rm, H, z3);
         else
           actor_valu(lds, x, Rm, H, z3);
@@ -180,18 +189,12 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
                         float* states, hipStream_t st) {
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
-  if (mfma && !ex)
-    hipLaunchKernelGGL((k_fused<true, false>), g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards,
-                       dones, states);
-  else if (mfma)
-    hipLaunchKernelGGL((k_fused<true, true>), g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards,
-                       dones, states);
-  else if (!ex)
-    hipLaunchKernelGGL((k_fused<false, false>), g, blk, 0, st, c, b, W, ext_act, T, t_base,
-                       rewards, dones, states);
-  else
-    hipLaunchKernelGGL((k_fused<false, true>), g, blk, 0, st, c, b, W, ext_act, T, t_base,
-                       rewards, dones, states);
+  // the bf16 actor option runs on the matrix-core kernel
+  const bool bf = mfma && (c.flags & F_ACTOR_BF16) != 0;
+  auto k = bf ? (ex ? k_fused<true, true, true> : k_fused<true, false, true>)
+              : mfma ? (ex ? k_fused<true, true, false> : k_fused<true, false, false>)
+                     : (ex ? k_fused<false, true, false> : k_fused<false, false, false>);
+  hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones, states);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from parity import STEP_TOL, max_state_err
+from parity import STEP_TOL, max_state_err, state_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,18 +73,26 @@ def test_bf16_config_rules(pkg):
     assert ei.value.code == -1
     cfg = wl.crazyflie_config(n_envs=64, flags=wl.F_RENORM_Q | wl.F_ACTOR_BF16)
     sim = pkg.QuadSim(cfg)
-    with pytest.raises(SimError) as ei:
-        sim.set_variant(pkg.SIM_V_FUSED_MFMA)
-    assert ei.value.code == -5
     assert sim.get_variant()[0] == pkg.SIM_V_FUSED_MFMA4
+    for v in (pkg.SIM_V_FUSED_VALU, pkg.SIM_V_PLAIN, pkg.SIM_V_FUSED_SPLIT):
+        with pytest.raises(SimError) as ei:
+            sim.set_variant(v)
+        assert ei.value.code == -5
+    sim.set_variant(pkg.SIM_V_FUSED_MFMA)
+    assert sim.get_variant()[0] == pkg.SIM_V_FUSED_MFMA
     sim.close()
 
 
-def test_bf16_one_step_matches_bf16_arithmetic(pkg, oracle_lib):
+@pytest.mark.parametrize("variant", ["mfma4", "mfma"])
+def test_bf16_one_step_matches_bf16_arithmetic(pkg, oracle_lib, variant):
+    """Both matrix-core kernels (quarter-lane: 16x16x32 bf16 products; one
+    env per lane: 4-block 16x16x4 and 16x16x32 bf16 products, fp32 4x4x1 on
+    rounded inputs for layer 3) against the emulated bf16 arithmetic."""
     n = 1000
     cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, max_episode_steps=0,
                               flags=wl.F_RENORM_Q | wl.F_ACTOR_BF16)
     sim = pkg.QuadSim(cfg)
+    sim.set_variant({"mfma4": pkg.SIM_V_FUSED_MFMA4, "mfma": pkg.SIM_V_FUSED_MFMA}[variant])
     W = wl.random_actor(3)
     s, h = wl.random_states(n, seed=77)
     sim.set_state(state=s, hist=h)
@@ -165,3 +173,30 @@ def test_bf16_gradients_reported_against_fp64(pkg, oracle_lib):
     assert res["fp32"][0] < 1e-3
     assert res["bf16"][3] > 0.99      # same descent direction
     assert res["bf16"][0] > res["fp32"][0]
+
+
+def test_bf16_one_lane_rollout_tracks_quarter_lane(pkg):
+    """Long rollouts of the two bf16 kernels (different summation orders of
+    the same bf16 products) with resets: done flags mostly equal, states close
+    while episodes agree."""
+    n, T = 512, 60
+    flags = wl.F_RENORM_Q | wl.F_ACTOR_BF16 | wl.F_TERMINATE | wl.F_AUTORESET
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, flags=flags, max_episode_steps=25)
+    W = wl.random_actor(11)
+    res = {}
+    for v in ("mfma4", "mfma"):
+        sim = pkg.QuadSim(cfg)
+        sim.set_variant({"mfma4": pkg.SIM_V_FUSED_MFMA4, "mfma": pkg.SIM_V_FUSED_MFMA}[v])
+        out = sim.rollout(sim.actor_tensor(W), T, rewards=True, dones=True, states=True)
+        res[v] = {k: np_(x) for k, x in out.items()}
+        sim.close()
+    same = (res["mfma4"]["dones"] == res["mfma"]["dones"]).mean()
+    assert same > 0.99, same
+    # R16 norm (relative, with per-group floors) over the first steps, on the
+    # envs whose done flags agree there
+    ok = (res["mfma4"]["dones"][:5] == res["mfma"]["dones"][:5]).all(axis=0)
+    assert ok.mean() > 0.98
+    d = state_err(res["mfma"]["states"][1:6][:, :, ok],
+                  np.transpose(res["mfma4"]["states"][1:6][:, :, ok], (0, 2, 1))).max()
+    print("one-lane vs quarter-lane bf16, steps 1..5, R16 norm", d)
+    assert d < 1e-4, d
