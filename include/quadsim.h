@@ -148,7 +148,10 @@ typedef struct sim_handle sim_handle;
 /* Creates a simulator for cfg->n_envs envs on HIP device `device`, allocates
  * all device memory (including the tape for max_tape_horizon steps), draws the
  * per-env parameters from dr_seed and resets every env to episode 0 from
- * cfg->seed.  Synchronises.  *out is NULL on failure. */
+ * cfg->seed.  Synchronises.  *out is NULL on failure.  A differentiable handle
+ * (max_tape_horizon > 0) needs the backward's per-segment record, about
+ * (128 + 171 ckpt_every) x 4 bytes per env, below 4 GiB (SIM_E_INVAL
+ * otherwise). */
 int sim_create(const sim_config* cfg, int device, sim_handle** out);
 
 /* Frees everything the handle owns.  Synchronises.  NULL is allowed. */

@@ -116,10 +116,12 @@ int check_config(const sim_config* c) {
     return fail(SIM_E_UNSUPPORTED, "SIM_F_FP64 handles are forward only (max_tape_horizon 0)");
   if (c->max_tape_horizon < 0 || c->max_tape_horizon > (1 << 20))
     return fail(SIM_E_INVAL, "max_tape_horizon out of range");
-  // per-step record offsets of the backward are 32-bit
-  if (c->max_tape_horizon > 0 && (double)REC_F * (double)rb_pad(c->n_envs) >= 4294967296.0)
-    return fail(SIM_E_INVAL, "n_envs %d too large for a differentiable handle", c->n_envs);
   if (c->ckpt_every < 1 || c->ckpt_every > 4096) return fail(SIM_E_INVAL, "ckpt_every must be in [1, 4096]");
+  // the backward addresses a segment's record with 32-bit byte offsets
+  if (c->max_tape_horizon > 0 &&
+      4.0 * (double)rec_floats(c->ckpt_every, c->n_envs) >= 4294967296.0)
+    return fail(SIM_E_INVAL, "n_envs %d x ckpt_every %d too large for a differentiable handle",
+                c->n_envs, c->ckpt_every);
   if (!finite_pos(c->dt) || !finite_pos(c->g) || !finite_pos(c->arm) || !std::isfinite(c->k_m))
     return fail(SIM_E_INVAL, "dt, g, arm must be finite and positive");
   if (!std::isfinite(c->rpm_min) || !std::isfinite(c->rpm_max) || !(c->rpm_max > c->rpm_min))

@@ -20,7 +20,7 @@ struct BwdBufs {
              e_dw[BWD_NBUF] = {};
   float* lam = nullptr;    // [145][N] state and history adjoints between segments
   float* gth = nullptr;    // [8][N] parameter gradients
-  float* gpart = nullptr;  // [n_parts][13828] weight-gradient partials, one per slot
+  float* gpart = nullptr;  // [n_parts] weight-gradient partial slots (k_bwd_dw's layout)
   float* gsum = nullptr;   // [13828] sink when no actor gradient is requested
 };
 

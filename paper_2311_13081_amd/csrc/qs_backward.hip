@@ -3,7 +3,8 @@
 // The taped forward stored checkpoints (state, history) every K steps.  The
 // backward walks the segments last to first; per segment:
 //   1. recompute: the fused MFMA kernel restarts from the checkpoint and
-//      records x_t, a_t, the layer pre-activations z1, z2 and o_t per step;
+//      records x_t, a_t, the layer pre-activations z1, z2 and the state
+//      features of o_t per step (the history features are earlier actions);
 //   2. reverse sweep (k_bwd_reverse): four lanes per env, the adjoints of
 //      the state and of the action history in registers, stepping back
 //      through reward, quaternion renormalisation, the four RK4 stages, the
@@ -11,10 +12,11 @@
 //      parameter gradients accumulate in registers; the layer cotangents
 //      dz1, dz2, dz3 of every (step, env) go to scratch;
 //   3. weight gradients (k_bwd_dw): sum over (step, env) rows of dz (x) input
-//      on fp32 MFMA, one workgroup per 64-env chunk accumulating into its own
-//      partial; biases come from a constant-one input column.
-// Finally k_bwd_reduce adds the workgroup partials in ascending order, so
-// the result does not depend on scheduling.
+//      on fp32 MFMA, one workgroup per (64-env chunk, step group)
+//      accumulating into its own partial; biases come from a constant-one
+//      input column.
+// Finally k_bwd_reduce adds the workgroup partials in a fixed order, so the
+// result does not depend on scheduling.
 #include "qs_actor.h"
 #include "qs_backward.h"
 #include "qs_forward.h"
@@ -101,7 +103,7 @@ __device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __res
   const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
   const uint32_t zoff = opaque((uint32_t)(rb_at(e, REC_F) + 4 * k * RB));
   const int t = t0 + tl;
-  const float* rt = rec + (size_t)tl * REC_F * rb_pad(N);
+  const float* rt = rec + rec_step(tl, N);
 #pragma unroll
   for (int i = 0; i < NS; ++i) in.x[i] = rt[(size_t)(REC_X + i) * RB + roff];
 #pragma unroll
@@ -370,212 +372,348 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 // Weight gradients of one segment: for every (step, env) row,
 //   dW1 += dz1 o^T, dW2 += dz2 relu(z1)^T, dW3 += dz3 relu(z2)^T, db += dz,
 // on fp32 MFMA (v_mfma_f32_16x16x4f32) with the rows as the K dimension:
-// A[i][k] (lane i + 16 k) = dz of neuron 16 w + i at env e0 + k, B[k][j] =
-// input column j of a 16-column tile at the same env; the result register r
-// of a tile holds row 4 lg + r, column li.  Biases come from a constant-one
+// A[i][k] (lane i + 16 k) = dz of neuron 16 n + i at env e0 + k, B[k][j] =
+// input column 16 t + j at the same env; result register r of a tile holds
+// neuron 16 n + 4 lg + r, column 16 t + li.  Biases come from a constant-one
 // input column (generated, not stored).
 //
-// One workgroup per (64-env block, step group), one wave per 16-neuron tile
-// w.  The layer inputs of a step (o, relu(z1), relu(z2): 274 rows x 64 envs,
-// read once from HBM as whole 256-byte block rows) are staged in LDS and
-// shared by the four waves; the staging of step t + 1 is issued into
-// registers before step t's matrix work and written to the other LDS buffer
-// after it, so the loads' latency hides behind the MFMAs.  Each wave reads its
-// own dz rows straight from the record, also one step ahead.  Layer 3 (4
-// outputs) is split by column tiles: wave w takes tile w, wave 0 also tile 4
-// (the bias column).  Each (block, step group) owns one partial slot,
-// accumulated across segments.
-constexpr int DW_ROWS = NO + 2 * NHID;  // staged input rows per step: o | z1 | z2
-constexpr int DW_P = 68;                // LDS row pitch in floats (64 envs + 4)
-constexpr int DW_BUF = DW_ROWS * DW_P;  // floats per staging buffer
-constexpr int DW_LD = (DW_ROWS * 16 + 255) / 256;  // float4 staging loads per thread
+// One workgroup of 8 waves per (64-env block, step group).  The output tiles
+// are split by input column.  Column tiles 0..9 are layer 1's (147 columns
+// with the bias), 10..14 layer 2's and 15..19 layer 3's (65 each); tiles 14
+// and 19 hold only the bias column and are generated, not loaded.  A layer-1
+// or -2 tile carries its 4 neuron tiles, a layer-3 tile 1 (4 outputs).  The
+// groups: 0 {0 4 8 12}, 1 {1 5 9 13}, 2 {2 6 10 11}, 3 {3 7 14 15..19}: 16,
+// 16, 16 and 17 output tiles, and every input value is read by one group
+// only (the dz rows, a third of the bytes, by all four, through L2).  Waves
+// g and g + 4 run column group g on alternate steps -- two waves per SIMD, so
+// one's loads overlap the other's matrix work -- and add their sums through
+// LDS at the end, half 0 first.  Operands come straight from the record, one
+// 16-env slab ahead: no staging and no barrier in the loop.  The history
+// features of o_t are the actions of the 32 previous steps, read from the
+// segment's action tape (one contiguous span per 64-env block).
+constexpr int DW_MAXT = 17;  // output tiles of a column group
 
-// Four consecutive envs e..e+3 of one blocked row (p points at env e);
-// envs >= N read as zero.
-__device__ inline f4 dw_load(const float* __restrict__ p, int e, int N) {
-  if (e + 4 <= N) return *reinterpret_cast<const f4*>(p);
-  f4 v;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) v[m] = e + m < N ? p[m] : 0.0f;
-  return v;
+__host__ __device__ constexpr int dw_tile(int G, int i) {
+  return G == 0   ? (i < 4 ? 4 * i : -1)
+         : G == 1 ? (i < 4 ? 1 + 4 * i : -1)
+         : G == 2 ? (i < 2 ? 2 + 4 * i : i < 4 ? 8 + i : -1)
+                  : (i < 2 ? 3 + 4 * i : i < 8 ? 12 + i : -1);
 }
+__host__ __device__ constexpr int dw_ntile(int G) { return G == 3 ? 8 : 4; }
+__host__ __device__ constexpr int dw_nacc(int t) { return t < 15 ? 4 : 1; }
+__host__ __device__ constexpr bool dw_const(int t) { return t == 14 || t == 19; }
+// first accumulator of column tile i of group G (only group 3's tiles 3..7
+// are layer-3 tiles, one accumulator each)
+__host__ __device__ constexpr int dw_acc0(int G, int i) {
+  return G < 3 || i < 3 ? 4 * i : 12 + (i - 3);
+}
+static_assert(dw_acc0(3, 8) == DW_MAXT && dw_acc0(0, 4) == 16 && dw_acc0(2, 4) == 16 &&
+                  dw_acc0(3, 3) == dw_acc0(3, 2) + dw_nacc(dw_tile(3, 2)),
+              "column-group tile counts");
 
-struct DwStage {
-  f4 v[DW_LD];
+// Operands of one 16-env slab for column group G: the dz1 and dz2 tiles of
+// the four neuron tiles, dz3 (group 3), and the B tiles of its loaded
+// columns (slot i of column tile i; the bias-only tiles use no slot).
+template <int G>
+struct DwOps {
+  f4 a1[4], a2[4], a3;
+  f4 b[dw_ntile(G)];
 };
 
-// Issues the staging loads of one step (input row r, envs 4 c4 .. 4 c4 + 3
-// for slot i of thread tid: r = tid / 16 + 16 i, c4 = tid % 16).
-__device__ inline void dw_stage_load(DwStage& sg, const float* __restrict__ rt, int env0, int N,
-                                     int tid) {
-  const int c = (tid & 15) * 4;
+__device__ inline f4 const4(float v) { return f4{v, v, v, v}; }
+
+// Raw buffer view of a device array (bounds-checked by the hardware against
+// `bytes`: out-of-range loads read zero).  Loads take a 32-bit per-lane byte
+// offset, a uniform byte offset and a constant, so the per-tile and per-step
+// parts of an address stay scalar.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline f4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// A column tile whose rows depend on the lane only through li (state
+// features, z rows) is addressed as a uniform row offset plus the lane's
+// offset li * RB + 4 lg; a tile with history columns needs a per-lane offset
+// (the source step depends on the column).
+__host__ __device__ constexpr bool dw_hist(int t) { return t >= 1 && t < 10; }
+
+// Addressing of one step, in bytes from the dz and record buffers: uniform
+// offsets of this step's block, and the per-lane offsets of the history
+// tiles.
+template <int G>
+struct DwAddr {
+  uint32_t dzs, rs;
+  uint32_t h[dw_ntile(G)];
+};
+
+template <int G>
+__device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, int li, int lg) {
+  const uint32_t rbp = (uint32_t)rb_pad(N), rstep = (uint32_t)REC_F * rbp;
+  d.dzs = 4u * ((uint32_t)tl * (DZ_F * rbp) + (uint32_t)chunk * (DZ_F * RB));
+  d.rs = 4u * ((uint32_t)tl * rstep + (uint32_t)chunk * (REC_F * RB));
+  const uint32_t c4 = 4 * lg;
+  const uint32_t rbo = (uint32_t)tl * rstep + (uint32_t)chunk * (REC_F * RB) + c4;
+  // this block's action tape; history slot sl of step tl is tape slot tl + sl
+  const uint32_t tape = (uint32_t)n * rstep + (uint32_t)chunk * ((NH + n) * NA * RB) + c4;
 #pragma unroll
-  for (int i = 0; i < DW_LD; ++i) {
-    const int r = (tid >> 4) + 16 * i;
-    const int f = r < NO ? REC_O + r : REC_Z1 + (r - NO);  // z1 and z2 rows are adjacent
-    sg.v[i] = r < DW_ROWS ? dw_load(rt + (size_t)f * RB + c, env0 + c, N)
-                          : f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < dw_ntile(G); ++i) {
+    const int t = dw_tile(G, i);
+    if (!dw_hist(t)) continue;
+    const int col = 16 * t + li;
+    const int hc = col < 18 ? 0 : col < NO ? col - 18 : 0;
+    const uint32_t o_hist = tape + (uint32_t)((tl + (hc >> 2)) * NA + (hc & 3)) * RB;
+    d.h[i] = 4u * (col < 18 ? rbo + (REC_O + col) * RB : col < NO ? o_hist : rbo);
   }
 }
 
-// Writes staged rows to an LDS buffer: ReLU on the z rows, bf16 rounding of
-// every input when the forward rounded it.
-__device__ inline void dw_stage_store(const DwStage& sg, float* buf, int tid, int bf16) {
-  const int c = (tid & 15) * 4;
+// Issues the loads of slab q of a step; dw_prepare finishes the operands when
+// they are used, so the loads stay in flight during the previous slab's
+// matrix work.  Every lane of a loaded tile loads (lanes of constant columns
+// from a valid address, replaced later), so no load sits under a branch.
+// loff: the lane's byte offset 4 (li * RB + 4 lg).
+template <int G>
+__device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec,
+                                    __amdgpu_buffer_rsrc_t rdz, const DwAddr<G>& d, uint32_t loff,
+                                    int q) {
 #pragma unroll
-  for (int i = 0; i < DW_LD; ++i) {
-    const int r = (tid >> 4) + 16 * i;
-    if (r < DW_ROWS) {
-      f4 v = sg.v[i];
+  for (int nt = 0; nt < 4; ++nt) {
+    o.a1[nt] = bld4(rdz, loff + 64 * q, d.dzs + 4 * (16 * nt * RB));
+    o.a2[nt] = bld4(rdz, loff + 64 * q, d.dzs + 4 * ((NHID + 16 * nt) * RB));
+  }
+  if (G == 3) o.a3 = bld4(rdz, loff + 64 * q, d.dzs + 4 * (2 * NHID * RB));
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (r >= NO) v[m] = fmaxf(v[m], 0.0f);
-        if (bf16) v[m] = (float)(__bf16)v[m];
-      }
-      *reinterpret_cast<f4*>(&buf[r * DW_P + c]) = v;
+  for (int i = 0; i < dw_ntile(G); ++i) {
+    const int t = dw_tile(G, i);
+    if (dw_const(t)) continue;
+    if (dw_hist(t)) {
+      o.b[i] = bld4(rrec, d.h[i] + 64 * q, 0);
+    } else {
+      const int row = t == 0 ? REC_O : t < 15 ? REC_Z1 + 16 * (t - 10) : REC_Z2 + 16 * (t - 15);
+      o.b[i] = bld4(rrec, loff + 64 * q, d.rs + 4 * (row * RB));
     }
   }
 }
 
-struct DwA {
-  f4 a1[4], a2[4], a3[4];
-};
-
-__device__ inline void dw_a_load(DwA& A, const float* __restrict__ dzt, int env0, int N, int w,
-                                 int li, int lg) {
+// ReLU of the pre-activation columns, the constant columns (ones at the bias
+// column, zeros beyond), the forward's bf16 rounding of its inputs and dz3
+// rows only for the 4 outputs.  Envs >= N of the last block need nothing:
+// their record and dz slots are zero (cleared at allocation, never written).
+template <int G, bool BF16>
+__device__ inline void dw_prepare(DwOps<G>& o, int li) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int col = 16 * q + 4 * lg;
-    A.a1[q] = dw_load(dzt + (size_t)(16 * w + li) * RB + col, env0 + col, N);
-    A.a2[q] = dw_load(dzt + (size_t)(NHID + 16 * w + li) * RB + col, env0 + col, N);
-    A.a3[q] = li < NA ? dw_load(dzt + (size_t)(2 * NHID + li) * RB + col, env0 + col, N)
-                      : f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < dw_ntile(G); ++i) {
+    const int t = dw_tile(G, i);
+    if (dw_const(t)) continue;
+    const int n_in = t < 10 ? NO : NHID;
+    const int col0 = t < 10 ? 16 * t : 16 * (t < 15 ? t - 10 : t - 15);
+    const int col = col0 + li;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float v = t < 10 ? o.b[i][m] : relu_bits(o.b[i][m]);
+      if (BF16) v = (float)(__bf16)v;
+      // only a tile that reaches the bias column has constant lanes
+      o.b[i][m] = col0 + 15 < n_in ? v : col < n_in ? v : col == n_in ? 1.0f : 0.0f;
+    }
+  }
+  if (G == 3)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o.a3[m] = li < NA ? o.a3[m] : 0.0f;
+}
+
+// bias1: B of a bias-only tile (column 64 = lane li 0).
+template <int G>
+__device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, float bias1) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int i = 0; i < dw_ntile(G); ++i) {
+      const int t = dw_tile(G, i), a0 = dw_acc0(G, i);
+      const float bv = dw_const(t) ? bias1 : o.b[i][m];
+      if (t < 15) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          acc[a0 + nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(t < 10 ? o.a1[nt][m] : o.a2[nt][m],
+                                                              bv, acc[a0 + nt], 0, 0, 0);
+      } else {
+        acc[a0] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a3[m], bv, acc[a0], 0, 0, 0);
+      }
+    }
+}
+
+// This half's steps t_lo + half, t_lo + half + 2, ... of the group, the four
+// 16-env slabs of a step in turn, each slab's loads issued one slab ahead
+// into the other of two operand buffers (a copy between them would wait for
+// the loads in flight).  After the last step the look-ahead load repeats
+// that step's slab 0 rather than branch.
+template <int G, bool BF16>
+__device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
+                                     const float* __restrict__ dz, int N, int chunk, int t_lo,
+                                     int t_hi, int n, int half) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int t_first = t_lo + half;
+  if (t_first >= t_hi) return;
+  const uint32_t rbp = (uint32_t)rb_pad(N);
+  const __amdgpu_buffer_rsrc_t rrec =
+      buf_rsrc(rec, 4u * ((uint32_t)n * REC_F * rbp + (uint32_t)(NH + n) * NA * rbp));
+  const __amdgpu_buffer_rsrc_t rdz = buf_rsrc(dz, 4u * ((uint32_t)n * DZ_F * rbp));
+  const uint32_t loff = 4u * (uint32_t)(li * RB + 4 * lg);
+  const float bias1 = li == 0 ? 1.0f : 0.0f;
+  DwOps<G> ob0, ob1;
+  DwAddr<G> d;
+  dw_addr<G>(d, t_first, n, chunk, N, li, lg);
+  dw_load_slab<G>(ob0, rrec, rdz, d, loff, 0);
+  // scheduling barriers keep each slab's loads ahead of the previous slab's
+  // matrix work (left alone, the scheduler interleaves a slab's products
+  // with its own loads and the waits then cover the loads just issued)
+  for (int tl = t_first; tl < t_hi; tl += 2) {
+    dw_load_slab<G>(ob1, rrec, rdz, d, loff, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_prepare<G, BF16>(ob0, li);
+    dw_mfma<G>(acc, ob0, bias1);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_load_slab<G>(ob0, rrec, rdz, d, loff, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_prepare<G, BF16>(ob1, li);
+    dw_mfma<G>(acc, ob1, bias1);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_load_slab<G>(ob1, rrec, rdz, d, loff, 3);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_prepare<G, BF16>(ob0, li);
+    dw_mfma<G>(acc, ob0, bias1);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_addr<G>(d, tl + 2 < t_hi ? tl + 2 : tl, n, chunk, N, li, lg);
+    dw_load_slab<G>(ob0, rrec, rdz, d, loff, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    dw_prepare<G, BF16>(ob1, li);
+    dw_mfma<G>(acc, ob1, bias1);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// B operand: input column `row` of a layer with n_in inputs whose staged
-// rows start at LDS row `base`: the staged value, the bias column of ones
-// (valid envs) at row == n_in, zeros beyond.
-__device__ inline f4 dw_b(const float* buf, int base, int row, int n_in, int col, int env0,
-                          int N) {
-  if (row < n_in) return *reinterpret_cast<const f4*>(&buf[(base + row) * DW_P + col]);
-  f4 v;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) v[m] = (row == n_in && env0 + col + m < N) ? 1.0f : 0.0f;
-  return v;
+// A partial slot holds the sums in the tiles' own register layout:
+// [group 4][output tile 17][lane 64][register 4] floats, so a wave adds its
+// tiles with whole-wave vector loads and stores; dw_slot maps a flat
+// gradient index to its place in a slot (k_bwd_reduce gathers with it).
+constexpr int DW_SLOT = 4 * DW_MAXT * 64 * 4;
+
+// owner (group, tile slot i) of column tile t: the inverse of dw_tile
+__host__ __device__ constexpr int dw_owner_g(int t) {
+  return t < 10 ? t % 4 : t == 10 || t == 11 ? 2 : t == 12 ? 0 : t == 13 ? 1 : 3;
+}
+__host__ __device__ constexpr int dw_owner_i(int t) {
+  return t < 10 ? t / 4 : t == 10 ? 2 : t == 11 ? 3 : t == 12 || t == 13 ? 3 : t == 14 ? 2 : t - 12;
+}
+static_assert(dw_tile(dw_owner_g(11), dw_owner_i(11)) == 11 &&
+                  dw_tile(dw_owner_g(14), dw_owner_i(14)) == 14 &&
+                  dw_tile(dw_owner_g(17), dw_owner_i(17)) == 17 &&
+                  dw_tile(dw_owner_g(9), dw_owner_i(9)) == 9,
+              "tile owners");
+
+// Place in a slot of the sum for (neuron or output row, column) of column
+// tile t (column within the tile c = 0..15).
+__host__ __device__ constexpr int dw_place(int t, int row, int c) {
+  const int g = dw_owner_g(t), i = dw_owner_i(t);
+  const int acc = t < 15 ? dw_acc0(g, i) + row / 16 : dw_acc0(g, i);
+  const int r = t < 15 ? row % 16 : row;  // row within the 16-row tile
+  const int lane = c + 16 * (r / 4);
+  return ((g * DW_MAXT + acc) * 64 + lane) * 4 + r % 4;
 }
 
-__global__ void __launch_bounds__(256)
+// flat gradient index (torch Linear layout) -> place in a slot
+__device__ inline int dw_slot(int idx) {
+  if (idx < OFF_B1) {
+    const int nrn = idx / NO, col = idx % NO;
+    return dw_place(col / 16, nrn, col % 16);
+  }
+  if (idx < OFF_W2) return dw_place(NO / 16, idx - OFF_B1, NO % 16);
+  if (idx < OFF_B2) {
+    const int nrn = (idx - OFF_W2) / NHID, col = (idx - OFF_W2) % NHID;
+    return dw_place(10 + col / 16, nrn, col % 16);
+  }
+  if (idx < OFF_W3) return dw_place(14, idx - OFF_B2, 0);
+  if (idx < OFF_B3) {
+    const int o = (idx - OFF_W3) / NHID, col = (idx - OFF_W3) % NHID;
+    return dw_place(15 + col / 16, o, col % 16);
+  }
+  return dw_place(19, idx - OFF_B3, 0);
+}
+
+// grid (64-env blocks, S step groups), 512 threads; group sg takes steps
+// [sg * per, min(n, (sg + 1) * per)), per = ceil(n / S), and accumulates
+// into its own partial slot (chunk * S + sg) across segments.
+template <bool BF16>
+__global__ void __launch_bounds__(512)
 k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n, int S,
-         float* __restrict__ gpart, int bf16) {
-  extern __shared__ __attribute__((aligned(16))) float sm[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int chunk = blockIdx.x, w = tid >> 6, sg = blockIdx.y;
-  const int env0 = chunk * RB;
+         float* __restrict__ gpart) {
+  __shared__ f4 xacc[4][DW_MAXT][64];
+  const int chunk = blockIdx.x, sg = blockIdx.y;
+  // the wave index is uniform across the wave: keep it (and every offset
+  // derived from it) in scalar registers
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = wv & 3, half = wv >> 2;
   const int per = (n + S - 1) / S;
-  const int t_begin = sg * per, t_end = (t_begin + per) < n ? (t_begin + per) : n;
-  const size_t rstep = (size_t)REC_F * rb_pad(N), dstep = (size_t)DZ_F * rb_pad(N);
-  const float* rblk = rec + (size_t)chunk * REC_F * RB;
-  const float* dblk = dz + (size_t)chunk * DZ_F * RB;
-
-  f4 acc1[10], acc2[5], acc3[2];
+  const int t_lo = sg * per, t_hi = (t_lo + per) < n ? (t_lo + per) : n;
+  f4 acc[DW_MAXT];
 #pragma unroll
-  for (int i = 0; i < 10; ++i) acc1[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int i = 0; i < 5; ++i) acc2[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  acc3[0] = acc3[1] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-
-  if (t_begin < t_end) {
-    DwStage st;
-    DwA A, An;
-    dw_stage_load(st, rblk + (size_t)t_begin * rstep, env0, N, tid);
-    dw_a_load(A, dblk + (size_t)t_begin * dstep, env0, N, w, li, lg);
-    dw_stage_store(st, sm, tid, bf16);
-    __syncthreads();
-    for (int tl = t_begin; tl < t_end; ++tl) {
-      const int cur = (tl - t_begin) & 1;
-      const float* buf = sm + cur * DW_BUF;
-      const bool more = tl + 1 < t_end;
-      if (more) {  // next step's loads in flight during this step's MFMAs
-        dw_stage_load(st, rblk + (size_t)(tl + 1) * rstep, env0, N, tid);
-        dw_a_load(An, dblk + (size_t)(tl + 1) * dstep, env0, N, w, li, lg);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col = 16 * q + 4 * lg;
-        // independent accumulators innermost, so consecutive MFMAs never
-        // wait on each other's results
-        f4 bo[10], bh[5];
-#pragma unroll
-        for (int kt = 0; kt < 10; ++kt) bo[kt] = dw_b(buf, 0, 16 * kt + li, NO, col, env0, N);
-#pragma unroll
-        for (int kt = 0; kt < 5; ++kt) bh[kt] = dw_b(buf, NO, 16 * kt + li, NHID, col, env0, N);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-#pragma unroll
-          for (int kt = 0; kt < 10; ++kt)
-            acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a1[q][m], bo[kt][m], acc1[kt], 0, 0, 0);
-#pragma unroll
-          for (int kt = 0; kt < 5; ++kt)
-            acc2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a2[q][m], bh[kt][m], acc2[kt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (j == 1 && w != 0) break;
-          const int kt = j == 0 ? w : 4;
-          const f4 bh = dw_b(buf, NO + NHID, 16 * kt + li, NHID, col, env0, N);
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-            acc3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a3[q][m], bh[m], acc3[j], 0, 0, 0);
-        }
-      }
-      if (more) {
-        dw_stage_store(st, sm + (cur ^ 1) * DW_BUF, tid, bf16);
-        A = An;
-      }
-      __syncthreads();  // next buffer complete; this buffer free for reuse
-    }
+  for (int i = 0; i < DW_MAXT; ++i) acc[i] = const4(0.0f);
+  switch (g) {
+    case 0: dw_accumulate<0, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
+    case 1: dw_accumulate<1, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
+    case 2: dw_accumulate<2, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
+    default: dw_accumulate<3, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
   }
-  float* gp = gpart + ((size_t)chunk * S + sg) * NW;
+  // half 1 hands its sums to half 0 (fixed order: half 0 + half 1)
+  if (half == 1)
 #pragma unroll
-  for (int kt = 0; kt < 10; ++kt)
+    for (int i = 0; i < DW_MAXT; ++i) xacc[g][i][lane] = acc[i];
+  __syncthreads();
+  if (half == 1) return;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int nrn = 16 * w + 4 * lg + r, col = 16 * kt + li;
-      if (col < NO) gp[OFF_W1 + nrn * NO + col] += acc1[kt][r];
-      else if (col == NO) gp[OFF_B1 + nrn] += acc1[kt][r];
-    }
+  for (int i = 0; i < DW_MAXT; ++i) {
+    const f4 o = xacc[g][i][lane];
 #pragma unroll
-  for (int kt = 0; kt < 5; ++kt)
+    for (int r = 0; r < 4; ++r) acc[i][r] += o[r];
+  }
+  // add into this group's part of the slot: all loads, then all stores
+  f4* gp = reinterpret_cast<f4*>(gpart + ((size_t)chunk * S + sg) * DW_SLOT) + g * DW_MAXT * 64;
+  f4 old[DW_MAXT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int nrn = 16 * w + 4 * lg + r, col = 16 * kt + li;
-      if (col < NHID) gp[OFF_W2 + nrn * NHID + col] += acc2[kt][r];
-      else if (col == NHID) gp[OFF_B2 + nrn] += acc2[kt][r];
-    }
+  for (int i = 0; i < DW_MAXT; ++i) old[i] = gp[i * 64 + lane];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    if (j == 1 && w != 0) break;
-    const int kt = j == 0 ? w : 4;
+  for (int i = 0; i < DW_MAXT; ++i) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 4 * lg + r, col = 16 * kt + li;
-      if (o < NA) {
-        if (col < NHID) gp[OFF_W3 + o * NHID + col] += acc3[j][r];
-        else if (col == NHID) gp[OFF_B3 + o] += acc3[j][r];
-      }
-    }
+    for (int r = 0; r < 4; ++r) old[i][r] += acc[i][r];
+    gp[i * 64 + lane] = old[i];
   }
 }
 
-// grad[i] = sum over workgroups of gpart[g][i], in ascending g.
-__global__ void k_bwd_reduce(const float* __restrict__ gpart, int G, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NW) return;
+// grad[i] = sum over the G partial slots of slot g's entry for i, in a fixed
+// order:
+// DR_SPLIT threads per output each add a contiguous range of slots in
+// ascending order, then the range sums are added in ascending range order.
+constexpr int DR_OUT = 32, DR_SPLIT = 8;
+__global__ void __launch_bounds__(DR_OUT * DR_SPLIT)
+k_bwd_reduce(const float* __restrict__ gpart, int G, float* __restrict__ out) {
+  __shared__ float part[DR_SPLIT][DR_OUT];
+  const int tx = threadIdx.x % DR_OUT, ty = threadIdx.x / DR_OUT;
+  const int i = blockIdx.x * DR_OUT + tx;
+  const int per = (G + DR_SPLIT - 1) / DR_SPLIT;
+  const int g0 = ty * per, g1 = (g0 + per) < G ? (g0 + per) : G;
   float s = 0.0f;
-  for (int g = 0; g < G; ++g) s += gpart[(size_t)g * NW + i];
-  out[i] = s;
+  if (i < NW) {
+    const int pl = dw_slot(i);
+#pragma unroll 8
+    for (int gg = g0; gg < g1; ++gg) s += gpart[(size_t)gg * DW_SLOT + pl];
+  }
+  part[ty][tx] = s;
+  __syncthreads();
+  if (ty != 0 || i >= NW) return;
+  float t = part[0][tx];
+#pragma unroll
+  for (int r = 1; r < DR_SPLIT; ++r) t += part[r][tx];
+  out[i] = t;
 }
 
 __global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, size_t n) {
@@ -599,14 +737,18 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
       (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   }
   int S = n_cu / chunks;
-  if (S > K) S = K;
+  if (S > K / 2) S = K / 2;  // at least two steps per group: one per half
   if (S < 1) S = 1;
   bw.dw_groups = S;
   bw.n_parts = chunks * S;
   hipError_t e;
   for (int i = 0; i < BWD_NBUF; ++i) {
-    if ((e = hipMalloc(&bw.seg[i], (size_t)K * REC_F * rb_pad(N) * 4)) != hipSuccess) return e;
+    // zeroed once: the slots of envs >= N in the last 64-env block are never
+    // written and must read as zero in the weight-gradient pass
+    if ((e = hipMalloc(&bw.seg[i], rec_floats(K, N) * 4)) != hipSuccess) return e;
+    if ((e = hipMemset(bw.seg[i], 0, rec_floats(K, N) * 4)) != hipSuccess) return e;
     if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
+    if ((e = hipMemset(bw.dz[i], 0, (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_rec[i], hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_rev[i], hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&bw.e_dw[i], hipEventDisableTiming)) != hipSuccess) return e;
@@ -621,14 +763,10 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   if ((e = hipStreamCreateWithFlags(&bw.s_dw, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.lam, (size_t)LAM_F * N * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gth, (size_t)NP * N * 4)) != hipSuccess) return e;
-  if ((e = hipMalloc(&bw.gpart, (size_t)bw.n_parts * NW * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&bw.gpart, (size_t)bw.n_parts * DW_SLOT * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gsum, (size_t)NW * 4)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_bwd_reverse,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4)) !=
-      hipSuccess)
-    return e;
-  return hipFuncSetAttribute((const void*)k_bwd_dw, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             2 * DW_BUF * 4);
+  return hipFuncSetAttribute((const void*)k_bwd_reverse,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4);
 }
 
 void bwd_free(BwdBufs& bw) {
@@ -672,7 +810,7 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
                         const float* d_states, float* grad_actor, float* grad_params,
                         hipStream_t st) {
   const int N = c.n_envs;
-  const size_t np = (size_t)bw.n_parts * NW;
+  const size_t np = (size_t)bw.n_parts * DW_SLOT;
   hipLaunchKernelGGL(k_fill, dim3(nb((int)np, 256)), dim3(256), 0, st, bw.gpart, np, 0.0f);
   hipLaunchKernelGGL(k_bwd_init, dim3(nb(N, 256)), dim3(256), 0, st, N,
                      d_states ? d_states + (size_t)T * NS * N : nullptr, bw.lam, bw.gth);
@@ -703,15 +841,16 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
       BWD_TRY(hipEventRecord(bw.e_rev[buf], st));
       BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_rev[buf], 0));
     }
-    hipLaunchKernelGGL(k_bwd_dw, dim3(nb(N, 64), bw.dw_groups), dim3(256), 2 * DW_BUF * 4, s_dw, N,
-                       bw.seg[buf], bw.dz[buf], n, bw.dw_groups, bw.gpart,
-                       (c.flags & F_ACTOR_BF16) ? 1 : 0);
+    hipLaunchKernelGGL((c.flags & F_ACTOR_BF16) ? k_bwd_dw<true> : k_bwd_dw<false>,
+                       dim3(nb(N, 64), bw.dw_groups), dim3(512), 0, s_dw, N, bw.seg[buf],
+                       bw.dz[buf], n, bw.dw_groups, bw.gpart);
     BWD_TRY(hipGetLastError());
     if (overlap) BWD_TRY(hipEventRecord(bw.e_dw[buf], s_dw));
     last = buf;
   }
   if (overlap) BWD_TRY(hipStreamWaitEvent(st, bw.e_dw[last], 0));
-  hipLaunchKernelGGL(k_bwd_reduce, dim3(nb(NW, 256)), dim3(256), 0, st, bw.gpart, bw.n_parts,
+  hipLaunchKernelGGL(k_bwd_reduce, dim3(nb(NW, DR_OUT)), dim3(DR_OUT * DR_SPLIT), 0, st, bw.gpart,
+                     bw.n_parts,
                      grad_actor ? grad_actor : bw.gsum);
   if (grad_params)
     hipLaunchKernelGGL(k_copy, dim3(nb(NP * N, 256)), dim3(256), 0, st, bw.gth, grad_params,

@@ -33,10 +33,16 @@ hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* ac
                               int T, float* rewards, uint8_t* dones, float* states,
                               hipStream_t st);
 // Per-step record of the backward recompute, REC_F rows per env: x_t (17),
-// a_t (4), layer-1 and layer-2 pre-activations (64 + 64), observation o_t
-// (146).
+// a_t (4), layer-1 and layer-2 pre-activations (64 + 64) and the 18 state
+// features of the observation o_t (as the actor saw them, noise included).
+// The 128 history features of o_t are not stored per step: they are the
+// actions of the 32 previous steps.  After the n step records of a segment
+// comes its action tape: per 64-env block, (NH + n) slots of NA rows, slot s
+// < NH the checkpoint's history slot s (oldest first), slot NH + t the
+// action of step t; the history slot sl of step t is tape slot t + sl.  One
+// block's tape is one contiguous span (48 KB for n = 16).
 constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z1 + NHID,
-              REC_O = REC_Z2 + NHID, REC_F = REC_O + NO;
+              REC_O = REC_Z2 + NHID, REC_F = REC_O + 18;
 
 // Tape checkpoint of a differentiable rollout, CK_F rows of [N]: state (17),
 // history oldest first (128), then the step within the episode and the
@@ -54,6 +60,13 @@ constexpr int RB = 64;
 __host__ __device__ inline size_t rb_pad(int N) { return (size_t)((N + RB - 1) / RB) * RB; }
 __host__ __device__ inline size_t rb_at(int e, int F) {
   return (size_t)(e / RB) * F * RB + (size_t)(e % RB);
+}
+// Step t of a record buffer, and the action tape of a segment of n steps.
+__host__ __device__ inline size_t rec_step(int t, int N) { return (size_t)t * REC_F * rb_pad(N); }
+__host__ __device__ inline size_t rec_act(int n, int N) { return (size_t)n * REC_F * rb_pad(N); }
+// floats of a record buffer for segments of up to K steps
+__host__ __device__ inline size_t rec_floats(int K, int N) {
+  return ((size_t)K * REC_F + (size_t)(NH + K) * NA) * rb_pad(N);
 }
 
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,

@@ -319,7 +319,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     }
     // observation state part: 18 features, this quarter keeps 4c + k
     quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F);
-    float* rt = rec_on ? rec + (size_t)t * REC_F * rb_pad(N) : nullptr;
+    float* rt = rec_on ? rec + rec_step(t, N) : nullptr;
     float z3[NA];
     // per-lane part of record addresses, recomputed every step (see opaque())
     const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
@@ -335,12 +335,19 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
     if (rec_on && active) {
+      // the state features (feature 4 cc + k); the history ones are earlier
+      // actions, kept on the segment's action tape
 #pragma unroll
-      for (int cc = 0; cc < Q_C; ++cc) {
-        // feature q_phi(cc, k) = base + k for valid slots
-        const int base = cc < 5 ? 4 * cc : 18 + 4 * (cc - 5);
-        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + base) * RB + koff] = F[cc];
+      for (int cc = 0; cc < 5; ++cc)
+        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + 4 * cc) * RB + koff] = F[cc];
+      // action tape of the segment: the checkpoint history once, then a_t
+      float* act = rec + rec_act(T, N);
+      const uint32_t aoff = opaque((uint32_t)(rb_at(e, (NH + T) * NA) + k * RB));
+      if (t == 0) {
+#pragma unroll
+        for (int s = 0; s < NH; ++s) act[(size_t)(s * NA) * RB + aoff] = F[5 + s];
       }
+      act[(size_t)((NH + t) * NA) * RB + aoff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
 #pragma unroll
       for (int i = 0; i < NS; ++i)
         if ((i & 3) == k) rt[(size_t)(REC_X + i) * RB + roff] = x[i];
