@@ -37,18 +37,35 @@ __global__ void k_init(DevCfg c, SimBufs b, int params) {
   b.ep[e] = 0;
 }
 
+// Snapshot copies.  Each thread loads a batch of rows before storing any of
+// them: the source and destination may not be assumed disjoint, so a
+// load-store-load sequence would wait out one memory round trip per row.
 __global__ void k_get_state(SimBufs b, int N, float* state, float* hist, int32_t* t_ep,
                             int32_t* ep) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
-  if (state)
-    for (int i = 0; i < NS; ++i) state[i * N + e] = b.state[i * N + e];
+  if (state) {
+    float v[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = b.state[i * N + e];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) state[i * N + e] = v[i];
+  }
   if (hist) {
     const int h = b.head[e];
-    for (int s = 0; s < NH; ++s) {
-      const int slot = (h + s) & (NH - 1);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) hist[(s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+    for (int s0 = 0; s0 < NH; s0 += 8) {
+      float v[8 * NA];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int slot = (h + s0 + s) & (NH - 1);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) v[s * NA + a] = b.ring[(slot * NA + a) * N + e];
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) hist[((s0 + s) * NA + a) * N + e] = v[s * NA + a];
     }
   }
   if (t_ep) t_ep[e] = b.t_ep[e];
@@ -59,10 +76,22 @@ __global__ void k_set_state(SimBufs b, int N, const float* state, const float* h
                             const int32_t* t_ep, const int32_t* ep) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
-  if (state)
-    for (int i = 0; i < NS; ++i) b.state[i * N + e] = state[i * N + e];
+  if (state) {
+    float v[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = state[i * N + e];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) b.state[i * N + e] = v[i];
+  }
   if (hist) {
-    for (int i = 0; i < NH * NA; ++i) b.ring[i * N + e] = hist[i * N + e];
+#pragma unroll
+    for (int i0 = 0; i0 < NH * NA; i0 += 32) {
+      float v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = hist[(i0 + i) * N + e];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) b.ring[(i0 + i) * N + e] = v[i];
+    }
     b.head[e] = 0;
   }
   if (t_ep) b.t_ep[e] = t_ep[e];
