@@ -269,7 +269,8 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
         HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
                               st));
       else if (variant == SIM_V_FUSED_SPLIT)
-        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, st));
+        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
+                             st));
       else
         HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
@@ -432,7 +433,8 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
     HIP_TRY(launch_fused4(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr,
                           h->cfg.ckpt_every, nullptr, nullptr, st));
   } else if (v == SIM_V_FUSED_SPLIT && actor) {
-    HIP_TRY(launch_split(h->dc, h->b, actor, 1, 0, reward, done, nullptr, st));
+    HIP_TRY(launch_split(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr, 1, nullptr,
+                         nullptr, st));
   } else {
     // external actions run on the one-env-per-lane kernel (it has the
     // action-input path); both kernels share the state layout
@@ -465,10 +467,12 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
     h->timing_valid = true;
     return SIM_OK;
   }
-  // A taped rollout always runs on the quarter-lane fused kernel: the
-  // backward pass recomputes segments with that kernel, and the recompute
-  // must reproduce the forward trajectory bit for bit.
-  const int v = record_tape ? SIM_V_FUSED_MFMA4 : effective_variant(h);
+  // A taped rollout runs on the kernel the backward pass recomputes its
+  // segments with (the recompute must reproduce the forward trajectory bit
+  // for bit): the split-actor kernel for small fp32 batches, else the
+  // quarter-lane kernel.
+  const int v = record_tape ? (taped_on_split(h->dc) ? SIM_V_FUSED_SPLIT : SIM_V_FUSED_MFMA4)
+                            : effective_variant(h);
   const int spl = effective_spl(h);
   float* tape = record_tape ? h->tape : nullptr;
   h->tape_T = 0;

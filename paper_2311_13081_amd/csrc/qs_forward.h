@@ -79,9 +79,19 @@ hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int 
                          float* rewards, uint8_t* dones, float* states, float* tape,
                          int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
 // Split-actor fused kernel (qs_split.hip): 16 envs per workgroup of 4 waves,
-// wave w evaluating neuron tile w of layers 1 and 2; no tape or record mode.
+// wave w evaluating neuron tile w of layers 1 and 2; tape and record modes as
+// the quarter-lane kernel, whose results it reproduces bit for bit.
 hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
-                        float* rewards, uint8_t* dones, float* states, hipStream_t st);
+                        float* rewards, uint8_t* dones, float* states, float* tape,
+                        int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
+// The kernel of taped rollouts and of their backward recompute (the two must
+// agree bit for bit): the split-actor kernel below 16384 envs with the fp32
+// actor (the quarter-lane kernel leaves SIMDs idle there), else the
+// quarter-lane kernel.
+constexpr int TAPE_SPLIT_MAX_ENVS = 16384;
+inline bool taped_on_split(const DevCfg& c) {
+  return c.n_envs < TAPE_SPLIT_MAX_ENVS && !(c.flags & F_ACTOR_BF16);
+}
 // One-env-per-lane fused kernel (qs_fused.hip), actor on fp32 MFMA or VALU.
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,

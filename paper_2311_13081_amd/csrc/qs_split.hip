@@ -18,9 +18,13 @@
 namespace qs {
 
 // Layers 1 and 2 for tile w of the workgroup's 16 envs, exchange through
-// xz1/xz2 ([tile][lane]), layer 3 in every wave.
+// xz1/xz2 ([tile][lane]), layer 3 in every wave.  When rz1/rz2 are given,
+// writes this wave's tile of the layer pre-activations to the record (rows
+// 16 w + 4 lg + r; rec_lane_off addresses row 4 lg of this lane's env).
 __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz1, f4q* xz2,
-                                   float z3[NA]) {
+                                   float z3[NA], float* __restrict__ rz1,
+                                   float* __restrict__ rz2, bool rec_lane,
+                                   uint32_t rec_lane_off) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   const int w = threadIdx.x >> 6;
   f4q acc1;
@@ -37,6 +41,9 @@ __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz
             0, 0, 0);
     }
   }
+  if (rz1 && rec_lane)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rz1[(size_t)(16 * w + r) * RB + rec_lane_off] = acc1[r];
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc1[r] = relu_bits(acc1[r]);
   xz1[w * 64 + lane] = acc1;
@@ -54,6 +61,9 @@ __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz
       acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(wt[v], z1[n][v], (n == 0 && v == 0) ? b2 : acc2,
                                                   0, 0, 0);
   }
+  if (rz2 && rec_lane)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * w + r) * RB + rec_lane_off] = acc2[r];
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc2[r] = relu_bits(acc2[r]);
   xz2[w * 64 + lane] = acc2;
@@ -68,10 +78,16 @@ __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz
 // A barrier separates each layer's writes of the exchange buffers from the
 // reads, and the next step's writes of a buffer come after the barrier that
 // follows every wave's reads of it, so two barriers per step suffice.
+// As the quarter-lane kernel: with tape != NULL, checkpoints every
+// ckpt_every steps; with rec != NULL, record mode from checkpoint ck_in (no
+// write-back of the env state).  Wave 0 writes everything except the layer
+// pre-activations, which each wave writes for its own tile.
 template <bool EXTRAS>
 __global__ void __launch_bounds__(256)
 k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
-        float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states) {
+        float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states,
+        float* __restrict__ tape, int ckpt_every, const float* __restrict__ ck_in,
+        float* __restrict__ rec) {
   __shared__ __attribute__((aligned(16))) float lds[Q_TOTAL];
   __shared__ f4q xz1[4 * 64], xz2[4 * 64];
   const int N = c.n_envs;
@@ -84,6 +100,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
   const int env = env0 + j;
   const bool active = env < N;
   const int e = active ? env : env0;
+  const bool REC = rec != nullptr;
 
   float th[NP];
 #pragma unroll
@@ -93,15 +110,26 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
 
   float x[NS];
   float F[Q_C];  // F[0..4] observation state part (refreshed each step), F[5..36] history
+  int head0 = 0, t_ep = 0, ep = 0;
+  if (REC) {
 #pragma unroll
-  for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
-  const int head0 = b.head[e];
+    for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
 #pragma unroll
-  for (int s = 0; s < NH; ++s) {
-    const int slot = (head0 + s) & (NH - 1);
-    F[5 + s] = b.ring[(size_t)(slot * NA + k) * N + e];
+    for (int s = 0; s < NH; ++s) F[5 + s] = ck_in[(size_t)(NS + s * NA + k) * N + e];
+    t_ep = __float_as_int(ck_in[(size_t)CK_TEP * N + e]);
+    ep = __float_as_int(ck_in[(size_t)CK_EP * N + e]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
+    head0 = b.head[e];
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int slot = (head0 + s) & (NH - 1);
+      F[5 + s] = b.ring[(size_t)(slot * NA + k) * N + e];
+    }
+    t_ep = b.t_ep[e];
+    ep = b.ep[e];
   }
-  int t_ep = b.t_ep[e], ep = b.ep[e];
   bool was_reset = false;
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah = rpm_to_action(c, wh);
@@ -124,13 +152,48 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
   for (int t = 0; t < T; ++t) {
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
+    const bool rec_on = opaque(REC ? 1u : 0u) != 0u;
     const int gt = t_base + t;
+    if (tape && (gt % ckpt_every) == 0 && active && writer) {
+      float* ck = tape + (size_t)(gt / ckpt_every) * CK_F * N;
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if ((i & 3) == k) ck[(size_t)i * N + eo] = x[i];
+      const uint32_t kc = opaque((uint32_t)(k * N + e));
+#pragma unroll
+      for (int s = 0; s < NH; ++s) ck[(size_t)(NS + s * NA) * N + kc] = F[5 + s];
+      if (k == 0) {
+        ck[(size_t)CK_TEP * N + eo] = __int_as_float(t_ep);
+        ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
+      }
+    }
     quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F);
+    float* rt = rec_on ? rec + rec_step(t, N) : nullptr;
+    const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
     float z3[NA];
-    actor_split(lds, F, xz1, xz2, z3);
+    actor_split(lds, F, xz1, xz2, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
+                rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, active, zoff);
     float a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
+    if (rec_on && active && writer) {
+      const uint32_t koff = opaque((uint32_t)(rb_at(e, REC_F) + k * RB));
+      const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc)
+        if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + 4 * cc) * RB + koff] = F[cc];
+      float* act = rec + rec_act(T, N);
+      const uint32_t aoff = opaque((uint32_t)(rb_at(e, (NH + T) * NA) + k * RB));
+      if (t == 0) {
+#pragma unroll
+        for (int s = 0; s < NH; ++s) act[(size_t)(s * NA) * RB + aoff] = F[5 + s];
+      }
+      act[(size_t)((NH + t) * NA) * RB + aoff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if ((i & 3) == k) rt[(size_t)(REC_X + i) * RB + roff] = x[i];
+      rt[(size_t)REC_A * RB + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+    }
     float u[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
@@ -167,7 +230,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
           if ((i & 3) == k) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
     }
   }
-  if (!active || !writer) return;
+  if (!active || !writer || REC) return;
   const uint32_t ef = opaque((uint32_t)e);
 #pragma unroll
   for (int i = 0; i < NS; ++i)
@@ -188,11 +251,13 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
 }
 
 hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
-                        float* rewards, uint8_t* dones, float* states, hipStream_t st) {
+                        float* rewards, uint8_t* dones, float* states, float* tape,
+                        int ckpt_every, const float* ck_in, float* rec, hipStream_t st) {
   const unsigned grid = (unsigned)((c.n_envs + 15) / 16);
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
   auto k = ex ? k_split<true> : k_split<false>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states,
+                     tape, ckpt_every, ck_in, rec);
   return hipGetLastError();
 }
 

@@ -71,6 +71,8 @@ def _cfg(**kw):
     dict(nominal=[0.027, 3.85e-6, 3.85e-6, 5.9675e-6, 0, 0, 0.0, 0.15]),
     dict(rpm_max=-1.0), dict(max_tape_horizon=-3),
     dict(dr_enable=1, dr_lo=[0.8] * 7 + [-0.5]),
+    # a segment's backward record above 4 GiB (2M envs x 16 steps)
+    dict(n_envs=2_000_000, max_tape_horizon=64, ckpt_every=16),
 ])
 def test_invalid_config_rejected_before_device(L, bad):
     from paper_2311_13081_amd import _lib
