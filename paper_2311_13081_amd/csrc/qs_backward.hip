@@ -387,10 +387,15 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 // only (the dz rows, a third of the bytes, by all four, through L2).  Waves
 // g and g + 4 run column group g on alternate steps -- two waves per SIMD, so
 // one's loads overlap the other's matrix work -- and add their sums through
-// LDS at the end, half 0 first.  Operands come straight from the record, one
-// 16-env slab ahead: no staging and no barrier in the loop.  The history
-// features of o_t are the actions of the 32 previous steps, read from the
-// segment's action tape (one contiguous span per 64-env block).
+// LDS at the end, half 0 first.  The dz rows (A operands, the same for the
+// four groups of a half) are loaded once per step by the half's four waves
+// together, whole 256-byte rows per lane group, and staged in LDS; each wave
+// loads its own input columns (B operands) straight from the record, one
+// 16-env slab ahead.  The kernel is bound by the number of vector-memory
+// instructions (the address unit's queue fills), which the shared dz staging
+// halves.  The history features of o_t are the actions of the 32 previous
+// steps, read from the segment's action tape (one contiguous span per 64-env
+// block).
 constexpr int DW_MAXT = 17;  // output tiles of a column group
 
 __host__ __device__ constexpr int dw_tile(int G, int i) {
@@ -411,14 +416,23 @@ static_assert(dw_acc0(3, 8) == DW_MAXT && dw_acc0(0, 4) == 16 && dw_acc0(2, 4) =
                   dw_acc0(3, 3) == dw_acc0(3, 2) + dw_nacc(dw_tile(3, 2)),
               "column-group tile counts");
 
-// Operands of one 16-env slab for column group G: the dz1 and dz2 tiles of
-// the four neuron tiles, dz3 (group 3), and the B tiles of its loaded
-// columns (slot i of column tile i; the bias-only tiles use no slot).
+// B operands of one 16-env slab for column group G (slot i of column tile
+// i; the bias-only tiles use no slot), and the A operands: the dz1 and dz2
+// tiles of the four neuron tiles and dz3 (group 3).
 template <int G>
 struct DwOps {
-  f4 a1[4], a2[4], a3;
   f4 b[dw_ntile(G)];
 };
+struct DwA {
+  f4 a1[4], a2[4], a3;
+};
+
+// LDS staging of one step's dz rows for a half: DZ_F rows of 64 envs, pitch
+// DW_AP floats (the 4 extra floats put the 16 rows one ds_read_b128 touches
+// on distinct banks).  Wave g of the half loads rows DW_AW g .. DW_AW g +
+// DW_AW - 1, four rows per instruction.
+constexpr int DW_AP = RB + 4, DW_AW = (DZ_F + 3) / 4, DW_AL = (DW_AW + 3) / 4;
+constexpr int DW_ABUF = DZ_F * DW_AP;  // floats per half
 
 __device__ inline f4 const4(float v) { return f4{v, v, v, v}; }
 
@@ -468,21 +482,14 @@ __device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, in
   }
 }
 
-// Issues the loads of slab q of a step; dw_prepare finishes the operands when
-// they are used, so the loads stay in flight during the previous slab's
+// Issues the B loads of slab q of a step; dw_prepare finishes the operands
+// when they are used, so the loads stay in flight during the previous slab's
 // matrix work.  Every lane of a loaded tile loads (lanes of constant columns
 // from a valid address, replaced later), so no load sits under a branch.
 // loff: the lane's byte offset 4 (li * RB + 4 lg).
 template <int G>
-__device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec,
-                                    __amdgpu_buffer_rsrc_t rdz, const DwAddr<G>& d, uint32_t loff,
-                                    int q) {
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    o.a1[nt] = bld4(rdz, loff + 64 * q, d.dzs + 4 * (16 * nt * RB));
-    o.a2[nt] = bld4(rdz, loff + 64 * q, d.dzs + 4 * ((NHID + 16 * nt) * RB));
-  }
-  if (G == 3) o.a3 = bld4(rdz, loff + 64 * q, d.dzs + 4 * (2 * NHID * RB));
+__device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec, const DwAddr<G>& d,
+                                    uint32_t loff, int q) {
 #pragma unroll
   for (int i = 0; i < dw_ntile(G); ++i) {
     const int t = dw_tile(G, i);
@@ -496,9 +503,47 @@ __device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec,
   }
 }
 
+// This wave's share of step tl's dz rows (whole rows: lane l takes envs
+// 4 (l & 15) .. + 3 of row DW_AW g + 4 j + (l >> 4)); rows past the share
+// load a valid row and are not stored.
+__device__ inline void dw_a_load(f4 an[DW_AL], __amdgpu_buffer_rsrc_t rdz, int tl, int chunk,
+                                 int N, int g, int lane) {
+  const uint32_t rbp = (uint32_t)rb_pad(N);
+  const uint32_t so = 4u * ((uint32_t)tl * (DZ_F * rbp) + (uint32_t)chunk * (DZ_F * RB));
+#pragma unroll
+  for (int j = 0; j < DW_AL; ++j) {
+    int r = DW_AW * g + 4 * j + (lane >> 4);
+    r = r < DZ_F ? r : DZ_F - 1;
+    an[j] = bld4(rdz, 4u * (uint32_t)(r * RB + 4 * (lane & 15)), so);
+  }
+}
+__device__ inline void dw_a_store(const f4 an[DW_AL], float* sA, int g, int lane) {
+#pragma unroll
+  for (int j = 0; j < DW_AL; ++j) {
+    const int jr = 4 * j + (lane >> 4), r = DW_AW * g + jr;
+    if (jr < DW_AW && r < DZ_F) *reinterpret_cast<f4*>(&sA[r * DW_AP + 4 * (lane & 15)]) = an[j];
+  }
+}
+// A operands of slab q from the staged rows (dz3 rows only for the 4
+// outputs).
+template <int G>
+__device__ inline void dw_read_a(DwA& a, const float* sA, int q, int li, int lg) {
+  const int c = 16 * q + 4 * lg;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    a.a1[nt] = *reinterpret_cast<const f4*>(&sA[(16 * nt + li) * DW_AP + c]);
+    a.a2[nt] = *reinterpret_cast<const f4*>(&sA[(NHID + 16 * nt + li) * DW_AP + c]);
+  }
+  if (G == 3) {
+    a.a3 = *reinterpret_cast<const f4*>(&sA[(2 * NHID + (li & 3)) * DW_AP + c]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a.a3[m] = li < NA ? a.a3[m] : 0.0f;
+  }
+}
+
 // ReLU of the pre-activation columns, the constant columns (ones at the bias
-// column, zeros beyond), the forward's bf16 rounding of its inputs and dz3
-// rows only for the 4 outputs.  Envs >= N of the last block need nothing:
+// column, zeros beyond) and the forward's bf16 rounding of its inputs.  Envs
+// >= N of the last block need nothing:
 // their record and dz slots are zero (cleared at allocation, never written).
 template <int G, bool BF16>
 __device__ inline void dw_prepare(DwOps<G>& o, int li) {
@@ -517,14 +562,11 @@ __device__ inline void dw_prepare(DwOps<G>& o, int li) {
       o.b[i][m] = col0 + 15 < n_in ? v : col < n_in ? v : col == n_in ? 1.0f : 0.0f;
     }
   }
-  if (G == 3)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) o.a3[m] = li < NA ? o.a3[m] : 0.0f;
 }
 
 // bias1: B of a bias-only tile (column 64 = lane li 0).
 template <int G>
-__device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, float bias1) {
+__device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, const DwA& A, float bias1) {
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -534,61 +576,86 @@ __device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, float bias1) {
       if (t < 15) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
-          acc[a0 + nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(t < 10 ? o.a1[nt][m] : o.a2[nt][m],
+          acc[a0 + nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(t < 10 ? A.a1[nt][m] : A.a2[nt][m],
                                                               bv, acc[a0 + nt], 0, 0, 0);
       } else {
-        acc[a0] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a3[m], bv, acc[a0], 0, 0, 0);
+        acc[a0] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a3[m], bv, acc[a0], 0, 0, 0);
       }
     }
 }
 
 // This half's steps t_lo + half, t_lo + half + 2, ... of the group, the four
-// 16-env slabs of a step in turn, each slab's loads issued one slab ahead
+// 16-env slabs of a step in turn, each slab's B loads issued one slab ahead
 // into the other of two operand buffers (a copy between them would wait for
-// the loads in flight).  After the last step the look-ahead load repeats
-// that step's slab 0 rather than branch.
+// the loads in flight), the next step's dz share loaded during this step and
+// staged after it.  Both halves run the same number of iterations (every
+// wave meets every barrier); a half without a step left reads a valid step
+// and skips the products.  sA: this half's staging buffer.
 template <int G, bool BF16>
 __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
                                      const float* __restrict__ dz, int N, int chunk, int t_lo,
-                                     int t_hi, int n, int half) {
+                                     int t_hi, int n, int half, float* sA) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int t_first = t_lo + half;
-  if (t_first >= t_hi) return;
+  const int iters = (t_hi - t_lo + 1) / 2;  // half 0's steps, the same in every wave
+  if (iters <= 0) return;
   const uint32_t rbp = (uint32_t)rb_pad(N);
   const __amdgpu_buffer_rsrc_t rrec =
       buf_rsrc(rec, 4u * ((uint32_t)n * REC_F * rbp + (uint32_t)(NH + n) * NA * rbp));
   const __amdgpu_buffer_rsrc_t rdz = buf_rsrc(dz, 4u * ((uint32_t)n * DZ_F * rbp));
   const uint32_t loff = 4u * (uint32_t)(li * RB + 4 * lg);
   const float bias1 = li == 0 ? 1.0f : 0.0f;
+  auto step = [&](int i) {
+    const int t = t_lo + half + 2 * i;
+    return t < t_hi ? t : t_hi - 1;
+  };
+  f4 an[DW_AL];
+  dw_a_load(an, rdz, step(0), chunk, N, G, lane);
+  dw_a_store(an, sA, G, lane);
+  __syncthreads();
   DwOps<G> ob0, ob1;
+  DwA A;
   DwAddr<G> d;
-  dw_addr<G>(d, t_first, n, chunk, N, li, lg);
-  dw_load_slab<G>(ob0, rrec, rdz, d, loff, 0);
+  dw_addr<G>(d, step(0), n, chunk, N, li, lg);
+  dw_load_slab<G>(ob0, rrec, d, loff, 0);
   // scheduling barriers keep each slab's loads ahead of the previous slab's
   // matrix work (left alone, the scheduler interleaves a slab's products
   // with its own loads and the waits then cover the loads just issued)
-  for (int tl = t_first; tl < t_hi; tl += 2) {
-    dw_load_slab<G>(ob1, rrec, rdz, d, loff, 1);
+  for (int i = 0; i < iters; ++i) {
+    const bool live = t_lo + half + 2 * i < t_hi;
+    const bool more = i + 1 < iters;
+    // unconditional (the last iteration reloads its own step): a load under
+    // a branch would leave the waits below counting it conservatively
+    dw_a_load(an, rdz, step(more ? i + 1 : i), chunk, N, G, lane);
+    dw_load_slab<G>(ob1, rrec, d, loff, 1);
     __builtin_amdgcn_sched_barrier(0);
+    dw_read_a<G>(A, sA, 0, li, lg);
     dw_prepare<G, BF16>(ob0, li);
-    dw_mfma<G>(acc, ob0, bias1);
+    if (live) dw_mfma<G>(acc, ob0, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
-    dw_load_slab<G>(ob0, rrec, rdz, d, loff, 2);
+    dw_load_slab<G>(ob0, rrec, d, loff, 2);
     __builtin_amdgcn_sched_barrier(0);
+    dw_read_a<G>(A, sA, 1, li, lg);
     dw_prepare<G, BF16>(ob1, li);
-    dw_mfma<G>(acc, ob1, bias1);
+    if (live) dw_mfma<G>(acc, ob1, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
-    dw_load_slab<G>(ob1, rrec, rdz, d, loff, 3);
+    dw_load_slab<G>(ob1, rrec, d, loff, 3);
     __builtin_amdgcn_sched_barrier(0);
+    dw_read_a<G>(A, sA, 2, li, lg);
     dw_prepare<G, BF16>(ob0, li);
-    dw_mfma<G>(acc, ob0, bias1);
+    if (live) dw_mfma<G>(acc, ob0, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
-    dw_addr<G>(d, tl + 2 < t_hi ? tl + 2 : tl, n, chunk, N, li, lg);
-    dw_load_slab<G>(ob0, rrec, rdz, d, loff, 0);
+    dw_addr<G>(d, step(more ? i + 1 : i), n, chunk, N, li, lg);
+    dw_load_slab<G>(ob0, rrec, d, loff, 0);
     __builtin_amdgcn_sched_barrier(0);
+    dw_read_a<G>(A, sA, 3, li, lg);
     dw_prepare<G, BF16>(ob1, li);
-    dw_mfma<G>(acc, ob1, bias1);
+    if (live) dw_mfma<G>(acc, ob1, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      __syncthreads();  // every wave is done with this step's staged rows
+      dw_a_store(an, sA, G, lane);
+      __syncthreads();
+    }
   }
 }
 
@@ -647,7 +714,10 @@ template <bool BF16>
 __global__ void __launch_bounds__(512)
 k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n, int S,
          float* __restrict__ gpart) {
-  __shared__ f4 xacc[4][DW_MAXT][64];
+  // dz staging of the two halves during the loop, then the exchange of sums
+  __shared__ __attribute__((aligned(16))) float smem[2 * DW_ABUF];
+  static_assert(2 * DW_ABUF * 4 >= 4 * DW_MAXT * 64 * 16, "exchange fits the staging space");
+  f4(*xacc)[DW_MAXT][64] = reinterpret_cast<f4(*)[DW_MAXT][64]>(smem);
   const int chunk = blockIdx.x, sg = blockIdx.y;
   // the wave index is uniform across the wave: keep it (and every offset
   // derived from it) in scalar registers
@@ -658,12 +728,14 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
   f4 acc[DW_MAXT];
 #pragma unroll
   for (int i = 0; i < DW_MAXT; ++i) acc[i] = const4(0.0f);
+  float* sA = smem + half * DW_ABUF;
   switch (g) {
-    case 0: dw_accumulate<0, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
-    case 1: dw_accumulate<1, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
-    case 2: dw_accumulate<2, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
-    default: dw_accumulate<3, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half); break;
+    case 0: dw_accumulate<0, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
+    case 1: dw_accumulate<1, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
+    case 2: dw_accumulate<2, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
+    default: dw_accumulate<3, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
   }
+  __syncthreads();  // the staging space becomes the exchange buffer
   // half 1 hands its sums to half 0 (fixed order: half 0 + half 1)
   if (half == 1)
 #pragma unroll
