@@ -591,6 +591,14 @@ __device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, const DwA& A, float b
 // staged after it.  Both halves run the same number of iterations (every
 // wave meets every barrier); a half without a step left reads a valid step
 // and skips the products.  sA: this half's staging buffer.
+// Barrier discipline: the four column groups run separate instantiations of
+// this loop, so their waves reach the workgroup barriers at different
+// program locations; the hardware barrier counts arriving waves, and every
+// wave executes the same sequence of barriers (one before the loop, two per
+// iteration but the last, iters uniform over the workgroup), so they pair up.
+// A loop in the kernel body with the group switched per step would keep the
+// barriers in uniform code, but it keeps every group's operand slots live
+// across the switch and spills.
 template <int G, bool BF16>
 __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
                                      const float* __restrict__ dz, int N, int chunk, int t_lo,
