@@ -89,19 +89,22 @@ __device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bo
 }
 
 // Inputs of one reverse step: the recorded state and action, this lane's
-// 16 layer-1 and layer-2 pre-activations (rows 16 q + 4 k + r), the reward
-// and state cotangents.
+// layer-1 and layer-2 pre-activations (ZT tiles: all four, rows 16 q + 4 k
+// + r at index 4 q + r, or, for the split sweep, tile w only, at index r),
+// the reward and state cotangents.
+template <int ZT>
 struct StepIn {
-  float x[NS], a[NA], z1[16], z2[16], dS[NS], dR;
+  float x[NS], a[NA], z1[4 * ZT], z2[4 * ZT], dS[NS], dR;
 };
 
-__device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __restrict__ rec,
+template <int ZT>
+__device__ inline void load_step(StepIn<ZT>& in, const DevCfg& c, const float* __restrict__ rec,
                                  const float* __restrict__ d_rewards,
                                  const float* __restrict__ d_states, int tl, int t0, int N, int e,
-                                 int k) {
+                                 int k, int w) {
   const uint32_t eo = opaque((uint32_t)e);
   const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
-  const uint32_t zoff = opaque((uint32_t)(rb_at(e, REC_F) + 4 * k * RB));
+  const uint32_t zoff = opaque((uint32_t)(rb_at(e, REC_F) + 4 * k * RB + (ZT == 1 ? 16 * w * RB : 0)));
   const int t = t0 + tl;
   const float* rt = rec + rec_step(tl, N);
 #pragma unroll
@@ -109,7 +112,7 @@ __device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __res
 #pragma unroll
   for (int i = 0; i < NA; ++i) in.a[i] = rt[(size_t)(REC_A + i) * RB + roff];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < ZT; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       in.z1[4 * q + r] = rt[(size_t)(REC_Z1 + 16 * q + r) * RB + zoff];
@@ -121,6 +124,164 @@ __device__ inline void load_step(StepIn& in, const DevCfg& c, const float* __res
     in.dS[i] = d_states ? d_states[((size_t)t * NS + i) * N + eo] : 0.0f;
 }
 
+// Reverse of one step's dynamics: recomputes the RK4 stages from the recorded
+// state x and action a, then steps back through the reward, the quaternion
+// renormalisation and the four stages.  In: ls (state adjoint after the
+// step), lh_new (adjoint of the newest history slot, this lane's component).
+// Out: gx (state adjoint before the step, without the observation's share),
+// ga (action adjoint, the history coupling included); gth accumulates the
+// parameter gradients.
+__device__ __forceinline__ void reverse_dynamics(const DevCfg& c, const Body<float>& B,
+                                                 const float th[NP], bool renorm, const float x[NS],
+                                                 const float a[NA], float dR, const float ls[NS],
+                                                 float lh_new, int j, float gx[NS], float ga[NA],
+                                                 float gth[NP]) {
+  const float h = c.dt;
+  float u[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
+  float x2[NS], x3[NS], x4[NS], kd[NS], acc[NS];
+  deriv<float>(B, c.arm, c.km, c.g, x, u, kd);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] = kd[i];
+    x2[i] = x[i] + 0.5f * h * kd[i];
+  }
+  deriv<float>(B, c.arm, c.km, c.g, x2, u, kd);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] += 2.0f * kd[i];
+    x3[i] = x[i] + 0.5f * h * kd[i];
+  }
+  deriv<float>(B, c.arm, c.km, c.g, x3, u, kd);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    acc[i] += 2.0f * kd[i];
+    x4[i] = x[i] + h * kd[i];
+  }
+  deriv<float>(B, c.arm, c.km, c.g, x4, u, kd);
+  float sn[NS];  // post-step state (renormalised)
+#pragma unroll
+  for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + kd[i]);
+  float rn = 1.0f;
+  if (renorm) {
+    // the forward's reciprocal square root (rk4_step)
+    rn = rsqrt_r(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sn[3 + i] *= rn;
+  }
+
+  // --- reward and history coupling -----------------------------------------
+  float g[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) g[i] = ls[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[i] += -2.0f * c.C_rp * sn[i] * dR;
+    g[7 + i] += -2.0f * c.C_rv * sn[7 + i] * dR;
+    g[10 + i] += -2.0f * c.C_rw * sn[10 + i] * dR;
+  }
+  g[3] += 2.0f * c.C_rq * sn[3] * dR;
+  // newest history slot: component i lives in quarter i of the same env
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const float hn =
+        __int_as_float(__builtin_amdgcn_ds_bpermute((j + 16 * i) << 2, __float_as_int(lh_new)));
+    ga[i] = -2.0f * c.C_ra * (a[i] - c.C_rab) * dR + hn;
+  }
+
+  // --- renormalisation ------------------------------------------------------
+  if (renorm) {
+    const float d = sn[3] * g[3] + sn[4] * g[4] + sn[5] * g[5] + sn[6] * g[6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[3 + i] = (g[3 + i] - sn[3 + i] * d) * rn;
+  }
+
+  // --- RK4 stages in reverse ----------------------------------------------
+  float gk[NS], gs[NS], gu[NA] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    gx[i] = g[i];
+    gk[i] = (h / 6.0f) * g[i];
+    gs[i] = 0.0f;
+  }
+  deriv_vjp(B, th, c.arm, c.km, x4, u, gk, gs, gu, gth);  // k4 = f(x4)
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    gx[i] += gs[i];
+    gk[i] = (h / 3.0f) * g[i] + h * gs[i];
+    gs[i] = 0.0f;
+  }
+  deriv_vjp(B, th, c.arm, c.km, x3, u, gk, gs, gu, gth);  // k3 = f(x3)
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    gx[i] += gs[i];
+    gk[i] = (h / 3.0f) * g[i] + 0.5f * h * gs[i];
+    gs[i] = 0.0f;
+  }
+  deriv_vjp(B, th, c.arm, c.km, x2, u, gk, gs, gu, gth);  // k2 = f(x2)
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    gx[i] += gs[i];
+    gk[i] = (h / 6.0f) * g[i] + 0.5f * h * gs[i];
+  }
+  deriv_vjp(B, th, c.arm, c.km, x, u, gk, gx, gu, gth);   // k1 = f(x)
+#pragma unroll
+  for (int i = 0; i < NA; ++i) ga[i] += gu[i] * c.rpm_half_range;
+}
+
+// The observation's share of the adjoints, from do (dob: tile p, register r
+// of quarter k = the cotangent of feature PHI(4p + r, k)): shifts the
+// history adjoint (H_t[s] feeds H_{t+1}[s-1]), gathers the 18 state features
+// from the quarters, adds them (through R(q)) to gx and forms the state
+// adjoint before the step, ls = gx + dS.
+__device__ __forceinline__ void reverse_observation(const float dob[40], const float x[NS],
+                                                    const float dS[NS], int j, float gx[NS],
+                                                    float lH[NH], float ls[NS]) {
+  // descending s reads the older adjoint before it is overwritten
+#pragma unroll
+  for (int s = NH - 1; s >= 0; --s) lH[s] = (s >= 1 ? lH[s - 1] : 0.0f) + dob[5 + s];
+  // state features 4cc + q live in quarter q: gather them into every lane
+  float gf[20];
+#pragma unroll
+  for (int cc = 0; cc < 5; ++cc)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      gf[4 * cc + q] = __int_as_float(
+          __builtin_amdgcn_ds_bpermute((j + 16 * q) << 2, __float_as_int(dob[cc])));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gx[i] += gf[i];
+    gx[7 + i] += gf[12 + i];
+    gx[10 + i] += gf[15 + i];
+  }
+  {
+    float gq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float q[4] = {x[3], x[4], x[5], x[6]};
+    rotmat_vjp(q, gf + 3, gq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gx[3 + i] += gq[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) ls[i] = gx[i] + dS[i];
+}
+
+// Exchange space of the split sweep, after the staged weights: dz2 and dz1
+// tiles [4][64] and do tiles [10][64] (f4 each).
+constexpr int R_XCH = (4 + 4 + 10) * 64 * 4;
+// Batches up to this size run the split sweep (four times the waves; the
+// quarter-lane sweep leaves most SIMDs idle there).
+constexpr int REVERSE_SPLIT_MAX_ENVS = 4096;
+
+// Reverse sweep of one segment.  SPLIT = false: 16 envs per wave in the
+// quarter-lane layout.  SPLIT = true: 16 envs per workgroup of 4 waves, each
+// in that layout; wave w evaluates neuron tile w of dz2 and dz1 and the do
+// tiles w, w + 4, w + 8 on MFMA, the tiles go through LDS (three barriers a
+// step, each exchange buffer rewritten only after the barrier that follows
+// every wave's reads of it), and every wave runs the dynamics and the
+// observation adjoints.  The MFMA chains of each tile are the same in both,
+// so they agree bit for bit.
+template <bool SPLIT>
 __global__ void __launch_bounds__(256)
 k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict__ W,
               const float* __restrict__ ck, const float* __restrict__ rec, int n, int t0,
@@ -132,11 +293,15 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   __syncthreads();
   const int N = c.n_envs;
   const int lane = threadIdx.x & 63, j = lane & 15, k = lane >> 4;
-  const int env0 = (blockIdx.x * blockDim.x + threadIdx.x - lane) / 4;
-  if (env0 >= N) return;
+  const int w = SPLIT ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  const int env0 = SPLIT ? blockIdx.x * 16 : (blockIdx.x * blockDim.x + threadIdx.x - lane) / 4;
+  if (env0 >= N) return;  // SPLIT: the whole workgroup
   const int env = env0 + j;
   const bool active = env < N;
   const int e = active ? env : env0;
+  f4* xd2 = reinterpret_cast<f4*>(lds + R_TOTAL);
+  f4* xd1 = xd2 + 4 * 64;
+  f4* xdo = xd1 + 4 * 64;
 
   float th[NP];
 #pragma unroll
@@ -149,7 +314,6 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     set_disturbance(B, d);
   }
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
-  const float h = c.dt;
 
   float ls[NS], lH[NH], gth[NP];
 #pragma unroll
@@ -161,202 +325,141 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 
   // The per-step inputs (record rows and cotangents) of step tl - 1 are
   // loaded while step tl is processed, so their latency hides behind it.
-  StepIn cur, nxt;
-  load_step(cur, c, rec, d_rewards, d_states, n - 1, t0, N, e, k);
+  constexpr int ZT = SPLIT ? 1 : 4;
+  StepIn<ZT> cur, nxt;
+  load_step<ZT>(cur, c, rec, d_rewards, d_states, n - 1, t0, N, e, k, w);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
-    load_step(nxt, c, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k);
+    load_step<ZT>(nxt, c, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k, w);
     // blocked cotangent rows of this env: row k and row 4k
     const uint32_t koff = opaque((uint32_t)(rb_at(e, DZ_F) + k * RB));
     const uint32_t zoff = opaque((uint32_t)(rb_at(e, DZ_F) + 4 * k * RB));
     float* dzt = dz + (size_t)tl * DZ_F * rb_pad(N);
-    float x[NS], a[NA], u[NA];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) x[i] = cur.x[i];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      a[i] = cur.a[i];
-      u[i] = action_to_rpm(c, a[i]);
-    }
-    const float dR = cur.dR;
 
-    // --- forward recompute of the RK4 stages -------------------------------
-    float x2[NS], x3[NS], x4[NS], kd[NS], acc[NS];
-    deriv<float>(B, c.arm, c.km, c.g, x, u, kd);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      acc[i] = kd[i];
-      x2[i] = x[i] + 0.5f * h * kd[i];
-    }
-    deriv<float>(B, c.arm, c.km, c.g, x2, u, kd);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      acc[i] += 2.0f * kd[i];
-      x3[i] = x[i] + 0.5f * h * kd[i];
-    }
-    deriv<float>(B, c.arm, c.km, c.g, x3, u, kd);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      acc[i] += 2.0f * kd[i];
-      x4[i] = x[i] + h * kd[i];
-    }
-    deriv<float>(B, c.arm, c.km, c.g, x4, u, kd);
-    float sn[NS];  // post-step state (renormalised)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + kd[i]);
-    float rn = 1.0f;
-    if (renorm) {
-      // the forward's reciprocal square root (rk4_step)
-      rn = rsqrt_r(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sn[3 + i] *= rn;
-    }
-
-    // --- reward and history coupling -----------------------------------------
-    float g[NS], ga[NA];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) g[i] = ls[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      g[i] += -2.0f * c.C_rp * sn[i] * dR;
-      g[7 + i] += -2.0f * c.C_rv * sn[7 + i] * dR;
-      g[10 + i] += -2.0f * c.C_rw * sn[10 + i] * dR;
-    }
-    g[3] += 2.0f * c.C_rq * sn[3] * dR;
-    // newest history slot: component i lives in quarter i of the same env
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const float hn = __int_as_float(
-          __builtin_amdgcn_ds_bpermute((j + 16 * i) << 2, __float_as_int(lH[NH - 1])));
-      ga[i] = -2.0f * c.C_ra * (a[i] - c.C_rab) * dR + hn;
-    }
-
-    // --- renormalisation ------------------------------------------------------
-    if (renorm) {
-      const float d = sn[3] * g[3] + sn[4] * g[4] + sn[5] * g[5] + sn[6] * g[6];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) g[3 + i] = (g[3 + i] - sn[3 + i] * d) * rn;
-    }
-
-    // --- RK4 stages in reverse ----------------------------------------------
-    float gx[NS], gk[NS], gs[NS], gu[NA] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      gx[i] = g[i];
-      gk[i] = (h / 6.0f) * g[i];
-      gs[i] = 0.0f;
-    }
-    deriv_vjp(B, th, c.arm, c.km, x4, u, gk, gs, gu, gth);  // k4 = f(x4)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      gx[i] += gs[i];
-      gk[i] = (h / 3.0f) * g[i] + h * gs[i];
-      gs[i] = 0.0f;
-    }
-    deriv_vjp(B, th, c.arm, c.km, x3, u, gk, gs, gu, gth);  // k3 = f(x3)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      gx[i] += gs[i];
-      gk[i] = (h / 3.0f) * g[i] + 0.5f * h * gs[i];
-      gs[i] = 0.0f;
-    }
-    deriv_vjp(B, th, c.arm, c.km, x2, u, gk, gs, gu, gth);  // k2 = f(x2)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      gx[i] += gs[i];
-      gk[i] = (h / 6.0f) * g[i] + 0.5f * h * gs[i];
-    }
-    deriv_vjp(B, th, c.arm, c.km, x, u, gk, gx, gu, gth);   // k1 = f(x)
-#pragma unroll
-    for (int i = 0; i < NA; ++i) ga[i] += gu[i] * c.rpm_half_range;
+    float gx[NS], ga[NA];
+    reverse_dynamics(c, B, th, renorm, cur.x, cur.a, cur.dR, ls, lH[NH - 1], j, gx, ga, gth);
 
     // --- actor VJP on matrix cores --------------------------------------------
     float d3[NA];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) d3[i] = ga[i] * (1.0f - a[i] * a[i]);
+    for (int i = 0; i < NA; ++i) d3[i] = ga[i] * (1.0f - cur.a[i] * cur.a[i]);
     const float d3k = k == 0 ? d3[0] : k == 1 ? d3[1] : k == 2 ? d3[2] : d3[3];
-    if (active) dzt[(size_t)(2 * NHID) * RB + koff] = d3k;
-    // dz2 = (W3^T dz3) * [z2 > 0]: tile q rows 16q + 4k + r, env j
-    f4 dz2[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      dz2[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lds[R_W3 + k * NHID + 16 * q + j], d3k,
-                                                    f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float z2 = cur.z2[4 * q + r];
-        dz2[q][r] = z2 > 0.0f ? dz2[q][r] : 0.0f;
-        if (active) dzt[(size_t)(NHID + 16 * q + r) * RB + zoff] = dz2[q][r];
-      }
-    }
-    // dz1 = (W2^T dz2) * [z1 > 0]
-    f4 dz1[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      f4 accm = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const f4 w = *reinterpret_cast<const f4*>(
-            &lds[R_W2P + (((q * 4 + k) * 4 + mt) * 16 + j) * 4]);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          accm = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz2[q][v], accm, 0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float z1 = cur.z1[4 * mt + r];
-        dz1[mt][r] = z1 > 0.0f ? accm[r] : 0.0f;
-        if (active) dzt[(size_t)(16 * mt + r) * RB + zoff] = dz1[mt][r];
-      }
-    }
+    if (active && w == 0) dzt[(size_t)(2 * NHID) * RB + koff] = d3k;
     // do = W1^T dz1 in observation order: tile p, register r of quarter k is
     // the cotangent of feature PHI(4p + r, k)
     float dob[40];
+    if (!SPLIT) {
+      // dz2 = (W3^T dz3) * [z2 > 0]: tile q rows 16q + 4k + r, env j
+      f4 dz2[4];
 #pragma unroll
-    for (int p = 0; p < 10; ++p) {
-      f4 accp = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int q = 0; q < 4; ++q) {
+        dz2[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lds[R_W3 + k * NHID + 16 * q + j], d3k,
+                                                      f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float z2 = cur.z2[(4 * q + r) % (4 * ZT)];
+          dz2[q][r] = z2 > 0.0f ? dz2[q][r] : 0.0f;
+          if (active) dzt[(size_t)(NHID + 16 * q + r) * RB + zoff] = dz2[q][r];
+        }
+      }
+      // dz1 = (W2^T dz2) * [z1 > 0]
+      f4 dz1[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
-        const f4 w = *reinterpret_cast<const f4*>(
-            &lds[R_W1P + (((mt * 4 + k) * 10 + p) * 16 + j) * 4]);
+        f4 accm = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          accp = __builtin_amdgcn_mfma_f32_16x16x4f32(w[v], dz1[mt][v], accp, 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+          const f4 wv = *reinterpret_cast<const f4*>(
+              &lds[R_W2P + (((q * 4 + k) * 4 + mt) * 16 + j) * 4]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            accm = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], dz2[q][v], accm, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float z1 = cur.z1[(4 * mt + r) % (4 * ZT)];
+          dz1[mt][r] = z1 > 0.0f ? accm[r] : 0.0f;
+          if (active) dzt[(size_t)(16 * mt + r) * RB + zoff] = dz1[mt][r];
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dob[4 * p + r] = accp[r];
+      for (int p = 0; p < 10; ++p) {
+        f4 accp = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const f4 wv = *reinterpret_cast<const f4*>(
+              &lds[R_W1P + (((mt * 4 + k) * 10 + p) * 16 + j) * 4]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            accp = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], dz1[mt][v], accp, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dob[4 * p + r] = accp[r];
+      }
+    } else {
+      // dz2 tile w
+      f4 d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(lds[R_W3 + k * NHID + 16 * w + j], d3k,
+                                                   f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        d2[r] = cur.z2[r] > 0.0f ? d2[r] : 0.0f;
+        if (active) dzt[(size_t)(NHID + 16 * w + r) * RB + zoff] = d2[r];
+      }
+      xd2[w * 64 + lane] = d2;
+      __syncthreads();
+      f4 dz2[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dz2[q] = xd2[q * 64 + lane];
+      // dz1 tile w
+      f4 accm = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4 wv =
+            *reinterpret_cast<const f4*>(&lds[R_W2P + (((q * 4 + k) * 4 + w) * 16 + j) * 4]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          accm = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], dz2[q][v], accm, 0, 0, 0);
+      }
+      f4 d1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        d1[r] = cur.z1[r] > 0.0f ? accm[r] : 0.0f;
+        if (active) dzt[(size_t)(16 * w + r) * RB + zoff] = d1[r];
+      }
+      xd1[w * 64 + lane] = d1;
+      __syncthreads();
+      f4 dz1[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) dz1[mt] = xd1[mt * 64 + lane];
+      // do tiles w, w + 4, w + 8
+#pragma unroll
+      for (int pi = 0; pi < 3; ++pi) {
+        const int p = w + 4 * pi;
+        if (p < 10) {
+          f4 accp = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            const f4 wv = *reinterpret_cast<const f4*>(
+                &lds[R_W1P + (((mt * 4 + k) * 10 + p) * 16 + j) * 4]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              accp = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], dz1[mt][v], accp, 0, 0, 0);
+          }
+          xdo[p * 64 + lane] = accp;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 10; ++p) {
+        const f4 v = xdo[p * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dob[4 * p + r] = v[r];
+      }
     }
-    // history adjoint: H_t[s] feeds H_{t+1}[s-1]; descending s reads the
-    // older adjoint before it is overwritten
-#pragma unroll
-    for (int s = NH - 1; s >= 0; --s) lH[s] = (s >= 1 ? lH[s - 1] : 0.0f) + dob[5 + s];
-    // state features 4cc + q live in quarter q: gather them into every lane
-    float gf[20];
-#pragma unroll
-    for (int cc = 0; cc < 5; ++cc)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        gf[4 * cc + q] = __int_as_float(
-            __builtin_amdgcn_ds_bpermute((j + 16 * q) << 2, __float_as_int(dob[cc])));
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      gx[i] += gf[i];
-      gx[7 + i] += gf[12 + i];
-      gx[10 + i] += gf[15 + i];
-    }
-    {
-      float gq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      const float q[4] = {x[3], x[4], x[5], x[6]};
-      rotmat_vjp(q, gf + 3, gq);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) gx[3 + i] += gq[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NS; ++i)
-      ls[i] = gx[i] + cur.dS[i];
+    reverse_observation(dob, cur.x, cur.dS, j, gx, lH, ls);
     cur = nxt;
   }
-  if (!active) return;
+  if (!active || w != 0) return;
   const uint32_t ef = opaque((uint32_t)e);
   const uint32_t kf = opaque((uint32_t)(k * N + e));
 #pragma unroll
@@ -845,8 +948,12 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   if ((e = hipMalloc(&bw.gth, (size_t)NP * N * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gpart, (size_t)bw.n_parts * DW_SLOT * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&bw.gsum, (size_t)NW * 4)) != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_bwd_reverse,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4);
+  if ((e = hipFuncSetAttribute((const void*)k_bwd_reverse<false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4)) !=
+      hipSuccess)
+    return e;
+  return hipFuncSetAttribute((const void*)k_bwd_reverse<true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (R_TOTAL + R_XCH) * 4);
 }
 
 void bwd_free(BwdBufs& bw) {
@@ -913,9 +1020,14 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
       BWD_TRY(hipEventRecord(bw.e_rec[buf], s_rec));
       BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
     }
-    hipLaunchKernelGGL(k_bwd_reverse, dim3(nb(N, 64)), dim3(256), R_TOTAL * 4, st, c, b.theta, W,
-                       tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0, d_rewards, d_states,
-                       bw.lam, bw.gth, bw.dz[buf]);
+    if (N <= REVERSE_SPLIT_MAX_ENVS)
+      hipLaunchKernelGGL(k_bwd_reverse<true>, dim3(nb(N, 16)), dim3(256), (R_TOTAL + R_XCH) * 4,
+                         st, c, b.theta, W, tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0,
+                         d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf]);
+    else
+      hipLaunchKernelGGL(k_bwd_reverse<false>, dim3(nb(N, 64)), dim3(256), R_TOTAL * 4, st, c,
+                         b.theta, W, tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0, d_rewards,
+                         d_states, bw.lam, bw.gth, bw.dz[buf]);
     BWD_TRY(hipGetLastError());
     if (overlap) {
       BWD_TRY(hipEventRecord(bw.e_rev[buf], st));

@@ -165,6 +165,23 @@ def test_backward_is_deterministic(pkg, oracle_lib):
     sim.close()
 
 
+def test_split_kernels_match_quarter_lane_bitwise(pkg, oracle_lib):
+    """Up to 4096 envs the reverse sweep runs on the split kernel (four waves
+    per 16 envs), below 16384 the taped forward and its recompute too; above,
+    the quarter-lane kernels.  The per-env parameter gradients depend on the
+    env alone (states and parameters are keyed by env id), and both kernel
+    sets evaluate the same MFMA chains, so the first 4096 envs of a
+    16384-env handle give the 4096-env handle's gradients bit for bit."""
+    T, K = 24, 8
+    gps = []
+    for n in (4096, 16384):
+        cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
+        ga, gp = gpu_grad(sim, wl.xavier_actor(0), T)
+        gps.append(gp[:4096])
+        sim.close()
+    assert np.array_equal(gps[0], gps[1])
+
+
 def test_autograd_function(pkg, oracle_lib):
     """RolloutFn: loss = sum of rewards + a state term; torch autograd gives
     the same gradients as the direct C-ABI backward."""
