@@ -177,7 +177,9 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
  * states dev [T+1][17][N] with states[0] the start state.
  * record_tape != 0 stores checkpoints for sim_backward; it requires
  * T <= max_tape_horizon and flags without TERMINATE and AUTORESET, else
- * SIM_E_STATE / SIM_E_INVAL. */
+ * SIM_E_STATE / SIM_E_INVAL.  A taped rollout runs on the kernel its
+ * backward recomputes with (split-actor below 16384 envs with the fp32
+ * actor, else quarter-lane), whatever variant is set or tuned. */
 int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
                 float* states, int32_t record_tape, void* stream);
 

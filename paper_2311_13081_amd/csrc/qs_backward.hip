@@ -43,8 +43,9 @@ __global__ void k_bwd_init(int N, const float* __restrict__ dS_T, float* __restr
   for (int i = 0; i < NP; ++i) gth[(size_t)i * N + e] = 0.0f;
 }
 
-// Quarter-lane reverse sweep (16 envs per wave, lane L = j + 16 k: env j,
-// quarter k), the adjoint of the quarter-lane forward kernel.  Per lane:
+// Reverse sweep in the quarter-lane layout (16 envs per wave, lane L = j +
+// 16 k: env j, quarter k), the adjoint of the forward step (the quarter-lane
+// or the split-actor kernel, which compute the same values).  Per lane:
 // the state adjoint (17) and the dynamics VJP, replicated over the 4 quarters
 // of an env; the history adjoint of action component k (32 slots).  The actor
 // VJP runs on 16x16x4 fp32 MFMAs:
