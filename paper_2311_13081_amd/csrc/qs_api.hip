@@ -77,6 +77,7 @@ struct sim_handle {
   float* tape = nullptr;     // [max_tape_horizon/K + 1][145][N]
   int tape_ckpts = 0;
   int tape_T = 0;            // horizon of the recorded tape (0 = none)
+  bool last_seg_recorded = false;  // bw.seg[0] holds the tape's last segment's record
   BwdBufs bw{};
   int variant = SIM_V_AUTO, spl = 0, use_graph = 1;
   int tuned_variant = SIM_V_FUSED_MFMA, tuned_spl = 0;
@@ -247,6 +248,9 @@ void drop_graph(sim_handle* h) {
 }
 
 // Queues the launches of a T-step rollout on st.
+// With tape != NULL the launches also write the backward's record of the
+// tape's last segment (steps from (J - 1) K on, J = ceil(T / K)) into the
+// first segment buffer, so the backward need not recompute that segment.
 int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, float* rew,
                     uint8_t* done, float* states, float* tape, hipStream_t st, int* launches) {
   const int N = h->N;
@@ -263,14 +267,17 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
   } else {
     const bool mfma = variant == SIM_V_FUSED_MFMA;
     const int chunk = (spl <= 0 || spl > T) ? T : spl;
+    float* rec = tape ? h->bw.seg[0] : nullptr;
+    const int rec_from = tape ? ((T + K - 1) / K - 1) * K : 0;
+    const int rec_n = T - rec_from;
     for (int t0 = 0; t0 < T; t0 += chunk) {
       const int n = (T - t0) < chunk ? (T - t0) : chunk;
       if (variant == SIM_V_FUSED_MFMA4)
-        HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
-                              st));
+        HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
+                              rec_from, rec_n, st));
       else if (variant == SIM_V_FUSED_SPLIT)
-        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, nullptr,
-                             st));
+        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
+                             rec_from, rec_n, st));
       else
         HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
@@ -431,10 +438,10 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
                               nullptr, st));
   } else if (v == SIM_V_FUSED_MFMA4 && actor) {
     HIP_TRY(launch_fused4(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr,
-                          h->cfg.ckpt_every, nullptr, nullptr, st));
+                          h->cfg.ckpt_every, nullptr, nullptr, 0, 0, st));
   } else if (v == SIM_V_FUSED_SPLIT && actor) {
     HIP_TRY(launch_split(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr, 1, nullptr,
-                         nullptr, st));
+                         nullptr, 0, 0, st));
   } else {
     // external actions run on the one-env-per-lane kernel (it has the
     // action-input path); both kernels share the state layout
@@ -520,7 +527,10 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   }
   h->last_launches = launches;
   h->timing_valid = true;
-  if (record_tape) h->tape_T = T;
+  if (record_tape) {
+    h->tape_T = T;
+    h->last_seg_recorded = true;
+  }
   return SIM_OK;
 }
 
@@ -576,7 +586,11 @@ int sim_backward(sim_handle* h, const float* actor, const float* d_rewards, cons
   int rc = sticky_error();
   if (rc) return rc;
   HIP_TRY(run_backward(h->dc, h->b, h->bw, actor, h->tape, h->cfg.ckpt_every, h->tape_T, d_rewards,
-                       d_states, grad_actor, grad_params, (hipStream_t)stream));
+                       d_states, grad_actor, grad_params, h->last_seg_recorded,
+                       (hipStream_t)stream));
+  // with more segments than buffers, the first buffer was reused
+  const int J = (h->tape_T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
+  if (J > BWD_NBUF) h->last_seg_recorded = false;
   return SIM_OK;
 }
 

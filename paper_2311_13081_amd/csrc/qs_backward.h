@@ -26,9 +26,11 @@ struct BwdBufs {
 
 hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H);
 void bwd_free(BwdBufs& bw);
+// last_recorded: bw.seg[0] already holds the record of the last segment
+// (written by the taped rollout), so its recompute is skipped.
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
-                        hipStream_t st);
+                        bool last_recorded, hipStream_t st);
 
 }  // namespace qs

@@ -996,7 +996,7 @@ void bwd_free(BwdBufs& bw) {
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
-                        hipStream_t st) {
+                        bool last_recorded, hipStream_t st) {
   const int N = c.n_envs;
   const size_t np = (size_t)bw.n_parts * DW_SLOT;
   hipLaunchKernelGGL(k_fill, dim3(nb((int)np, 256)), dim3(256), 0, st, bw.gpart, np, 0.0f);
@@ -1015,11 +1015,15 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
     const int t0 = j * K;
     const int n = (T - t0) < K ? (T - t0) : K;
     const int buf = idx % BWD_NBUF;
-    if (overlap && idx >= BWD_NBUF) BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_dw[buf], 0));
-    BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * CK_F * N, bw.seg[buf], s_rec));
-    if (overlap) {
-      BWD_TRY(hipEventRecord(bw.e_rec[buf], s_rec));
-      BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
+    // the last segment's record may come from the taped rollout itself
+    // (written on the caller's stream, ahead of this call)
+    if (!(idx == 0 && last_recorded)) {
+      if (overlap && idx >= BWD_NBUF) BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_dw[buf], 0));
+      BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * CK_F * N, bw.seg[buf], s_rec));
+      if (overlap) {
+        BWD_TRY(hipEventRecord(bw.e_rec[buf], s_rec));
+        BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
+      }
     }
     if (N <= REVERSE_SPLIT_MAX_ENVS)
       hipLaunchKernelGGL(k_bwd_reverse<true>, dim3(nb(N, 16)), dim3(256), (R_TOTAL + R_XCH) * 4,

@@ -73,17 +73,22 @@ hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, i
                             const float* ck_in, float* rec, hipStream_t st);
 // Quarter-lane fused kernel (qs_fused4.hip): 16 envs per wave, 4 lanes per
 // env; the kernel of taped rollouts (tape: CK_F-row checkpoints every
-// ckpt_every steps).  With rec != NULL it runs in recompute mode from
-// checkpoint ck_in.
+// ckpt_every steps).  With ck_in != NULL it starts from that checkpoint and
+// leaves the env state alone (the backward's recompute).  With rec != NULL
+// it writes the backward's record of the steps t_base + t >= rec_from, a
+// segment of rec_n steps (the recompute: rec_from 0, rec_n T; a taped
+// rollout: its last segment).
 hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                          float* rewards, uint8_t* dones, float* states, float* tape,
-                         int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
+                         int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
+                         hipStream_t st);
 // Split-actor fused kernel (qs_split.hip): 16 envs per workgroup of 4 waves,
 // wave w evaluating neuron tile w of layers 1 and 2; tape and record modes as
 // the quarter-lane kernel, whose results it reproduces bit for bit.
 hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                         float* rewards, uint8_t* dones, float* states, float* tape,
-                        int ckpt_every, const float* ck_in, float* rec, hipStream_t st);
+                        int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
+                        hipStream_t st);
 // The kernel of taped rollouts and of their backward recompute (the two must
 // agree bit for bit): the split-actor kernel below 16384 envs with the fp32
 // actor (the quarter-lane kernel leaves SIMDs idle there), else the

@@ -323,8 +323,8 @@ hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, i
                             const float* ck_in, float* rec, hipStream_t st) {
   // the kernel of taped rollouts, in record mode
   if (taped_on_split(c))
-    return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, st);
-  return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, st);
+    return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T, st);
+  return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T, st);
 }
 
 }  // namespace qs

@@ -182,6 +182,22 @@ def test_split_kernels_match_quarter_lane_bitwise(pkg, oracle_lib):
     assert np.array_equal(gps[0], gps[1])
 
 
+@pytest.mark.parametrize("T,K", [(24, 8), (40, 8)])
+def test_backward_twice_on_one_tape(pkg, oracle_lib, T, K):
+    """The taped rollout writes the backward's record of its last segment, so
+    the first backward skips that recompute.  With more segments than record
+    buffers (40 / 8 = 5 > 3) the backward reuses that buffer and a second
+    backward on the same tape recomputes the segment; with 3 segments it
+    still holds it.  Either way the gradients repeat bit for bit."""
+    cfg, sim, ref, th = setup(pkg, oracle_lib, 300, T, K, dr=1)
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    sim.rollout(a, T, rewards=False, dones=False, states=False, record_tape=True)
+    g1 = [np_(x) for x in sim.backward(a)]
+    g2 = [np_(x) for x in sim.backward(a)]
+    assert np.array_equal(g1[0], g2[0]) and np.array_equal(g1[1], g2[1])
+    sim.close()
+
+
 def test_autograd_function(pkg, oracle_lib):
     """RolloutFn: loss = sum of rewards + a state term; torch autograd gives
     the same gradients as the direct C-ABI backward."""
