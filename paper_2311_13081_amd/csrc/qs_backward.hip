@@ -99,7 +99,7 @@ struct StepIn {
 };
 
 template <int ZT>
-__device__ inline void load_step(StepIn<ZT>& in, const DevCfg& c, const float* __restrict__ rec,
+__device__ inline void load_step(StepIn<ZT>& in, const float* __restrict__ rec,
                                  const float* __restrict__ d_rewards,
                                  const float* __restrict__ d_states, int tl, int t0, int N, int e,
                                  int k, int w) {
@@ -328,10 +328,10 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
   // loaded while step tl is processed, so their latency hides behind it.
   constexpr int ZT = SPLIT ? 1 : 4;
   StepIn<ZT> cur, nxt;
-  load_step<ZT>(cur, c, rec, d_rewards, d_states, n - 1, t0, N, e, k, w);
+  load_step<ZT>(cur, rec, d_rewards, d_states, n - 1, t0, N, e, k, w);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
-    load_step<ZT>(nxt, c, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k, w);
+    load_step<ZT>(nxt, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k, w);
     // blocked cotangent rows of this env: row k and row 4k
     const uint32_t koff = opaque((uint32_t)(rb_at(e, DZ_F) + k * RB));
     const uint32_t zoff = opaque((uint32_t)(rb_at(e, DZ_F) + 4 * k * RB));

@@ -22,6 +22,7 @@ namespace qs {
 constexpr int P_W1T = 0, P_B1 = P_W1T + NO * NHID, P_W2T = P_B1 + NHID,
               P_B2 = P_W2T + NHID * NHID, P_W3T = P_B2 + NHID, P_B3 = P_W3T + NHID * NA,
               P_TOTAL = P_B3 + NA;
+static_assert(P_TOTAL * 8 == PRECISE_LDS_BYTES, "LDS layout must fill the launch's LDS");
 
 __device__ inline void uniforms4_f64(uint32_t klo, uint32_t khi, uint32_t env, uint32_t episode,
                                      uint32_t block, uint32_t stream, double u[4]) {
