@@ -229,17 +229,20 @@ int sim_set_state(sim_handle* h, const float* state, const float* hist, const in
 int sim_get_params(sim_handle* h, float* theta, void* stream);
 int sim_set_params(sim_handle* h, const float* theta, void* stream);
 
-/* Chooses the forward variant (SIM_V_*; taped rollouts always use
- * SIM_V_FUSED_MFMA4, the kernel the backward pass recomputes with), steps per launch for the fused
+/* Chooses the forward variant (SIM_V_*), steps per launch for the fused
  * variants (0 = whole rollout in one launch) and whether multi-launch
- * rollouts are replayed from a captured hipGraph (use_graph != 0). */
+ * rollouts are replayed from a captured hipGraph (use_graph != 0).  Taped
+ * rollouts ignore the variant: they run on the kernel the backward pass
+ * recomputes segments with (see sim_rollout). */
 int sim_set_variant(sim_handle* h, int variant, int steps_per_launch, int use_graph);
 int sim_get_variant(const sim_handle* h, int* variant, int* steps_per_launch, int* use_graph);
 
 /* Times every variant and launch shape on a T-step rollout with HIP events,
  * keeps the fastest (ties go to the earlier candidate), restores the env state
  * afterwards.  Writes the chosen variant and its time to *variant_out and
- * *ms_out (either may be NULL).  Synchronises. */
+ * *ms_out (either may be NULL).  Synchronises.  On failure the tuned choice
+ * and the variant settings are left as they were, the temporary snapshot is
+ * freed, and the env state is unspecified. */
 int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int* variant_out,
                  float* ms_out);
 

@@ -361,9 +361,12 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   if (!rc && cfg->max_tape_horizon > 0) {
     h->tape_ckpts = (cfg->max_tape_horizon + cfg->ckpt_every - 1) / cfg->ckpt_every + 1;
     rc = alloc((void**)&h->tape, (size_t)h->tape_ckpts * CK_F * N * 4);
-    if (!rc) rc = bwd_alloc(h->bw, h->N, cfg->ckpt_every, cfg->max_tape_horizon) == hipSuccess
-                      ? SIM_OK
-                      : fail(SIM_E_NOMEM, "backward scratch allocation failed");
+    if (!rc) {
+      const hipError_t e = bwd_alloc(h->bw, h->N, cfg->ckpt_every, cfg->max_tape_horizon);
+      if (e != hipSuccess)
+        rc = fail(e == hipErrorOutOfMemory ? SIM_E_NOMEM : SIM_E_DEVICE,
+                  "backward scratch set-up: %s", hipGetErrorString(e));
+    }
   }
   if (!rc && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
     rc = fail(SIM_E_DEVICE, "stream creation failed");
@@ -691,14 +694,36 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   hipStream_t st = (hipStream_t)stream;
   const size_t N = (size_t)h->N;
   // Snapshot so every candidate starts from the same state and the caller's
-  // state is restored afterwards.
-  float *s_state = nullptr, *s_hist = nullptr;
-  int32_t *s_tep = nullptr, *s_ep = nullptr;
-  HIP_TRY(hipMalloc(&s_state, N * NS * 4));
-  HIP_TRY(hipMalloc(&s_hist, N * NH * NA * 4));
-  HIP_TRY(hipMalloc(&s_tep, N * 4));
-  HIP_TRY(hipMalloc(&s_ep, N * 4));
-  HIP_TRY(launch_get_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
+  // state is restored afterwards.  The snapshot is freed, and the caller's
+  // variant restored, on every way out (the guards' destructors run in
+  // reverse order: variant first, then the buffers once the stream is idle).
+  struct Snapshot {
+    hipStream_t st;
+    float *state = nullptr, *hist = nullptr;
+    int32_t *tep = nullptr, *ep = nullptr;
+    ~Snapshot() {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(state);
+      (void)hipFree(hist);
+      (void)hipFree(tep);
+      (void)hipFree(ep);
+    }
+  } snap{st};
+  struct VariantRestore {
+    sim_handle* h;
+    int v, spl;
+    ~VariantRestore() {
+      h->variant = v;
+      h->spl = spl;
+      h->tape_T = 0;
+      drop_graph(h);
+    }
+  } restore{h, h->variant, h->spl};
+  HIP_TRY(hipMalloc(&snap.state, N * NS * 4));
+  HIP_TRY(hipMalloc(&snap.hist, N * NH * NA * 4));
+  HIP_TRY(hipMalloc(&snap.tep, N * 4));
+  HIP_TRY(hipMalloc(&snap.ep, N * 4));
+  HIP_TRY(launch_get_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
   struct Cand { int v, spl; };
   std::vector<Cand> cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0},
                              {SIM_V_FUSED_SPLIT, 0}, {SIM_V_FUSED_MFMA4, 100},
@@ -707,7 +732,6 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   if (h->bf16)
     cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0}, {SIM_V_FUSED_MFMA4, 100},
              {SIM_V_FUSED_MFMA, 100}};
-  const int save_v = h->variant, save_spl = h->spl;
   float best = 1e30f;
   Cand bestc = cands[0];
   for (const Cand& cd : cands) {
@@ -717,36 +741,23 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
     drop_graph(h);
     float acc = 0;
     for (int rep = 0; rep < 3; ++rep) {
-      HIP_TRY(launch_set_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st));
+      HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
       rc = sim_rollout(h, actor, T, nullptr, nullptr, nullptr, 0, stream);
-      if (rc) break;
+      if (rc) return rc;
       HIP_TRY(hipEventSynchronize(h->ev1));
       float ms = 0;
       HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
       if (rep > 0) acc += ms;  // first run warms up (and captures the graph)
     }
-    if (rc) break;
     const float ms = acc / 2;
     if (ms < best) {
       best = ms;
       bestc = cd;
     }
   }
-  h->variant = save_v;
-  h->spl = save_spl;
-  drop_graph(h);
-  if (!rc) {
-    h->tuned_variant = bestc.v;
-    h->tuned_spl = bestc.spl;
-    (void)launch_set_state(h->b, h->N, s_state, s_hist, s_tep, s_ep, st);
-  }
-  (void)hipStreamSynchronize(st);
-  (void)hipFree(s_state);
-  (void)hipFree(s_hist);
-  (void)hipFree(s_tep);
-  (void)hipFree(s_ep);
-  h->tape_T = 0;
-  if (rc) return rc;
+  HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
+  h->tuned_variant = bestc.v;
+  h->tuned_spl = bestc.spl;
   if (variant_out) *variant_out = bestc.v;
   if (ms_out) *ms_out = best;
   return SIM_OK;
