@@ -281,11 +281,13 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
                 "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA}
     roof["flop_per_env_step"] = FLOP_FWD_BWD_ENV_STEP
     K = cfg["ckpt_every"]
-    # checkpoints of (state, history, counters): 147 floats per env; one
-    # step's backward record: 295 floats per env
+    # checkpoints of (state, history, counters): 147 floats per env; the
+    # backward's record: 171 floats per env and step (state features, x, a,
+    # both layers' pre-activations, the step's action) and the 128-float
+    # action history at the start of the recorded span
     mem = {"device_bytes_of_handle": handle_bytes,
            "tape_bytes": (H // K + 1) * 147 * N * 4,
-           "records_of_whole_horizon_bytes": H * 295 * N * 4}
+           "records_of_whole_horizon_bytes": (H * 171 + 128) * N * 4}
     return {"env_steps_per_s": rate, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
             "horizon": H, "ckpt_every": K, "actor": "bf16" if bf16 else "f32",
             "roofline": roof, "memory": mem}
@@ -293,9 +295,12 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
 
 def fwd_bwd_legs(torch, pkg, W):
     """The differentiable workloads: the policy gradient on 1024 nominal envs
-    over 64 steps, and system identification on 16384 randomised envs over
-    256 steps (fp32 and bf16 actor), checkpoints every 16 steps."""
+    over 64 steps, the same on 65536 randomised envs (the hover-biased
+    policy, which keeps every body's rates bounded over the horizon),
+    and system identification on 16384 randomised envs over 256 steps (fp32
+    and bf16 actor), checkpoints every 16 steps."""
     return {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
+            "grad65536_dr": fwd_bwd(torch, pkg, "grad65536_dr", 16, wl.sysid_actor(0)),
             "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0)),
             "sysid16384_bf16": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0),
                                        bf16=True)}

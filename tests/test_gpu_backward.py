@@ -112,10 +112,8 @@ def test_backward_vs_fp64_central_differences(pkg, oracle_lib):
     eps = 1e-6
     fd = np.zeros((n, 8))
     for k in range(8):
-        bp, bm = ref.copy(), ref.copy()
-        bp.theta[:, k] += eps * sc[:, k]
-        bm.theta[:, k] -= eps * sc[:, k]
-        # envs are independent: one perturbed batch gives every env's derivative
+        # the oracle's loss sums over envs, so each env's parameter is
+        # perturbed on its own
         for i in range(n):
             b1, b2 = ref.copy(), ref.copy()
             b1.theta[i, k] += eps * sc[i, k]
@@ -321,5 +319,59 @@ def test_sysid16384_full_size(pkg, oracle_lib):
     sc = param_scale(cfg, ref.theta)
     ep = np.linalg.norm((gp - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
     print(f"sysid16384 sampled VJP (H=32): max rel err {ep.max():.2e}, median {np.median(ep):.2e}")
+    assert ep.max() < GRAD_TOL
+    sim.close()
+
+
+def test_grad65536_dr_full_size(pkg, oracle_lib):
+    """Policy gradient at the large batch's size: 65536 randomised envs,
+    horizon 64, checkpoints every 16, the hover-biased policy.  The backward
+    is linear in its cotangents and the envs are independent, so with reward
+    cotangent one on a sample of envs and zero elsewhere the actor gradient
+    is the sample's own and every other env's parameter gradient is exactly
+    zero; the sample's gradients match the oracle's adjoint of those envs.
+    With the full cotangent the gradients are finite and a second backward
+    on the same tape repeats them bit for bit."""
+    orc = oracle_lib
+    cfg = wl.workload_config("grad65536_dr")
+    H = wl.workload_steps("grad65536_dr")
+    N = cfg["n_envs"]
+    sim = pkg.QuadSim(cfg)
+    W = wl.sysid_actor(0)
+    a = sim.actor_tensor(W)
+    ids = np.sort(np.random.default_rng(5).choice(N, 24, replace=False)).astype(np.uint32)
+    ob = orc.Batch.init(cfg, len(ids), ids=ids)
+    s32, h32 = (x.astype(np.float32) for x in ob.soa())
+    st = {k: v.clone() for k, v in sim.get_state().items()}
+    idx = torch.as_tensor(ids.astype(np.int64)).cuda()
+    st["state"][:, idx] = torch.as_tensor(s32).cuda()
+    st["hist"][:, :, idx] = torch.as_tensor(h32).cuda()
+    sim.set_state(**st)
+    th = np_(sim.get_params())
+    sim.rollout(a, H, rewards=False, dones=False, record_tape=True)
+
+    ga1, gp1 = (np_(x).copy() for x in sim.backward(a))
+    ga2, gp2 = (np_(x) for x in sim.backward(a))
+    assert np.all(np.isfinite(ga1)) and np.all(np.isfinite(gp1))
+    assert np.array_equal(ga1, ga2) and np.array_equal(gp1, gp2)
+
+    mask = torch.zeros(H, N, device="cuda")
+    mask[:, idx] = 1.0
+    ga, gp = sim.backward(a, d_rewards=mask)
+    ga = np_(ga).astype(np.float64)
+    gp = np_(gp).astype(np.float64)
+    rest = np.ones(N, bool)
+    rest[ids] = False
+    assert not gp[:, rest].any()
+    ref = orc.Batch(cfg, len(ids), ids=ids)
+    ref.set_soa(s32, h32, theta_soa=th[:, ids])
+    _, gW, gth = ref.grad(W, H, nthreads=8)
+    ea = np.linalg.norm(ga - gW) / np.linalg.norm(gW)
+    gps = gp[:, ids].T
+    sc = param_scale(cfg, ref.theta)
+    ep = np.linalg.norm((gps - gth) * sc, axis=1) / np.linalg.norm(gth * sc, axis=1)
+    print(f"grad65536_dr sample of {len(ids)}: actor rel err {ea:.2e}, "
+          f"params max rel err {ep.max():.2e}")
+    assert ea < GRAD_TOL
     assert ep.max() < GRAD_TOL
     sim.close()

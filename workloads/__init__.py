@@ -111,8 +111,9 @@ def training_extras(cfg: dict) -> dict:
     return out
 
 
-# The five workloads: a small parity case, the plain-vs-fused comparison, the
-# large randomised batch, the differentiable rollout and the system-ID rollout.
+# The workloads: a small parity case, the plain-vs-fused comparison, the large
+# randomised batch, the differentiable rollout, the system-ID rollout, and the
+# policy gradient at the large batch's size (65536 randomised envs).
 WORKLOADS = {
     "fwd64": dict(n_envs=64, steps=500, flags=F_RENORM_Q, dr_enable=0, max_episode_steps=500),
     "fwd4096": dict(n_envs=4096, steps=1000, flags=F_RENORM_Q | F_AUTORESET, dr_enable=0,
@@ -123,7 +124,12 @@ WORKLOADS = {
     "grad1024": dict(n_envs=1024, steps=64, flags=F_RENORM_Q, dr_enable=0, max_episode_steps=0),
     "sysid16384": dict(n_envs=16384, steps=256, flags=F_RENORM_Q, dr_enable=1,
                        max_episode_steps=0, ckpt_every=16),
+    "grad65536_dr": dict(n_envs=65536, steps=64, flags=F_RENORM_Q, dr_enable=1,
+                         max_episode_steps=0, ckpt_every=16),
 }
+
+# workloads whose rollouts are differentiated (a tape of the whole horizon)
+DIFFERENTIABLE = ("grad1024", "sysid16384", "grad65536_dr")
 
 
 def workload_config(name: str, **overrides) -> dict:
@@ -131,7 +137,7 @@ def workload_config(name: str, **overrides) -> dict:
     steps = w.pop("steps")
     w.update(overrides)
     cfg = crazyflie_config(**w)
-    if name in ("grad1024", "sysid16384") and "max_tape_horizon" not in overrides:
+    if name in DIFFERENTIABLE and "max_tape_horizon" not in overrides:
         cfg["max_tape_horizon"] = steps
     return cfg
 
