@@ -19,6 +19,7 @@ class RolloutFn(torch.autograd.Function):
         out = sim.rollout(a, T, rewards=True, dones=False, states=True, record_tape=True)
         ctx.sim = sim
         ctx.T = T
+        ctx.tape_gen = sim.tape_gen
         ctx.save_for_backward(a)
         return out["states"], out["rewards"]
 
@@ -26,6 +27,11 @@ class RolloutFn(torch.autograd.Function):
     def backward(ctx, d_states, d_rewards):
         (a,) = ctx.saved_tensors
         sim = ctx.sim
+        # the handle holds one tape: refuse to differentiate another rollout's
+        if sim.tape_gen != ctx.tape_gen or sim.tape_T != ctx.T:
+            raise RuntimeError("the simulator's tape no longer belongs to this rollout (another "
+                               "taped rollout, or a call that drops the tape, came in between); "
+                               "run the backward before the next rollout on the same handle")
         # a NULL reward cotangent means "all ones" at the C ABI, so an absent
         # one is passed as explicit zeros
         if d_rewards is None:

@@ -39,6 +39,12 @@ class QuadSim:
         h = ctypes.c_void_p()
         check(self.L.sim_create(ctypes.byref(c), device, ctypes.byref(h)), "sim_create")
         self.h = h
+        # Mirror of the handle's tape: the horizon of the last taped rollout
+        # (0 once a call has dropped the tape, as the library does) and a
+        # count of taped rollouts, so that a backward can tell which tape it
+        # would differentiate and size-check its cotangents against it.
+        self.tape_T = 0
+        self.tape_gen = 0
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -75,6 +81,7 @@ class QuadSim:
     def reset(self, seed: int | None = None):
         s = self.cfg["seed"] if seed is None else seed
         check(self.L.sim_reset(self.h, ctypes.c_uint64(s), _stream()), "sim_reset")
+        self.tape_T = 0
 
     def step(self, actor: torch.Tensor | None = None, actions: torch.Tensor | None = None):
         """One step; returns (reward [N], done [N] uint8)."""
@@ -84,6 +91,7 @@ class QuadSim:
         d = torch.empty(self.N, dtype=torch.uint8, device=self.device)
         check(self.L.sim_step(self.h, _ptr(actor), _ptr(actions), _ptr(r), _ptr(d), _stream()),
               "sim_step")
+        self.tape_T = 0
         return r, d
 
     def rollout(self, actor: torch.Tensor, T: int, rewards=True, dones=True, states=False,
@@ -106,6 +114,9 @@ class QuadSim:
         check(self.L.sim_rollout(self.h, _ptr(actor), T, _ptr(out.get("rewards")),
                                  _ptr(out.get("dones")), _ptr(out.get("states")),
                                  1 if record_tape else 0, _stream()), "sim_rollout")
+        self.tape_T = int(T) if record_tape else 0
+        if record_tape:
+            self.tape_gen += 1
         return out
 
     def observe(self, actor=True, critic=True):
@@ -142,10 +153,21 @@ class QuadSim:
                                          _ptr(out.get("rewards")), _ptr(out.get("dones")),
                                          _ptr(out.get("states")), _stream()),
               "sim_rollout_actions")
+        self.tape_T = 0
         return out
 
     def backward(self, actor: torch.Tensor, d_rewards=None, d_states=None, want_actor=True,
                  want_params=True):
+        """Gradients of the last taped rollout: (grad_actor [13828], grad_params
+        [8][N]) for the loss sum d_rewards * rewards + sum d_states * states
+        (d_rewards None = all ones, d_states None = zeros)."""
+        self._need(actor, (_lib.SIM_NACTOR,), torch.float32, "actor")
+        T = self.tape_T
+        if T > 0:
+            self._need(d_rewards, (T, self.N), torch.float32, "d_rewards")
+            self._need(d_states, (T + 1, 17, self.N), torch.float32, "d_states")
+        # without a tape the library refuses the call (SIM_E_STATE) before it
+        # reads any argument
         ga = torch.empty(_lib.SIM_NACTOR, dtype=torch.float32, device=self.device) if want_actor else None
         gp = self._f32(8, self.N) if want_params else None
         check(self.L.sim_backward(self.h, _ptr(actor), _ptr(d_rewards), _ptr(d_states), _ptr(ga),
@@ -166,8 +188,13 @@ class QuadSim:
             return None if x is None else torch.as_tensor(x, dtype=dt).to(self.device).contiguous()
         s, h = dev(state, torch.float32), dev(hist, torch.float32)
         t, e = dev(t_ep, torch.int32), dev(episode, torch.int32)
+        self._need(s, (17, self.N), torch.float32, "state")
+        self._need(h, (32, 4, self.N), torch.float32, "hist")
+        self._need(t, (self.N,), torch.int32, "t_ep")
+        self._need(e, (self.N,), torch.int32, "episode")
         check(self.L.sim_set_state(self.h, _ptr(s), _ptr(h), _ptr(t), _ptr(e), _stream()),
               "sim_set_state")
+        self.tape_T = 0
 
     def get_params(self):
         th = self._f32(8, self.N)
@@ -176,7 +203,9 @@ class QuadSim:
 
     def set_params(self, theta):
         th = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()
+        self._need(th, (8, self.N), torch.float32, "theta")
         check(self.L.sim_set_params(self.h, _ptr(th), _stream()), "sim_set_params")
+        self.tape_T = 0
 
     def set_variant(self, variant: int, steps_per_launch: int = 0, use_graph: bool = True):
         check(self.L.sim_set_variant(self.h, variant, steps_per_launch, 1 if use_graph else 0),
@@ -208,6 +237,7 @@ class QuadSim:
         v, ms = ctypes.c_int(), ctypes.c_float()
         check(self.L.sim_autotune(self.h, _ptr(actor), T, _stream(), ctypes.byref(v),
                                   ctypes.byref(ms)), "sim_autotune")
+        self.tape_T = 0
         if key is not None:
             _, spl, _ = self.get_variant()
             table[key] = {"variant": v.value, "steps_per_launch": spl, "ms": ms.value}

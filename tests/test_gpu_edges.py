@@ -175,8 +175,50 @@ def test_binding_refuses_tensors_of_the_wrong_shape(pkg):
         lambda: sim.step(actions=torch.zeros(4, n + 1, device="cuda")),
         lambda: sim.step(actor=a[:-1]),
         lambda: sim.rollout(a, 8, out={"rewards": torch.zeros(7, n, device="cuda")}),
+        lambda: sim.set_state(state=torch.zeros(17, n - 1, device="cuda")),
+        lambda: sim.set_state(hist=torch.zeros(32, n, device="cuda")),
+        lambda: sim.set_state(t_ep=torch.zeros(n + 1, dtype=torch.int32, device="cuda")),
+        lambda: sim.set_params(torch.ones(7, n, device="cuda")),
     ]
     for call in bad:
         with pytest.raises(ValueError):
             call()
+    sim.close()
+    # cotangents of a backward are checked against the tape's horizon
+    T = 6
+    cfg = wl.crazyflie_config(n_envs=n, max_episode_steps=0, max_tape_horizon=8, ckpt_every=4)
+    sim = pkg.QuadSim(cfg)
+    a = sim.actor_tensor(wl.xavier_actor(0))
+    sim.rollout(a, T, record_tape=True)
+    for kw in (dict(d_rewards=torch.ones(T + 1, n, device="cuda")),
+               dict(d_rewards=torch.ones(T, n, dtype=torch.float64, device="cuda")),
+               dict(d_states=torch.zeros(T, 17, n, device="cuda")),
+               dict(d_states=torch.zeros(T + 1, 17, n - 1, device="cuda"))):
+        with pytest.raises(ValueError):
+            sim.backward(a, **kw)
+    ga, gp = sim.backward(a, d_rewards=torch.ones(T, n, device="cuda"),
+                          d_states=torch.zeros(T + 1, 17, n, device="cuda"))
+    assert bool(torch.isfinite(ga).all()) and bool(torch.isfinite(gp).all())
+    sim.close()
+
+
+def test_autograd_refuses_a_replaced_tape(pkg):
+    """The handle holds one tape: the backward of a rollout whose tape a later
+    taped rollout (or a call that drops the tape) replaced raises instead of
+    differentiating the other trajectory."""
+    n, T = 32, 8
+    cfg = wl.crazyflie_config(n_envs=n, max_episode_steps=0, max_tape_horizon=T, ckpt_every=4)
+    sim = pkg.QuadSim(cfg)
+    W = sim.actor_tensor(wl.xavier_actor(0)).requires_grad_()
+    theta = sim.get_params().clone().requires_grad_()
+    S1, R1 = pkg.rollout(sim, W, theta, T)
+    S2, R2 = pkg.rollout(sim, W, theta, T)
+    with pytest.raises(RuntimeError, match="tape"):
+        R1.sum().backward()
+    R2.sum().backward()
+    assert W.grad is not None and bool(torch.isfinite(W.grad).all())
+    S3, R3 = pkg.rollout(sim, W, theta, T)
+    sim.set_params(theta.detach())
+    with pytest.raises(RuntimeError, match="tape"):
+        R3.sum().backward()
     sim.close()
