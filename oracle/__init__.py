@@ -18,18 +18,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "quad_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# QS_ORACLE_LIB names another build of the oracle's source to load instead
+# (the planted-mistake tests compile mutated copies and run the pins on them)
+_LIB = os.environ.get("QS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 NS, NH, NA, NO, NHID, NP, NW = 17, 32, 4, 146, 64, 8, 13828
 
 
+def compile_source(src: str, out: str) -> None:
+    """gcc build of an oracle source (plain -O2, IEEE double, no fast-math,
+    no contraction into fused multiply-adds)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
+           "-Wall", "-Wno-unused-variable", src, "-o", out + ".tmp", "-lm", "-lpthread"]
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain -O2, IEEE double, no fast-math)."""
+    """Compile liboracle.so from quad_oracle.c."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
-               "-Wall", "-Wno-unused-variable", _SRC, "-o", _LIB + ".tmp", "-lm", "-lpthread"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 

@@ -233,6 +233,56 @@ def test_hover_equilibrium(orc):
         assert np.allclose(S, s0[None, :], rtol=0, atol=1e-11 * np.maximum(1, np.abs(s0)))
 
 
+def test_thrust_acts_along_body_z(orc):
+    """The collective thrust F = sum(c0 + c1 w + c2 w^2) accelerates the body
+    along its own z axis, the third column of the library rotation matrix
+    (body to world): dv/dt = F/m R e_z - g e_z, for any attitude and rotor
+    speeds.  Worked case: a body rolled by +30 degrees about x pushes towards
+    -y with F/m sin 30."""
+    from scipy.spatial.transform import Rotation
+    cfg = base_cfg()
+    th = np.array([0.031, 4.1e-6, 3.7e-6, 6.2e-6, 0.004, 2.1e-6, 2.9e-10, 0.11])
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        wm = rng.uniform(3000, 20000, size=4)
+        x = state(q=q, wm=wm)
+        dx = orc.dynamics(cfg, th, x, wm)
+        F = np.sum(th[4] + th[5] * wm + th[6] * wm * wm)
+        ez = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()[:, 2]
+        want = F / th[0] * ez - np.array([0.0, 0.0, cfg["g"]])
+        assert np.allclose(dx[7:10], want, rtol=1e-13, atol=1e-13)
+    phi = math.radians(30.0)
+    wm = np.full(4, 15000.0)
+    x = state(q=(math.cos(phi / 2), math.sin(phi / 2), 0.0, 0.0), wm=wm)
+    dx = orc.dynamics(cfg, th, x, wm)
+    F = 4 * (th[4] + th[5] * 15000.0 + th[6] * 15000.0 ** 2)
+    assert dx[7] == pytest.approx(0.0, abs=1e-15)
+    assert dx[8] == pytest.approx(-F / th[0] * math.sin(phi), rel=1e-13)
+    assert dx[9] == pytest.approx(F / th[0] * math.cos(phi) - cfg["g"], rel=1e-13)
+
+
+def test_history_push_order(orc):
+    """Each step appends its action as the newest of the 32 history slots and
+    drops the oldest: after T < 32 steps with given actions a_0 .. a_{T-1}
+    the history is the start history's last 32 - T slots followed by
+    a_0 .. a_{T-1}, and the observation shows it oldest first."""
+    cfg = base_cfg(max_episode_steps=0)
+    rng = np.random.default_rng(22)
+    H0 = rng.uniform(-1, 1, size=(32, 4))
+    A = rng.uniform(-1, 1, size=(5, 4))
+    s0 = state(wm=(14000.0,) * 4)
+    b = orc.Batch(cfg, 1)
+    b.theta[0] = nominal(cfg)
+    b.s[0] = s0
+    b.H[0] = H0
+    b.rollout(None, 5, actions=A.reshape(5, 1, 4))
+    want = np.concatenate([H0[5:], A])
+    assert np.array_equal(b.H[0], want)
+    assert np.array_equal(orc.observe(b.s[0], b.H[0])[18:], want.ravel())
+
+
 def test_free_fall_exact_under_rk4(orc):
     """No thrust: p(t) = p0 + v0 t - g t^2/2 e_z exactly (RK4 is exact for
     polynomials of degree <= 4); attitude and rotors unchanged."""
