@@ -123,7 +123,7 @@ enum {
 };
 
 typedef struct sim_config {
-  int32_t n_envs;            /* N >= 1                                               */
+  int32_t n_envs;            /* 1 <= N <= 2^24 (16 777 216)                          */
   int32_t max_episode_steps; /* truncation cap (0 = none)                            */
   int32_t flags;             /* SIM_F_*                                              */
   int32_t dr_enable;         /* 1: per-env parameters = nominal * U(dr_lo, dr_hi)    */

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) k_plain_obs(DevCfg c, SimBufs b, float* _
     const int slot = (h + s) & (NH - 1);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
-      obs[(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+      obs[(size_t)(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
   }
 }
 
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) k_plain_dense(int N, const float* __restr
 #pragma unroll
   for (int n = 0; n < NOUT; ++n) acc[n] = sb[n];
   for (int k = 0; k < NIN; ++k) {
-    const float x = in[k * N + e];
+    const float x = in[(size_t)k * N + e];
 #pragma unroll
     for (int n = 0; n < NOUT; ++n) acc[n] = fmaf(sW[k * NOUT + n], x, acc[n]);
   }
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) k_observe(DevCfg c, SimBufs b, float* __r
       const int slot = (h + s) & (NH - 1);
 #pragma unroll
       for (int a = 0; a < NA; ++a)
-        aobs[(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
+        aobs[(size_t)(18 + s * NA + a) * N + e] = b.ring[(slot * NA + a) * N + e];
     }
   }
 }

@@ -459,3 +459,38 @@ def test_split_actor_equals_quarter_lane_bitwise(pkg, n):
     assert out["split"]["dones"].any()
     for k in out["mfma4"]:
         assert np.array_equal(out["mfma4"][k], out["split"][k], equal_nan=True), k
+
+
+def test_maximum_batch_one_step(pkg, orc):
+    """The largest batch a handle takes, 2^24 randomised envs: one step on each
+    variant from the same state matches the oracle on sampled envs, among them
+    the last 70, whose observation rows lie past 2^31 elements of the
+    146-row observation array (the plain path's and sim_observe's); the
+    observation call matches the oracle's observation there too."""
+    N = 1 << 24
+    cfg = wl.crazyflie_config(n_envs=N, dr_enable=1, flags=wl.F_RENORM_Q, max_episode_steps=0)
+    sim = make_sim(pkg, cfg, "mfma")
+    W = wl.random_actor(3)
+    a = sim.actor_tensor(W)
+    ids = np.unique(np.concatenate([np.arange(N - 70, N),
+                                    np.random.default_rng(9).choice(N - 70, 58, replace=False)]))
+    idx = torch.as_tensor(ids.astype(np.int64)).cuda()
+    snap = {k: v.clone() for k, v in sim.get_state().items()}
+    s0 = np_(snap["state"][:, idx])
+    h0 = np_(snap["hist"][:, :, idx])
+    th = np_(sim.get_params()[:, idx])
+    obs = np_(sim.observe(actor=True, critic=False)["actor"][:, idx])
+    for i in range(len(ids)):
+        o_ref = orc.observe(s0[:, i].astype(np.float64), h0[:, :, i].astype(np.float64))
+        assert np.allclose(obs[:, i], o_ref, rtol=2e-6, atol=2e-6), int(ids[i])
+    ref = oracle_batch_from_gpu_inputs(orc, cfg, s0, h0, None, None, th,
+                                       ids=ids.astype(np.uint32))
+    out = ref.rollout(W, 1)
+    for v in VARIANTS:
+        sim.set_state(**snap)
+        sim.set_variant(VARIANTS[v], 0, True)
+        r, _ = sim.step(actor=a)
+        st = np_(sim.get_state()["state"][:, idx])
+        assert max_state_err(st, ref.s) < STEP_TOL, v
+        assert reward_err(np_(r[idx]), out["rewards"][0]) < STEP_TOL, v
+    sim.close()
