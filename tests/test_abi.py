@@ -64,7 +64,8 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n_envs=0), dict(dt=-0.01), dict(flags=128), dict(ckpt_every=0),
+    dict(n_envs=0), dict(n_envs=(1 << 24) + 1), dict(dt=-0.01), dict(flags=128),
+    dict(ckpt_every=0),
     dict(flags=8 | 16), dict(dist_force=-1.0), dict(dist_torque=float("nan")),
     dict(obs_noise=(0.0, -0.1, 0.0, 0.0)),
     dict(nominal=[0.0, 3.85e-6, 3.85e-6, 5.9675e-6, 0, 0, 3.16e-10, 0.15]),
