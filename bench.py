@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain / per-step comparison legs")
-    ap.add_argument("--cpu-seconds", type=float, default=45.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (3 times): the "
                          "reference for scaling HBM traffic counters")
@@ -206,6 +206,55 @@ def oracle_step_error(torch, pkg, cfg, W, variant, warm_steps=250, n_sample=2048
     return {"one_step_state_max": float(err[same].max()), "one_step_reward_max":
             float(rerr[same].max()), "done_flags_equal": int(same.sum()), "envs": n_sample,
             "after_steps": warm_steps, "bar": 1e-5}
+
+
+def _traj_err(S_gpu, S_ref):
+    """Worst R16 error over envs and components at every step; S_gpu
+    [T+1][17][n] (GPU layout), S_ref [T+1][n][17] (oracle layout)."""
+    g = np.swapaxes(np.asarray(S_gpu, np.float64), 1, 2)
+    e = np.abs(g - S_ref) / np.maximum(np.abs(S_ref), _FLOORS)
+    return np.where(np.isnan(e), np.inf, e).max(axis=(1, 2))
+
+
+def oracle_trajectory_error(torch, pkg, W, variant, T=64, trials=8):
+    """The 64-step trajectory figures of the 64-env forward workload (nominal
+    body, seeded Xavier policy, no termination): the worst error over steps
+    0..T against the FP64 oracle of the headline kernel and of the FP64 path,
+    beside the FP64 oracle's own envelope (its trajectory from start states
+    perturbed by one float32 rounding, worst of `trials` draws)."""
+    import oracle
+    cfg = wl.workload_config("fwd64")
+    n = cfg["n_envs"]
+    ref = oracle.Batch.init(cfg, n)
+    base = ref.copy().rollout(W, T, record=True)["states"]
+    rng = np.random.default_rng(0)
+    env = np.zeros(T + 1)
+    for _ in range(trials):
+        b = ref.copy()
+        b.s = b.s * (1 + 2.0 ** -24 * rng.choice([-1.0, 1.0], size=b.s.shape))
+        env = np.maximum(env, _traj_err(np.swapaxes(b.rollout(W, T, record=True)["states"], 1, 2),
+                                        base))
+    out = {}
+    for label, flags in (("fp32_headline_kernel", 0), ("fp64_path", wl.F_FP64)):
+        c = dict(cfg)
+        c["flags"] = cfg["flags"] | flags
+        sim = pkg.QuadSim(c)
+        if not flags:
+            sim.set_variant(*variant)
+        S = sim.rollout(sim.actor_tensor(W), T, rewards=False, dones=False,
+                        states=True)["states"].cpu().numpy()
+        sim.close()
+        out[label] = _traj_err(S, base)
+    e32, e64 = out["fp32_headline_kernel"], out["fp64_path"]
+    return {"workload": f"fwd64: {n} nominal envs, seeded Xavier policy, {T} steps",
+            "bar": 1e-4,
+            "fp32_headline_kernel_max": float(e32.max()),
+            "fp32_headline_kernel_step1": float(e32[1]),
+            "fp64_oracle_envelope_max": float(env.max()),
+            "fp32_over_envelope": float(e32.max() / env.max()),
+            "fp64_path_max": float(e64.max()),
+            "fp32_meets_bar": bool(e32.max() < 1e-4),
+            "fp64_path_meets_bar": bool(e64.max() < 1e-4)}
 
 
 def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
@@ -426,7 +475,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n_envs": N, "rollout_steps": T, "dr": bool(cfg["dr_enable"]),
                    "terminate_autoreset": True, "variant": vname, "steps_per_launch": spl,
-                   "hipgraph": bool(graph), "launches_per_step": launches},
+                   # a graph is captured and replayed only for multi-launch rollouts
+                   "hipgraph": bool(graph) and launches > 1,
+                   "launch": ("hipGraph replay of %d launches" % launches if graph and launches > 1
+                              else "%d launch(es) from the host" % launches),
+                   "launches_per_step": launches},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": measured_traffic(kname, N, T // launches),
@@ -457,6 +510,13 @@ def main():
                                            "ms_per_env_step": w3 * 1e3 / (2 * args.plain_steps)}
         s3.close()
         extras["fused_vs_plain_speedup"] = value / extras["plain_graph"]["env_steps_per_s"]
+        # the same kernel as a hipGraph-captured rollout of 100-step launches
+        # (ten kernel nodes replayed per rollout)
+        sim.set_variant(v, 100, True)
+        wg, dg, lg = time_rollouts(torch, sim, actor, T, 2, 1)
+        extras["headline_graph_100_steps_per_launch"] = {
+            "env_steps_per_s": N * T * 2 / wg, "kernel_ms": dg / (2 * lg),
+            "launches_per_rollout": lg, "hipgraph": lg > 1}
         # the headline kernel and shape with per-step rewards and done flags
         # written to HBM (5 B per env step)
         sim.set_variant(v, spl, graph)
@@ -504,6 +564,8 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, W, args.cpu_seconds)
         res["err_vs_oracle"] = oracle_step_error(torch, pkg, cfg, W, (v, spl, graph))
+        res["err_vs_oracle"]["trajectory_64"] = oracle_trajectory_error(torch, pkg, W,
+                                                                        (v, spl, graph))
     print(json.dumps(res), flush=True)
 
 

@@ -214,14 +214,48 @@ int sim_backward(sim_handle* h, const float* actor, const float* d_rewards,
                  const float* d_states, float* grad_actor, float* grad_params, void* stream);
 
 /* Snapshot of the per-env state: state dev [17][N], hist dev [32][4][N]
- * (oldest first), t_ep dev [N], episode dev [N].  Any pointer may be NULL. */
+ * (oldest first), t_ep dev [N], episode dev [N], and the episode
+ * accumulators (Sec. V, Training: episode return and length are the measures
+ * of training progress): returns dev [2][N] = {return of the current episode
+ * so far, return of the last finished episode}, last_len dev [N] = steps of
+ * the last finished episode (0 until one finishes).  An episode finishes when
+ * the step resets the env (SIM_F_AUTORESET): its summed rewards and its
+ * length become the "last" values and the running return restarts at 0;
+ * without in-step resets the running return keeps summing.  sim_create and
+ * sim_reset zero them.  Any pointer may be NULL. */
 int sim_get_state(sim_handle* h, float* state, float* hist, int32_t* t_ep, int32_t* episode,
-                  void* stream);
+                  float* returns, int32_t* last_len, void* stream);
 
 /* Restores a snapshot (same layouts).  NULL pointers leave that part as is.
  * Invalidates the tape. */
 int sim_set_state(sim_handle* h, const float* state, const float* hist, const int32_t* t_ep,
-                  const int32_t* episode, void* stream);
+                  const int32_t* episode, const float* returns, const int32_t* last_len,
+                  void* stream);
+
+/* Replaces the reward constants C = host {C_rp, C_rq, C_rv, C_rw, C_ra,
+ * C_rab, C_rs} (the reward equation of Sec. IV) without touching any env:
+ * steps queued after the call use the new values.  This is the hook of a
+ * reward curriculum (Sec. IV: the penalty weights grow during training).
+ * Values must be finite.  Host-side only (nothing is queued); drops a
+ * captured rollout graph. */
+int sim_set_reward(sim_handle* h, const double* C);
+
+/* Ends the episodes of the envs with mask[e] != 0 (mask dev uint8 [N]) and
+ * starts their next ones exactly as an in-step reset would (episode + 1,
+ * step 0, the counter-RNG start state of (env, episode + 1), history filled
+ * with the hover action, episode accumulators closed).  For a caller that
+ * steps without SIM_F_AUTORESET so it can read every transition's post-step
+ * state before restarting the finished envs.  Not available on SIM_F_FP64
+ * handles.  Invalidates the tape. */
+int sim_reset_envs(sim_handle* h, const uint8_t* mask, void* stream);
+
+/* Rewards of M given transitions under the handle's current reward
+ * constants: rewards dev [M] = r(s', a) for post-step states dev [17][M] and
+ * normalised actions dev [4][M] (the reward equation of Sec. IV), e.g. to
+ * re-score a replay buffer after sim_set_reward.  M >= 0; with M == 0 the
+ * pointers are not used (may be NULL). */
+int sim_reward(sim_handle* h, const float* states, const float* actions, int32_t M,
+               float* rewards, void* stream);
 
 /* Per-env dynamics parameters theta dev [8][N] (m, Jxx, Jyy, Jzz, c0, c1, c2,
  * T_m).  set: values must be finite with m, J, T_m > 0 and c2 >= 0 (checked

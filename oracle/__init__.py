@@ -154,6 +154,12 @@ class Batch:
         self.H = np.zeros((n, NH, NA))
         self.t_ep = np.zeros(n, np.int32)
         self.ep = np.zeros(n, np.int32)
+        # episode accumulators (Sec. V: episode return and length measure
+        # training): return of the running episode, return and length of the
+        # last episode that ended with an in-step reset
+        self.ret_cur = np.zeros(n)
+        self.ret_last = np.zeros(n)
+        self.len_last = np.zeros(n, np.int32)
 
     @classmethod
     def init(cls, cfg: dict, n: int, ids=None) -> "Batch":
@@ -180,7 +186,48 @@ class Batch:
         b = Batch(self.cfg, self.n, self.ids)
         b.theta, b.s, b.H = self.theta.copy(), self.s.copy(), self.H.copy()
         b.t_ep, b.ep = self.t_ep.copy(), self.ep.copy()
+        b.ret_cur, b.ret_last = self.ret_cur.copy(), self.ret_last.copy()
+        b.len_last = self.len_last.copy()
         return b
+
+    def reset_envs(self, mask):
+        """Ends the episodes of the masked envs and starts their next ones:
+        the start state and hover-filled history of (env, episode + 1), step
+        0, and the accumulators closed (running return and step count become
+        the last finished episode's)."""
+        idx = np.nonzero(np.asarray(mask) != 0)[0]
+        if len(idx) == 0:
+            return
+        ep1 = np.ascontiguousarray(self.ep[idx] + 1, np.int32)
+        ids = np.ascontiguousarray(idx if self.ids is None else self.ids[idx], np.uint32)
+        th = _f64(self.theta[idx])
+        s = np.zeros((len(idx), NS))
+        H = np.zeros((len(idx), NH, NA))
+        lib().orc_reset_state(ctypes.byref(self.c), len(idx), _p(ids), _p(ep1), _p(th), _p(s),
+                              _p(H))
+        self.s[idx] = s
+        self.H[idx] = H
+        self.ret_last[idx] = self.ret_cur[idx]
+        self.len_last[idx] = self.t_ep[idx]
+        self.ret_cur[idx] = 0.0
+        self.t_ep[idx] = 0
+        self.ep[idx] = ep1
+
+    def _accumulate(self, rew, done, t_ep0):
+        """Episode accumulators over a rollout's rewards and done flags: every
+        reward adds to the running return; a transition that ends the episode
+        with an in-step reset (autoreset on) closes it, its return and length
+        (steps since its start) becoming the last finished episode's."""
+        reset = (int(self.cfg["flags"]) & 2) != 0
+        length = np.asarray(t_ep0, np.int64).copy()
+        for t in range(rew.shape[0]):
+            self.ret_cur = self.ret_cur + rew[t]
+            length += 1
+            fin = (done[t] != 0) & reset
+            self.ret_last = np.where(fin, self.ret_cur, self.ret_last)
+            self.len_last = np.where(fin, length, self.len_last).astype(np.int32)
+            self.ret_cur = np.where(fin, 0.0, self.ret_cur)
+            length = np.where(fin, 0, length)
 
     def rollout(self, W, T, actions=None, record=False, nthreads=1):
         """T steps in place.  W: flat actor (cast to FP64) or None with actions
@@ -193,9 +240,11 @@ class Batch:
         done = np.zeros((T, n), np.uint8)
         states = np.zeros((T + 1, n, NS)) if record else None
         acts = np.zeros((T, n, NA)) if record else None
+        t_ep0 = self.t_ep.copy()
         lib().orc_rollout(ctypes.byref(self.c), n, _p(self.ids), _p(Wd), _p(A), T, _p(self.s),
                           _p(self.H), _p(self.t_ep), _p(self.ep), _p(self.theta), _p(rew),
                           _p(done), _p(states), _p(acts), nthreads)
+        self._accumulate(rew, done, t_ep0)
         out = dict(rewards=rew, dones=done)
         if record:
             out["states"] = states

@@ -26,7 +26,7 @@ EXPORTS = (
     "sim_create", "sim_destroy", "sim_reset", "sim_step", "sim_rollout", "sim_backward",
     "sim_get_state", "sim_set_state", "sim_get_params", "sim_set_params", "sim_set_variant",
     "sim_get_variant", "sim_autotune", "sim_last_rollout_timing", "sim_n_envs", "sim_last_error",
-    "sim_rollout_actions", "sim_observe",
+    "sim_rollout_actions", "sim_observe", "sim_set_reward", "sim_reset_envs", "sim_reward",
 )
 
 
@@ -94,8 +94,11 @@ def load(path: str | None = None):
         "sim_backward": ([H, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_rollout_actions": ([H, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "sim_observe": ([H, vp, vp, vp], ctypes.c_int),
-        "sim_get_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
-        "sim_set_state": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
+        "sim_get_state": ([H, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "sim_set_state": ([H, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "sim_set_reward": ([H, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "sim_reset_envs": ([H, vp, vp], ctypes.c_int),
+        "sim_reward": ([H, vp, vp, i32, vp, vp], ctypes.c_int),
         "sim_get_params": ([H, vp, vp], ctypes.c_int),
         "sim_set_params": ([H, vp, vp], ctypes.c_int),
         "sim_set_variant": ([H, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),

@@ -333,6 +333,8 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
     rc = rc ? rc : alloc((void**)&h->pb.t_ep, N * 4);
     rc = rc ? rc : alloc((void**)&h->pb.ep, N * 4);
     rc = rc ? rc : alloc((void**)&h->pb.theta, N * NP * 8);
+    rc = rc ? rc : alloc((void**)&h->pb.ret, N * 2 * 8);
+    rc = rc ? rc : alloc((void**)&h->pb.last_len, N * 4);
     if (!rc && precise_prepare() != hipSuccess) rc = fail(SIM_E_DEVICE, "fp64 kernel setup failed");
     if (!rc && hipEventCreate(&h->ev0) == hipSuccess && hipEventCreate(&h->ev1) == hipSuccess) {
       hipError_t e = precise_init(h->pc, h->pb, 1, nullptr);
@@ -354,6 +356,8 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   rc = rc ? rc : alloc((void**)&h->b.t_ep, N * 4);
   rc = rc ? rc : alloc((void**)&h->b.ep, N * 4);
   rc = rc ? rc : alloc((void**)&h->b.theta, N * NP * 4);
+  rc = rc ? rc : alloc((void**)&h->b.ret, N * 2 * 4);
+  rc = rc ? rc : alloc((void**)&h->b.last_len, N * 4);
   rc = rc ? rc : alloc((void**)&h->p.obs, N * NO * 4);
   rc = rc ? rc : alloc((void**)&h->p.h1, N * NHID * 4);
   rc = rc ? rc : alloc((void**)&h->p.h2, N * NHID * 4);
@@ -390,9 +394,11 @@ int sim_destroy(sim_handle* h) {
   DeviceGuard g(h->device);
   (void)hipDeviceSynchronize();
   drop_graph(h);
-  void* ptrs[] = {h->b.state, h->b.ring, h->b.head,  h->b.t_ep,  h->b.ep,    h->b.theta,
-                  h->p.obs,   h->p.h1,   h->p.h2,    h->p.act,   h->tape,    h->pb.state,
-                  h->pb.ring, h->pb.head, h->pb.t_ep, h->pb.ep,  h->pb.theta};
+  void* ptrs[] = {h->b.state,  h->b.ring,  h->b.head,    h->b.t_ep,  h->b.ep,
+                  h->b.theta,  h->b.ret,   h->b.last_len, h->p.obs,   h->p.h1,
+                  h->p.h2,     h->p.act,   h->tape,      h->pb.state, h->pb.ring,
+                  h->pb.head,  h->pb.t_ep, h->pb.ep,     h->pb.theta, h->pb.ret,
+                  h->pb.last_len};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   bwd_free(h->bw);
@@ -598,31 +604,79 @@ int sim_backward(sim_handle* h, const float* actor, const float* d_rewards, cons
 }
 
 int sim_get_state(sim_handle* h, float* state, float* hist, int32_t* t_ep, int32_t* episode,
-                  void* stream) {
+                  float* returns, int32_t* last_len, void* stream) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;
   if (h->fp64) {
-    HIP_TRY(precise_get(h->pb, h->N, state, hist, t_ep, episode, nullptr, (hipStream_t)stream));
+    HIP_TRY(precise_get(h->pb, h->N, state, hist, t_ep, episode, nullptr, returns, last_len,
+                        (hipStream_t)stream));
     return SIM_OK;
   }
-  HIP_TRY(launch_get_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
+  HIP_TRY(launch_get_state(h->b, h->N, state, hist, t_ep, episode, returns, last_len,
+                           (hipStream_t)stream));
   return SIM_OK;
 }
 
 int sim_set_state(sim_handle* h, const float* state, const float* hist, const int32_t* t_ep,
-                  const int32_t* episode, void* stream) {
+                  const int32_t* episode, const float* returns, const int32_t* last_len,
+                  void* stream) {
   if (!h) return fail(SIM_E_INVAL, "handle is NULL");
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;
   h->tape_T = 0;
   if (h->fp64) {
-    HIP_TRY(precise_set(h->pb, h->N, state, hist, t_ep, episode, nullptr, (hipStream_t)stream));
+    HIP_TRY(precise_set(h->pb, h->N, state, hist, t_ep, episode, nullptr, returns, last_len,
+                        (hipStream_t)stream));
     return SIM_OK;
   }
-  HIP_TRY(launch_set_state(h->b, h->N, state, hist, t_ep, episode, (hipStream_t)stream));
+  HIP_TRY(launch_set_state(h->b, h->N, state, hist, t_ep, episode, returns, last_len,
+                           (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_set_reward(sim_handle* h, const double* C) {
+  if (!h || !C) return fail(SIM_E_INVAL, "NULL argument");
+  for (int i = 0; i < 7; ++i)
+    if (!std::isfinite(C[i])) return fail(SIM_E_INVAL, "reward constant %d is not finite", i);
+  DeviceGuard g(h->device);
+  h->cfg.C_rp = C[0];
+  h->cfg.C_rq = C[1];
+  h->cfg.C_rv = C[2];
+  h->cfg.C_rw = C[3];
+  h->cfg.C_ra = C[4];
+  h->cfg.C_rab = C[5];
+  h->cfg.C_rs = C[6];
+  h->dc = make_devcfg(h->cfg, h->cfg.seed);
+  if (h->fp64) h->pc = make_precise(h->cfg, h->cfg.seed);
+  // captured graphs hold the old constants in their kernel arguments
+  drop_graph(h);
+  return SIM_OK;
+}
+
+int sim_reset_envs(sim_handle* h, const uint8_t* mask, void* stream) {
+  if (!h || !mask) return fail(SIM_E_INVAL, "NULL argument");
+  if (h->fp64) return fail(SIM_E_UNSUPPORTED, "not available on SIM_F_FP64 handles");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  h->tape_T = 0;
+  HIP_TRY(launch_reset_envs(h->dc, h->b, mask, (hipStream_t)stream));
+  return SIM_OK;
+}
+
+int sim_reward(sim_handle* h, const float* states, const float* actions, int32_t M,
+               float* rewards, void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (M < 0) return fail(SIM_E_INVAL, "M = %d < 0", M);
+  if (M == 0) return SIM_OK;  // nothing is read or written
+  if (!states || !actions || !rewards) return fail(SIM_E_INVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  HIP_TRY(launch_reward_batch(h->dc, states, actions, M, rewards, (hipStream_t)stream));
   return SIM_OK;
 }
 
@@ -632,8 +686,8 @@ int sim_get_params(sim_handle* h, float* theta, void* stream) {
   int rc = sticky_error();
   if (rc) return rc;
   if (h->fp64) {
-    HIP_TRY(precise_get(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta,
-                        (hipStream_t)stream));
+    HIP_TRY(precise_get(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta, nullptr,
+                        nullptr, (hipStream_t)stream));
     return SIM_OK;
   }
   HIP_TRY(hipMemcpyAsync(theta, h->b.theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
@@ -648,8 +702,8 @@ int sim_set_params(sim_handle* h, const float* theta, void* stream) {
   if (rc) return rc;
   h->tape_T = 0;
   if (h->fp64) {
-    HIP_TRY(precise_set(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta,
-                        (hipStream_t)stream));
+    HIP_TRY(precise_set(h->pb, h->N, nullptr, nullptr, nullptr, nullptr, theta, nullptr,
+                        nullptr, (hipStream_t)stream));
     return SIM_OK;
   }
   HIP_TRY(hipMemcpyAsync(h->b.theta, theta, (size_t)h->N * NP * 4, hipMemcpyDeviceToDevice,
@@ -699,14 +753,16 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   // reverse order: variant first, then the buffers once the stream is idle).
   struct Snapshot {
     hipStream_t st;
-    float *state = nullptr, *hist = nullptr;
-    int32_t *tep = nullptr, *ep = nullptr;
+    float *state = nullptr, *hist = nullptr, *ret = nullptr;
+    int32_t *tep = nullptr, *ep = nullptr, *len = nullptr;
     ~Snapshot() {
       (void)hipStreamSynchronize(st);
       (void)hipFree(state);
       (void)hipFree(hist);
+      (void)hipFree(ret);
       (void)hipFree(tep);
       (void)hipFree(ep);
+      (void)hipFree(len);
     }
   } snap{st};
   struct VariantRestore {
@@ -723,7 +779,10 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
   HIP_TRY(hipMalloc(&snap.hist, N * NH * NA * 4));
   HIP_TRY(hipMalloc(&snap.tep, N * 4));
   HIP_TRY(hipMalloc(&snap.ep, N * 4));
-  HIP_TRY(launch_get_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
+  HIP_TRY(hipMalloc(&snap.ret, N * 2 * 4));
+  HIP_TRY(hipMalloc(&snap.len, N * 4));
+  HIP_TRY(launch_get_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, snap.ret,
+                           snap.len, st));
   struct Cand { int v, spl; };
   std::vector<Cand> cands = {{SIM_V_FUSED_MFMA4, 0}, {SIM_V_FUSED_MFMA, 0},
                              {SIM_V_FUSED_SPLIT, 0}, {SIM_V_FUSED_MFMA4, 100},
@@ -741,7 +800,8 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
     drop_graph(h);
     float acc = 0;
     for (int rep = 0; rep < 3; ++rep) {
-      HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
+      HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, snap.ret,
+                               snap.len, st));
       rc = sim_rollout(h, actor, T, nullptr, nullptr, nullptr, 0, stream);
       if (rc) return rc;
       HIP_TRY(hipEventSynchronize(h->ev1));
@@ -755,7 +815,8 @@ int sim_autotune(sim_handle* h, const float* actor, int32_t T, void* stream, int
       bestc = cd;
     }
   }
-  HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, st));
+  HIP_TRY(launch_set_state(h->b, h->N, snap.state, snap.hist, snap.tep, snap.ep, snap.ret,
+                               snap.len, st));
   h->tuned_variant = bestc.v;
   h->tuned_spl = bestc.spl;
   if (variant_out) *variant_out = bestc.v;

@@ -36,6 +36,35 @@ struct SimBufs {
   int32_t* t_ep;   // [N] steps in the current episode
   int32_t* ep;     // [N] episode index
   float* theta;    // [8][N] m, Jxx, Jyy, Jzz, c0, c1, c2, Tm
+  float* ret;      // [2][N] return of the current episode so far; of the last finished one
+  int32_t* last_len;  // [N] steps of the last finished episode (0 until one finishes)
+};
+
+// Episode accumulators of one env (Sec. V: episode return and length are
+// the training measures).  An episode closes when the env is reset inside
+// the step: its return and length become the "last" values and the running
+// return restarts at zero.  Without in-step resets the running return keeps
+// summing.
+struct EpAcc {
+  float cur, last;
+  int len;
+  __device__ inline void load(const SimBufs& b, int N, int e) {
+    cur = b.ret[e];
+    last = b.ret[(size_t)N + e];
+    len = b.last_len[e];
+  }
+  // after the step's reward r; t_ep = steps of the episode including this one
+  __device__ inline void add(float r, bool rst, int t_ep) {
+    cur += r;
+    last = rst ? cur : last;
+    len = rst ? t_ep : len;
+    cur = rst ? 0.0f : cur;
+  }
+  __device__ inline void store(const SimBufs& b, int N, uint32_t e) const {
+    b.ret[e] = cur;
+    b.ret[(size_t)N + e] = last;
+    b.last_len[e] = len;
+  }
 };
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,8 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = b.state[(size_t)i * N + e];
   int t_ep = b.t_ep[e], ep = b.ep[e];
+  EpAcc acc;
+  acc.load(b, N, e);
   if (DIST) {
     float d[6];
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
@@ -69,6 +71,7 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
     const float r = reward(c, x, a);
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
+    acc.add(r, d && (c.flags & F_AUTORESET), t_ep);
     if (d && (c.flags & F_AUTORESET)) {
       ++ep;
       t_ep = 0;
@@ -111,6 +114,7 @@ k_dyn_rollout(DevCfg c, SimBufs b, const float* __restrict__ act, int a_tstride,
   b.head[e] = head1;
   b.t_ep[e] = t_ep;
   b.ep[e] = ep;
+  acc.store(b, N, (uint32_t)e);
 }
 
 static inline unsigned nblk(int n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -14,14 +14,25 @@ struct PlainBufs {
 };
 
 hipError_t launch_init(const DevCfg& c, const SimBufs& b, int params, hipStream_t st);
+// Snapshots; ret [2][N] = {running return, last finished return}, last_len
+// [N]; any pointer may be NULL.
 hipError_t launch_get_state(const SimBufs& b, int N, float* state, float* hist, int32_t* t_ep,
-                            int32_t* ep, hipStream_t st);
+                            int32_t* ep, float* ret, int32_t* last_len, hipStream_t st);
 hipError_t launch_set_state(const SimBufs& b, int N, const float* state, const float* hist,
-                            const int32_t* t_ep, const int32_t* ep, hipStream_t st);
+                            const int32_t* t_ep, const int32_t* ep, const float* ret,
+                            const int32_t* last_len, hipStream_t st);
 hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs& p,
                              const float* W, const float* ext_act, float* reward, uint8_t* done,
                              float* state_out, hipStream_t st);
 hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st);
+// Resets the envs with mask[e] != 0 to their next episode (accumulators
+// closed as by an in-step reset).
+hipError_t launch_reset_envs(const DevCfg& c, const SimBufs& b, const uint8_t* mask,
+                             hipStream_t st);
+// out[i] = reward of post-step state s[:, i] ([17][M]) and action a[:, i]
+// ([4][M]) under the reward constants of c.
+hipError_t launch_reward_batch(const DevCfg& c, const float* s, const float* a, int M, float* out,
+                               hipStream_t st);
 // Observations of the current state: actor observation [146][N] (with the
 // noise of the coming step when enabled) and critic observation [28][N];
 // either may be NULL.

@@ -35,13 +35,16 @@ __global__ void k_init(DevCfg c, SimBufs b, int params) {
   b.head[e] = 0;
   b.t_ep[e] = 0;
   b.ep[e] = 0;
+  b.ret[e] = 0.0f;
+  b.ret[(size_t)N + e] = 0.0f;
+  b.last_len[e] = 0;
 }
 
 // Snapshot copies.  Each thread loads a batch of rows before storing any of
 // them: the source and destination may not be assumed disjoint, so a
 // load-store-load sequence would wait out one memory round trip per row.
 __global__ void k_get_state(SimBufs b, int N, float* state, float* hist, int32_t* t_ep,
-                            int32_t* ep) {
+                            int32_t* ep, float* ret, int32_t* last_len) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   if (state) {
@@ -70,10 +73,17 @@ __global__ void k_get_state(SimBufs b, int N, float* state, float* hist, int32_t
   }
   if (t_ep) t_ep[e] = b.t_ep[e];
   if (ep) ep[e] = b.ep[e];
+  if (ret) {
+    const float r0 = b.ret[e], r1 = b.ret[(size_t)N + e];
+    ret[e] = r0;
+    ret[(size_t)N + e] = r1;
+  }
+  if (last_len) last_len[e] = b.last_len[e];
 }
 
 __global__ void k_set_state(SimBufs b, int N, const float* state, const float* hist,
-                            const int32_t* t_ep, const int32_t* ep) {
+                            const int32_t* t_ep, const int32_t* ep, const float* ret,
+                            const int32_t* last_len) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   if (state) {
@@ -96,6 +106,12 @@ __global__ void k_set_state(SimBufs b, int N, const float* state, const float* h
   }
   if (t_ep) b.t_ep[e] = t_ep[e];
   if (ep) b.ep[e] = ep[e];
+  if (ret) {
+    const float r0 = ret[e], r1 = ret[(size_t)N + e];
+    b.ret[e] = r0;
+    b.ret[(size_t)N + e] = r1;
+  }
+  if (last_len) b.last_len[e] = last_len[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -189,6 +205,10 @@ __global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
   h = (h + 1) & (NH - 1);
   int t_ep = b.t_ep[e] + 1;
   const uint32_t d = episode_end(c, x, t_ep);
+  EpAcc acc;
+  acc.load(b, N, e);
+  acc.add(r, d && (c.flags & F_AUTORESET), t_ep);
+  acc.store(b, N, (uint32_t)e);
   if (d && (c.flags & F_AUTORESET)) {
     const int ep = b.ep[e] + 1;
     b.ep[e] = ep;
@@ -251,6 +271,48 @@ __global__ void __launch_bounds__(256) k_observe(DevCfg c, SimBufs b, float* __r
   }
 }
 
+// Ends the episodes of the envs with mask[e] != 0 and starts their next ones,
+// as an in-step reset does: episode + 1, step 0, the start state of (env,
+// episode + 1), the history filled with the env's hover action, and the
+// episode accumulators closed (the running return and the step count become
+// the last finished episode's).
+__global__ void k_reset_envs(DevCfg c, SimBufs b, const uint8_t* __restrict__ mask) {
+  const int N = c.n_envs;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N || !mask[e]) return;
+  float th[NP], s[NS];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) th[i] = b.theta[(size_t)i * N + e];
+  const int ep = b.ep[e] + 1;
+  const float ah = reset_state(c, (uint32_t)e, (uint32_t)ep, th[0], th[4], th[5], th[6], s);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + e] = s[i];
+  for (int i = 0; i < NH * NA; ++i) b.ring[(size_t)i * N + e] = ah;
+  b.ret[(size_t)N + e] = b.ret[e];
+  b.ret[e] = 0.0f;
+  b.last_len[e] = b.t_ep[e];
+  b.head[e] = 0;
+  b.t_ep[e] = 0;
+  b.ep[e] = ep;
+}
+
+// Rewards of given transitions under the configured reward constants: r(s',
+// a) of the reward equation (Sec. IV) for M post-step states s [17][M] and
+// actions a [4][M] (e.g. a replay buffer re-scored after the constants
+// changed).
+__global__ void __launch_bounds__(256) k_reward_batch(DevCfg c, const float* __restrict__ s,
+                                                      const float* __restrict__ a, int M,
+                                                      float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  float x[NS], u[NA];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) x[k] = s[(size_t)k * M + i];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) u[k] = a[(size_t)k * M + i];
+  out[i] = reward(c, x, u);
+}
+
 // Copies the state to a [17][N] slice (start state of a recorded rollout).
 __global__ void k_copy_state(SimBufs b, int N, float* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,16 +334,17 @@ hipError_t launch_init(const DevCfg& c, const SimBufs& b, int params, hipStream_
 }
 
 hipError_t launch_get_state(const SimBufs& b, int N, float* state, float* hist, int32_t* t_ep,
-                            int32_t* ep, hipStream_t st) {
+                            int32_t* ep, float* ret, int32_t* last_len, hipStream_t st) {
   hipLaunchKernelGGL(k_get_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, state, hist, t_ep,
-                     ep);
+                     ep, ret, last_len);
   return hipGetLastError();
 }
 
 hipError_t launch_set_state(const SimBufs& b, int N, const float* state, const float* hist,
-                            const int32_t* t_ep, const int32_t* ep, hipStream_t st) {
+                            const int32_t* t_ep, const int32_t* ep, const float* ret,
+                            const int32_t* last_len, hipStream_t st) {
   hipLaunchKernelGGL(k_set_state, dim3(nblk(N, 256)), dim3(256), 0, st, b, N, state, hist, t_ep,
-                     ep);
+                     ep, ret, last_len);
   return hipGetLastError();
 }
 
@@ -310,6 +373,18 @@ hipError_t launch_observe(const DevCfg& c, const SimBufs& b, float* actor_obs, f
                           hipStream_t st) {
   hipLaunchKernelGGL(k_observe, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, actor_obs,
                      critic_obs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_envs(const DevCfg& c, const SimBufs& b, const uint8_t* mask,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_envs, dim3(nblk(c.n_envs, 256)), dim3(256), 0, st, c, b, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_reward_batch(const DevCfg& c, const float* s, const float* a, int M, float* out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_reward_batch, dim3(nblk(M, 256)), dim3(256), 0, st, c, s, a, M, out);
   return hipGetLastError();
 }
 

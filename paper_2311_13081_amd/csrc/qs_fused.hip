@@ -14,8 +14,8 @@ namespace qs {
 // ---------------------------------------------------------------------------
 
 // T steps of the whole step (observation, actor, action map, RK4, reward,
-// history push, termination, truncation, reset) with state and history kept
-// in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
+// history push, termination, truncation, reset, episode accumulators) with
+// state and history kept in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
 // the actor when non-NULL.  Inactive lanes of the last wave shadow the wave's
 // first env (read only) so every MFMA operand is finite.  EXTRAS (the
 // training extras are on): the episode disturbance enters the dynamics and
@@ -59,6 +59,8 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
   }
   int t_ep = b.t_ep[e], ep = b.ep[e];
+  EpAcc acc;
+  acc.load(b, N, e);
   if (EXTRAS) {
     float d[6];
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
@@ -134,6 +136,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
     const bool rst = d && (c.flags & F_AUTORESET);
+    acc.add(r, rst, t_ep);
     // history push and the reset fill in one pass: one select per slot
 #pragma unroll
     for (int i = 0; i < (NH - 1) * NA; ++i) H[i] = rst ? ah : H[i + NA];
@@ -180,6 +183,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   b.head[ef] = head1;
   b.t_ep[ef] = t_ep;
   b.ep[ef] = ep;
+  acc.store(b, N, ef);
 }
 
 static inline unsigned nblk(int n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -22,6 +22,8 @@ struct PreciseBufs {
   int32_t* t_ep;   // [N]
   int32_t* ep;     // [N]
   double* theta;   // [8][N]
+  double* ret;     // [2][N] return of the current episode so far; of the last finished one
+  int32_t* last_len;  // [N] steps of the last finished episode
 };
 
 constexpr int PRECISE_LDS_BYTES = 13828 * 8;
@@ -31,10 +33,12 @@ hipError_t precise_init(const PreciseCfg& p, const PreciseBufs& b, int params, h
 hipError_t precise_run(const PreciseCfg& p, const PreciseBufs& b, const float* W,
                        const float* ext, int T, int t_base, float* rewards, uint8_t* dones,
                        float* states, hipStream_t st);
+// Float32 snapshots; ret [2][N] and last_len [N] are the episode
+// accumulators.  Any pointer may be NULL.
 hipError_t precise_get(const PreciseBufs& b, int N, float* state, float* hist, int32_t* t_ep,
-                       int32_t* ep, float* theta, hipStream_t st);
+                       int32_t* ep, float* theta, float* ret, int32_t* last_len, hipStream_t st);
 hipError_t precise_set(const PreciseBufs& b, int N, const float* state, const float* hist,
                        const int32_t* t_ep, const int32_t* ep, const float* theta,
-                       hipStream_t st);
+                       const float* ret, const int32_t* last_len, hipStream_t st);
 
 }  // namespace qs

@@ -129,6 +129,9 @@ __global__ void k_precise_init(PreciseCfg p, PreciseBufs b, int params) {
   b.head[e] = 0;
   b.t_ep[e] = 0;
   b.ep[e] = 0;
+  b.ret[e] = 0.0;
+  b.ret[(size_t)N + e] = 0.0;
+  b.last_len[e] = 0;
 }
 
 // T steps; outputs indexed by t_base + t, states rounded to float.
@@ -176,6 +179,8 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
   B.c2 = th[6];
   B.inv_Tm = 1.0 / th[7];
   int head = b.head[e], t_ep = b.t_ep[e], ep = b.ep[e];
+  double ret_cur = b.ret[e], ret_last = b.ret[(size_t)N + e];
+  int len_last = b.last_len[e];
   {
     double d[6];
     disturbance64(p, (uint32_t)e, (uint32_t)ep, d);
@@ -279,7 +284,11 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
     }
     const uint32_t trunc = (!term && p.max_steps > 0 && t_ep >= p.max_steps) ? 2u : 0u;
     const uint32_t d = term | trunc;
+    ret_cur += r;
     if (d && (p.flags & F_AUTORESET)) {
+      ret_last = ret_cur;
+      len_last = t_ep;
+      ret_cur = 0.0;
       ++ep;
       t_ep = 0;
       const double ah = reset64(p, th, (uint32_t)e, (uint32_t)ep, x);
@@ -298,6 +307,9 @@ k_precise(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, const float*
   b.head[e] = head;
   b.t_ep[e] = t_ep;
   b.ep[e] = ep;
+  b.ret[e] = ret_cur;
+  b.ret[(size_t)N + e] = ret_last;
+  b.last_len[e] = len_last;
 }
 
 // ---------------------------------------------------------------------------
@@ -472,6 +484,8 @@ k_precise4(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, int T, int 
   B.c2 = th[6];
   B.inv_Tm = 1.0 / th[7];
   int head = b.head[e], t_ep = b.t_ep[e], ep = b.ep[e];
+  double ret_cur = b.ret[e], ret_last = b.ret[(size_t)N + e];
+  int len_last = b.last_len[e];
   {
     double d[6];
     disturbance64(p, (uint32_t)e, (uint32_t)ep, d);
@@ -550,7 +564,11 @@ k_precise4(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, int T, int 
     }
     const uint32_t trunc = (!term && p.max_steps > 0 && t_ep >= p.max_steps) ? 2u : 0u;
     const uint32_t d = term | trunc;
+    ret_cur += r;
     if (d && (p.flags & F_AUTORESET)) {
+      ret_last = ret_cur;
+      len_last = t_ep;
+      ret_cur = 0.0;
       ++ep;
       t_ep = 0;
       const double ah = reset64(p, th, (uint32_t)e, (uint32_t)ep, x);
@@ -576,12 +594,15 @@ k_precise4(PreciseCfg p, PreciseBufs b, const float* __restrict__ W, int T, int 
     b.head[e] = head;
     b.t_ep[e] = t_ep;
     b.ep[e] = ep;
+    b.ret[e] = ret_cur;
+    b.ret[(size_t)N + e] = ret_last;
+    b.last_len[e] = len_last;
   }
 }
 
 // Float32 snapshots of the double state (history in logical order).
 __global__ void k_precise_get(PreciseBufs b, int N, float* state, float* hist, int32_t* t_ep,
-                              int32_t* ep, float* theta) {
+                              int32_t* ep, float* theta, float* ret, int32_t* last_len) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   if (state)
@@ -597,10 +618,16 @@ __global__ void k_precise_get(PreciseBufs b, int N, float* state, float* hist, i
   if (ep) ep[e] = b.ep[e];
   if (theta)
     for (int i = 0; i < NP; ++i) theta[(size_t)i * N + e] = (float)b.theta[(size_t)i * N + e];
+  if (ret) {
+    ret[e] = (float)b.ret[e];
+    ret[(size_t)N + e] = (float)b.ret[(size_t)N + e];
+  }
+  if (last_len) last_len[e] = b.last_len[e];
 }
 
 __global__ void k_precise_set(PreciseBufs b, int N, const float* state, const float* hist,
-                              const int32_t* t_ep, const int32_t* ep, const float* theta) {
+                              const int32_t* t_ep, const int32_t* ep, const float* theta,
+                              const float* ret, const int32_t* last_len) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   if (state)
@@ -613,6 +640,11 @@ __global__ void k_precise_set(PreciseBufs b, int N, const float* state, const fl
   if (ep) b.ep[e] = ep[e];
   if (theta)
     for (int i = 0; i < NP; ++i) b.theta[(size_t)i * N + e] = (double)theta[(size_t)i * N + e];
+  if (ret) {
+    b.ret[e] = (double)ret[e];
+    b.ret[(size_t)N + e] = (double)ret[(size_t)N + e];
+  }
+  if (last_len) b.last_len[e] = last_len[e];
 }
 
 static inline unsigned pb(int n) { return (unsigned)((n + 255) / 256); }
@@ -646,17 +678,17 @@ hipError_t precise_run(const PreciseCfg& p, const PreciseBufs& b, const float* W
 }
 
 hipError_t precise_get(const PreciseBufs& b, int N, float* state, float* hist, int32_t* t_ep,
-                       int32_t* ep, float* theta, hipStream_t st) {
+                       int32_t* ep, float* theta, float* ret, int32_t* last_len, hipStream_t st) {
   hipLaunchKernelGGL(k_precise_get, dim3(pb(N)), dim3(256), 0, st, b, N, state, hist, t_ep, ep,
-                     theta);
+                     theta, ret, last_len);
   return hipGetLastError();
 }
 
 hipError_t precise_set(const PreciseBufs& b, int N, const float* state, const float* hist,
                        const int32_t* t_ep, const int32_t* ep, const float* theta,
-                       hipStream_t st) {
+                       const float* ret, const int32_t* last_len, hipStream_t st) {
   hipLaunchKernelGGL(k_precise_set, dim3(pb(N)), dim3(256), 0, st, b, N, state, hist, t_ep, ep,
-                     theta);
+                     theta, ret, last_len);
   return hipGetLastError();
 }
 

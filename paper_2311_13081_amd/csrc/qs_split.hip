@@ -133,6 +133,12 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     t_ep = b.t_ep[e];
     ep = b.ep[e];
   }
+  // episode accumulators: the recompute from a checkpoint leaves them alone
+  EpAcc acc;
+  if (REC)
+    acc.cur = acc.last = 0.0f, acc.len = 0;
+  else
+    acc.load(b, N, e);
   bool was_reset = false;
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah = rpm_to_action(c, wh);
@@ -206,6 +212,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     ++t_ep;
     const uint32_t d = episode_end(c, x, t_ep);
     const bool rst = d && (c.flags & F_AUTORESET);
+    acc.add(r, rst, t_ep);
     // history push and the reset fill in one pass: one select per slot
 #pragma unroll
     for (int s = 5; s < Q_C - 1; ++s) F[s] = rst ? ah : F[s + 1];
@@ -251,6 +258,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     b.head[ef] = head1;
     b.t_ep[ef] = t_ep;
     b.ep[ef] = ep;
+    acc.store(b, N, ef);
   }
 }
 

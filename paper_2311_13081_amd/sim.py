@@ -175,26 +175,67 @@ class QuadSim:
         return ga, gp
 
     def get_state(self):
+        """Snapshot: state [17][N], hist [32][4][N], t_ep [N], episode [N],
+        returns [2][N] (current episode so far, last finished episode) and
+        last_len [N] (steps of the last finished episode)."""
         s = self._f32(17, self.N)
         hist = self._f32(32, 4, self.N)
         t = torch.empty(self.N, dtype=torch.int32, device=self.device)
         e = torch.empty(self.N, dtype=torch.int32, device=self.device)
-        check(self.L.sim_get_state(self.h, _ptr(s), _ptr(hist), _ptr(t), _ptr(e), _stream()),
-              "sim_get_state")
-        return dict(state=s, hist=hist, t_ep=t, episode=e)
+        ret = self._f32(2, self.N)
+        ln = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        check(self.L.sim_get_state(self.h, _ptr(s), _ptr(hist), _ptr(t), _ptr(e), _ptr(ret),
+                                   _ptr(ln), _stream()), "sim_get_state")
+        return dict(state=s, hist=hist, t_ep=t, episode=e, returns=ret, last_len=ln)
 
-    def set_state(self, state=None, hist=None, t_ep=None, episode=None):
+    def set_state(self, state=None, hist=None, t_ep=None, episode=None, returns=None,
+                  last_len=None):
         def dev(x, dt):
             return None if x is None else torch.as_tensor(x, dtype=dt).to(self.device).contiguous()
         s, h = dev(state, torch.float32), dev(hist, torch.float32)
         t, e = dev(t_ep, torch.int32), dev(episode, torch.int32)
+        r, ln = dev(returns, torch.float32), dev(last_len, torch.int32)
         self._need(s, (17, self.N), torch.float32, "state")
         self._need(h, (32, 4, self.N), torch.float32, "hist")
         self._need(t, (self.N,), torch.int32, "t_ep")
         self._need(e, (self.N,), torch.int32, "episode")
-        check(self.L.sim_set_state(self.h, _ptr(s), _ptr(h), _ptr(t), _ptr(e), _stream()),
-              "sim_set_state")
+        self._need(r, (2, self.N), torch.float32, "returns")
+        self._need(ln, (self.N,), torch.int32, "last_len")
+        check(self.L.sim_set_state(self.h, _ptr(s), _ptr(h), _ptr(t), _ptr(e), _ptr(r), _ptr(ln),
+                                   _stream()), "sim_set_state")
         self.tape_T = 0
+
+    REWARD_KEYS = ("C_rp", "C_rq", "C_rv", "C_rw", "C_ra", "C_rab", "C_rs")
+
+    def set_reward(self, **constants):
+        """Replaces reward constants (any of REWARD_KEYS) for the steps that
+        follow, without touching the envs."""
+        unknown = set(constants) - set(self.REWARD_KEYS)
+        if unknown:
+            raise ValueError(f"unknown reward constants {sorted(unknown)}")
+        self.cfg.update({k: float(v) for k, v in constants.items()})
+        C = (ctypes.c_double * 7)(*[float(self.cfg[k]) for k in self.REWARD_KEYS])
+        check(self.L.sim_set_reward(self.h, C), "sim_set_reward")
+
+    def reset_envs(self, mask: torch.Tensor):
+        """Starts the next episode of every env with mask != 0 (uint8 or bool
+        [N]), as an in-step reset would."""
+        m = mask.to(device=self.device, dtype=torch.uint8).contiguous()
+        self._need(m, (self.N,), torch.uint8, "mask")
+        check(self.L.sim_reset_envs(self.h, _ptr(m), _stream()), "sim_reset_envs")
+        self.tape_T = 0
+
+    def reward(self, states: torch.Tensor, actions: torch.Tensor, out=None):
+        """Rewards r(s', a) of M transitions, states [17][M] and actions
+        [4][M], under the current reward constants."""
+        M = int(states.shape[-1]) if states.dim() == 2 else -1
+        self._need(states, (17, M), torch.float32, "states")
+        self._need(actions, (4, M), torch.float32, "actions")
+        r = self._f32(M) if out is None else out
+        self._need(r, (M,), torch.float32, "out")
+        check(self.L.sim_reward(self.h, _ptr(states), _ptr(actions), M, _ptr(r), _stream()),
+              "sim_reward")
+        return r
 
     def get_params(self):
         th = self._f32(8, self.N)

@@ -430,11 +430,20 @@ def test_fwd65536_dr_full_size(pkg, orc):
     one = oracle_batch_from_gpu_inputs(orc, cfg, s32, h32, ob.t_ep, ob.ep, th[:, ids], ids=ids)
     o1 = one.rollout(W, 1)
     d1 = np_(d1)[ids]
+    # the oracle's post-step state before any reset: a done flag may differ
+    # only where that state lies within 1e-5 of a box threshold
+    nr = oracle_batch_from_gpu_inputs(orc, dict(cfg, flags=wl.F_RENORM_Q), s32, h32, ob.t_ep,
+                                      ob.ep, th[:, ids], ids=ids)
+    nr.rollout(W, 1)
+    tie = box_margin(nr.s, cfg["pos_limit"], cfg["vel_limit"]) < 1e-5
     ok = d1 == o1["dones"][0]
-    assert ok.mean() > 0.9
+    print(f"fwd65536_dr sampled step: {int(ok.sum())} of {len(ids)} done flags equal, "
+          f"{int((~ok & tie).sum())} threshold ties")
+    assert np.all(ok | tie)
     sg = np_(sim.get_state()["state"])[:, ids]
     assert max_state_err(sg[:, ok], one.s[ok]) < STEP_TOL
-    assert reward_err(np_(r1)[ids][ok], o1["rewards"][0][ok]) < STEP_TOL
+    # the reward belongs to the transition, before any reset: every env
+    assert reward_err(np_(r1)[ids], o1["rewards"][0]) < STEP_TOL
     sim.close()
 
 
