@@ -213,6 +213,22 @@ int sim_rollout_actions(sim_handle* h, const float* actions, int32_t actions_per
 int sim_backward(sim_handle* h, const float* actor, const float* d_rewards,
                  const float* d_states, float* grad_actor, float* grad_params, void* stream);
 
+/* sim_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors as sim_backward, but every
+ * intermediate of the backward (one segment's record and layer cotangents,
+ * the adjoint carry, parameter gradients, weight-gradient partials) lives in
+ * a static device array of the library, 32 MiB on each device, held until
+ * the process ends; it calls no allocator.  The kernels run in order on
+ * `stream` and recompute every segment.  SIM_E_INVAL when the handle's
+ * shape needs more than 32 MiB (about 28 KB per env at ckpt_every 16: up to
+ * 1024 envs there, 3584 at ckpt_every 4).
+ * All calls on one device share the array: calls that overlap in time on
+ * one device (other streams, other threads) race and must not be issued. */
+int sim_backward_noalloc(sim_handle* h, const float* actor, const float* d_rewards,
+                         const float* d_states, float* grad_actor, float* grad_params,
+                         void* stream);
+
 /* Snapshot of the per-env state: state dev [17][N], hist dev [32][4][N]
  * (oldest first), t_ep dev [N], episode dev [N], and the episode
  * accumulators (Sec. V, Training: episode return and length are the measures

@@ -27,6 +27,7 @@ EXPORTS = (
     "sim_get_state", "sim_set_state", "sim_get_params", "sim_set_params", "sim_set_variant",
     "sim_get_variant", "sim_autotune", "sim_last_rollout_timing", "sim_n_envs", "sim_last_error",
     "sim_rollout_actions", "sim_observe", "sim_set_reward", "sim_reset_envs", "sim_reward",
+    "sim_backward_noalloc",
 )
 
 
@@ -92,6 +93,7 @@ def load(path: str | None = None):
         "sim_step": ([H, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_rollout": ([H, vp, i32, vp, vp, vp, i32, vp], ctypes.c_int),
         "sim_backward": ([H, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "sim_backward_noalloc": ([H, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_rollout_actions": ([H, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "sim_observe": ([H, vp, vp, vp], ctypes.c_int),
         "sim_get_state": ([H, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,31 @@ struct GraphKey {
   }
 };
 
+}  // namespace
+
+// Scratch of sim_backward_noalloc: a device array that every GPU the library
+// runs on holds until the process ends.  Host code must not use its name as
+// an address (it is a host-side stand-in); the device address of each GPU's
+// copy is looked up once per device at sim_create and kept in g_scratch.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = (size_t)8 << 20;  // 32 MiB
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the device is current).
+int scratch_lookup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(SIM_E_UNSUPPORTED, "device %d", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return SIM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(SIM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[device] = static_cast<float*>(ptr);
+  return SIM_OK;
+}
 }  // namespace
 
 static_assert(SIM_F_ACTOR_BF16 == F_ACTOR_BF16 && SIM_F_DISTURB == F_DISTURB &&
@@ -309,6 +335,10 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(SIM_E_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+  // once per device, with the device current: the address of its copy of
+  // the scratch array of sim_backward_noalloc
+  rc = scratch_lookup(device);
+  if (rc) return rc;
 
   sim_handle* h = new sim_handle();
   h->cfg = *cfg;
@@ -600,6 +630,28 @@ int sim_backward(sim_handle* h, const float* actor, const float* d_rewards, cons
   // with more segments than buffers, the first buffer was reused
   const int J = (h->tape_T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
   if (J > BWD_NBUF) h->last_seg_recorded = false;
+  return SIM_OK;
+}
+
+int sim_backward_noalloc(sim_handle* h, const float* actor, const float* d_rewards,
+                         const float* d_states, float* grad_actor, float* grad_params,
+                         void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (!actor) return fail(SIM_E_INVAL, "actor is NULL");
+  if (h->tape_T <= 0) return fail(SIM_E_STATE, "no taped rollout to differentiate");
+  const size_t need = bwd_scratch_floats(h->bw);
+  if (need > NOALLOC_SCRATCH_FLOATS)
+    return fail(SIM_E_INVAL,
+                "backward of %d envs with checkpoints every %d steps needs %zu bytes of scratch, "
+                "more than the %zu bytes of the static scratch array",
+                h->N, h->cfg.ckpt_every, need * 4, NOALLOC_SCRATCH_FLOATS * 4);
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  float* sp = (h->device >= 0 && h->device < MAX_DEVICES) ? g_scratch[h->device] : nullptr;
+  if (!sp) return fail(SIM_E_STATE, "scratch array of device %d not set up", h->device);
+  HIP_TRY(run_backward_in(h->dc, h->b, h->bw, sp, actor, h->tape, h->cfg.ckpt_every, h->tape_T,
+                          d_rewards, d_states, grad_actor, grad_params, (hipStream_t)stream));
   return SIM_OK;
 }
 

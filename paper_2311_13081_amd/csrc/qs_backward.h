@@ -33,4 +33,15 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
                         const float* d_states, float* grad_actor, float* grad_params,
                         bool last_recorded, hipStream_t st);
 
+// The same backward with every buffer of bw's shape carved out of `scratch`
+// (bwd_scratch_floats(bw) floats, device memory the caller owns) instead of
+// the handle's allocations: one segment buffer, every kernel in order on st,
+// the last segment recomputed.  The handle's tape is read as usual.  Results
+// equal run_backward's bit for bit.
+size_t bwd_scratch_floats(const BwdBufs& bw);
+hipError_t run_backward_in(const DevCfg& c, const SimBufs& b, const BwdBufs& bw, float* scratch,
+                           const float* W, const float* tape, int K, int T,
+                           const float* d_rewards, const float* d_states, float* grad_actor,
+                           float* grad_params, hipStream_t st);
+
 }  // namespace qs

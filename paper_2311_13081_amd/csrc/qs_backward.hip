@@ -993,16 +993,19 @@ void bwd_free(BwdBufs& bw) {
 // workgroups than CUs); for large batches the sweep (one wave per SIMD, most
 // registers) fills the chip and everything stays on the caller's stream in
 // order.
-hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
-                        const float* tape, int K, int T, const float* d_rewards,
-                        const float* d_states, float* grad_actor, float* grad_params,
-                        bool last_recorded, hipStream_t st) {
+// nbuf: segment buffers to rotate (BWD_NBUF, or 1 for the serial order of
+// the scratch-array variant, which also keeps every kernel on st).
+static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const BwdBufs& bw, int nbuf,
+                                    const float* W, const float* tape, int K, int T,
+                                    const float* d_rewards, const float* d_states,
+                                    float* grad_actor, float* grad_params, bool last_recorded,
+                                    hipStream_t st) {
   const int N = c.n_envs;
   const size_t np = (size_t)bw.n_parts * DW_SLOT;
   hipLaunchKernelGGL(k_fill, dim3(nb((int)np, 256)), dim3(256), 0, st, bw.gpart, np, 0.0f);
   hipLaunchKernelGGL(k_bwd_init, dim3(nb(N, 256)), dim3(256), 0, st, N,
                      d_states ? d_states + (size_t)T * NS * N : nullptr, bw.lam, bw.gth);
-  const bool overlap = (int)nb(N, 64) < bw.n_cu;
+  const bool overlap = nbuf == BWD_NBUF && (int)nb(N, 64) < bw.n_cu;
   hipStream_t s_rec = overlap ? bw.s_rec : st, s_dw = overlap ? bw.s_dw : st;
   if (overlap) {
     BWD_TRY(hipEventRecord(bw.e_init, st));
@@ -1014,7 +1017,7 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
   for (int j = J - 1, idx = 0; j >= 0; --j, ++idx) {
     const int t0 = j * K;
     const int n = (T - t0) < K ? (T - t0) : K;
-    const int buf = idx % BWD_NBUF;
+    const int buf = idx % nbuf;
     // the last segment's record may come from the taped rollout itself
     // (written on the caller's stream, ahead of this call)
     if (!(idx == 0 && last_recorded)) {
@@ -1053,6 +1056,58 @@ hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const fl
     hipLaunchKernelGGL(k_copy, dim3(nb(NP * N, 256)), dim3(256), 0, st, bw.gth, grad_params,
                        (size_t)NP * N);
   return hipGetLastError();
+}
+
+hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
+                        const float* tape, int K, int T, const float* d_rewards,
+                        const float* d_states, float* grad_actor, float* grad_params,
+                        bool last_recorded, hipStream_t st) {
+  return backward_segments(c, b, bw, BWD_NBUF, W, tape, K, T, d_rewards, d_states, grad_actor,
+                           grad_params, last_recorded, st);
+}
+
+// Layout of the scratch array in floats, every part starting on a 256-byte
+// boundary: one segment record, its layer cotangents, the adjoint carry,
+// the parameter gradients, the weight-gradient partials, the actor-gradient
+// sink.
+static inline size_t up64(size_t f) { return (f + 63) & ~(size_t)63; }
+
+size_t bwd_scratch_floats(const BwdBufs& bw) {
+  const int N = bw.N, K = bw.K;
+  return up64(rec_floats(K, N)) + up64((size_t)K * DZ_F * rb_pad(N)) + up64((size_t)LAM_F * N) +
+         up64((size_t)NP * N) + up64((size_t)bw.n_parts * DW_SLOT) + up64((size_t)NW);
+}
+
+hipError_t run_backward_in(const DevCfg& c, const SimBufs& b, const BwdBufs& bw, float* scratch,
+                           const float* W, const float* tape, int K, int T,
+                           const float* d_rewards, const float* d_states, float* grad_actor,
+                           float* grad_params, hipStream_t st) {
+  const int N = c.n_envs;
+  BwdBufs sb = bw;  // shape, groups and device attributes of the handle's backward
+  for (int i = 0; i < BWD_NBUF; ++i) sb.seg[i] = sb.dz[i] = nullptr;
+  float* p = scratch;
+  const size_t f_rec = rec_floats(K, N), f_dz = (size_t)K * DZ_F * rb_pad(N);
+  sb.seg[0] = p;
+  p += up64(f_rec);
+  sb.dz[0] = p;
+  p += up64(f_dz);
+  sb.lam = p;
+  p += up64((size_t)LAM_F * N);
+  sb.gth = p;
+  p += up64((size_t)NP * N);
+  sb.gpart = p;
+  p += up64((size_t)bw.n_parts * DW_SLOT);
+  sb.gsum = p;
+  // the array keeps whatever the last call on this device left in it; the
+  // record and cotangent slots of envs >= N in the last 64-env block are
+  // never written here and must read as zero
+  // (k_fill: one float per thread; both sizes are below 2^31 by the
+  // scratch bound the caller checked)
+  hipLaunchKernelGGL(k_fill, dim3(nb((int)f_rec, 256)), dim3(256), 0, st, sb.seg[0], f_rec, 0.0f);
+  hipLaunchKernelGGL(k_fill, dim3(nb((int)f_dz, 256)), dim3(256), 0, st, sb.dz[0], f_dz, 0.0f);
+  BWD_TRY(hipGetLastError());
+  return backward_segments(c, b, sb, 1, W, tape, K, T, d_rewards, d_states, grad_actor,
+                           grad_params, false, st);
 }
 
 }  // namespace qs

@@ -157,10 +157,12 @@ class QuadSim:
         return out
 
     def backward(self, actor: torch.Tensor, d_rewards=None, d_states=None, want_actor=True,
-                 want_params=True):
+                 want_params=True, out=None, noalloc=False):
         """Gradients of the last taped rollout: (grad_actor [13828], grad_params
         [8][N]) for the loss sum d_rewards * rewards + sum d_states * states
-        (d_rewards None = all ones, d_states None = zeros)."""
+        (d_rewards None = all ones, d_states None = zeros).  out=(ga, gp)
+        reuses output tensors; noalloc=True runs sim_backward_noalloc (the
+        library's static scratch array instead of the handle's buffers)."""
         self._need(actor, (_lib.SIM_NACTOR,), torch.float32, "actor")
         T = self.tape_T
         if T > 0:
@@ -168,10 +170,17 @@ class QuadSim:
             self._need(d_states, (T + 1, 17, self.N), torch.float32, "d_states")
         # without a tape the library refuses the call (SIM_E_STATE) before it
         # reads any argument
-        ga = torch.empty(_lib.SIM_NACTOR, dtype=torch.float32, device=self.device) if want_actor else None
-        gp = self._f32(8, self.N) if want_params else None
-        check(self.L.sim_backward(self.h, _ptr(actor), _ptr(d_rewards), _ptr(d_states), _ptr(ga),
-                                  _ptr(gp), _stream()), "sim_backward")
+        if out is not None:
+            ga, gp = out
+            self._need(ga, (_lib.SIM_NACTOR,), torch.float32, "grad_actor")
+            self._need(gp, (8, self.N), torch.float32, "grad_params")
+        else:
+            ga = torch.empty(_lib.SIM_NACTOR, dtype=torch.float32,
+                             device=self.device) if want_actor else None
+            gp = self._f32(8, self.N) if want_params else None
+        fn = self.L.sim_backward_noalloc if noalloc else self.L.sim_backward
+        check(fn(self.h, _ptr(actor), _ptr(d_rewards), _ptr(d_states), _ptr(ga), _ptr(gp),
+                 _stream()), "sim_backward_noalloc" if noalloc else "sim_backward")
         return ga, gp
 
     def get_state(self):
