@@ -256,6 +256,21 @@ int sim_set_state(sim_handle* h, const float* state, const float* hist, const in
  * captured rollout graph. */
 int sim_set_reward(sim_handle* h, const double* C);
 
+/* Set point of the actor's observation (Sec. IV: the position controller is
+ * steered to any position or velocity by shifting the observed position and
+ * velocity, with clipping to keep the errors in the trained range; Sec. VI
+ * tracks a trajectory this way): target dev [6][N] = {p_sp (3), v_sp (3)}
+ * per env, copied into the handle (stream-ordered); from the next step on
+ * the actor observes clip(p - p_sp, +-pos_clip) and clip(v - v_sp,
+ * +-vel_clip) in place of p and v (before its observation noise).  The
+ * dynamics, reward, termination box and the critic observation keep the
+ * absolute state.  target == NULL removes the set point (the clips are then
+ * ignored).  Forward only: a taped rollout with a set point in force returns
+ * SIM_E_STATE; not available on SIM_F_FP64 handles.  Drops a captured
+ * rollout graph and the tape. */
+int sim_set_target(sim_handle* h, const float* target, double pos_clip, double vel_clip,
+                   void* stream);
+
 /* Ends the episodes of the envs with mask[e] != 0 (mask dev uint8 [N]) and
  * starts their next ones exactly as an in-step reset would (episode + 1,
  * step 0, the counter-RNG start state of (env, episode + 1), history filled

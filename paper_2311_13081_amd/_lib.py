@@ -27,7 +27,7 @@ EXPORTS = (
     "sim_get_state", "sim_set_state", "sim_get_params", "sim_set_params", "sim_set_variant",
     "sim_get_variant", "sim_autotune", "sim_last_rollout_timing", "sim_n_envs", "sim_last_error",
     "sim_rollout_actions", "sim_observe", "sim_set_reward", "sim_reset_envs", "sim_reward",
-    "sim_backward_noalloc",
+    "sim_backward_noalloc", "sim_set_target",
 )
 
 
@@ -100,6 +100,7 @@ def load(path: str | None = None):
         "sim_set_state": ([H, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sim_set_reward": ([H, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "sim_reset_envs": ([H, vp, vp], ctypes.c_int),
+        "sim_set_target": ([H, vp, ctypes.c_double, ctypes.c_double, vp], ctypes.c_int),
         "sim_reward": ([H, vp, vp, i32, vp, vp], ctypes.c_int),
         "sim_get_params": ([H, vp, vp], ctypes.c_int),
         "sim_set_params": ([H, vp, vp], ctypes.c_int),

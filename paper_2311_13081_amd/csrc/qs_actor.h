@@ -175,8 +175,16 @@ __device__ inline void layer3_one_lane(const float* lds, int w3, int b3off, cons
 //           Each lane group ends with a partial sum over its quarter of the
 //           neurons; two swap-and-add rounds across 32 and 16 lanes add the
 //           quarters and leave output o of env (lane) in every lane.
+//  REC: also store the layer pre-activations into the backward's blocked
+//  record: rz1 / rz2 point at the first z1 / z2 row of the wave's 64-env
+//  block in this step's record; register 4 bb + v (neuron 16 n + 4 lg + v of
+//  env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li, for the
+//  blocks bb whose bit is set in colmask (envs past the batch stay unwritten).
+template <bool REC = false>
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
-                                  const float H[NH * NA], float z3out[NA]) {
+                                  const float H[NH * NA], float z3out[NA],
+                                  float* __restrict__ rz1 = nullptr,
+                                  float* __restrict__ rz2 = nullptr, uint32_t colmask = 0) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const f16 zero16 = {};
@@ -202,6 +210,16 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       }
     }
   }
+  if (REC) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (colmask & (1u << bb))
+            rz1[(size_t)(16 * n + 4 * lg + v) * 64 + 16 * bb + li] = acc1[n][4 * bb + v];
+  }
 #pragma unroll
   for (int n = 0; n < 4; ++n)
 #pragma unroll
@@ -222,6 +240,17 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
           acc2[n2][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
               w[v], acc1[n][4 * bb + v], (n == 0 && v == 0) ? b2 : acc2[n2][bb], 0, 0, 0);
     }
+  if (REC) {
+    // register r of acc2[n2][bb]: neuron 16 n2 + 4 lg + r of env 16 bb + li
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (colmask & (1u << bb))
+            rz2[(size_t)(16 * n2 + 4 * lg + r) * 64 + 16 * bb + li] = acc2[n2][bb][r];
+  }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll

@@ -118,6 +118,9 @@ struct sim_handle {
   bool bf16 = false;          // SIM_F_ACTOR_BF16: quarter-lane kernel with bf16 actor
   PreciseCfg pc{};
   PreciseBufs pb{};
+  float* target_buf = nullptr;  // [6][N] set points of the actor's observation
+  bool target_on = false;
+  float pos_clip = 0.0f, vel_clip = 0.0f;
 };
 
 namespace {
@@ -250,6 +253,13 @@ PreciseCfg make_precise(const sim_config& c, uint64_t seed) {
   return p;
 }
 
+// The set point of the actor's observation travels in the device config.
+void apply_target(sim_handle* h) {
+  h->dc.target = h->target_on ? h->target_buf : nullptr;
+  h->dc.pos_clip = h->pos_clip;
+  h->dc.vel_clip = h->vel_clip;
+}
+
 // Error left by earlier asynchronous work on this device, if any.
 int sticky_error() {
   hipError_t e = hipPeekAtLastError();
@@ -304,6 +314,9 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
       else if (variant == SIM_V_FUSED_SPLIT)
         HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
                              rec_from, rec_n, st));
+      else if (tape && mfma)
+        HIP_TRY(launch_fused_taped(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr,
+                                   rec, rec_from, rec_n, st));
       else
         HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
@@ -392,6 +405,7 @@ int sim_create(const sim_config* cfg, int device, sim_handle** out) {
   rc = rc ? rc : alloc((void**)&h->p.h1, N * NHID * 4);
   rc = rc ? rc : alloc((void**)&h->p.h2, N * NHID * 4);
   rc = rc ? rc : alloc((void**)&h->p.act, N * NA * 4);
+  rc = rc ? rc : alloc((void**)&h->target_buf, N * 6 * 4);
   if (!rc && cfg->max_tape_horizon > 0) {
     h->tape_ckpts = (cfg->max_tape_horizon + cfg->ckpt_every - 1) / cfg->ckpt_every + 1;
     rc = alloc((void**)&h->tape, (size_t)h->tape_ckpts * CK_F * N * 4);
@@ -426,7 +440,7 @@ int sim_destroy(sim_handle* h) {
   drop_graph(h);
   void* ptrs[] = {h->b.state,  h->b.ring,  h->b.head,    h->b.t_ep,  h->b.ep,
                   h->b.theta,  h->b.ret,   h->b.last_len, h->p.obs,   h->p.h1,
-                  h->p.h2,     h->p.act,   h->tape,      h->pb.state, h->pb.ring,
+                  h->p.h2,     h->p.act,   h->tape,      h->pb.state, h->pb.ring, h->target_buf,
                   h->pb.head,  h->pb.t_ep, h->pb.ep,     h->pb.theta, h->pb.ret,
                   h->pb.last_len};
   for (void* p : ptrs)
@@ -446,6 +460,7 @@ int sim_reset(sim_handle* h, uint64_t seed, void* stream) {
   if (rc) return rc;
   h->cfg.seed = seed;
   h->dc = make_devcfg(h->cfg, seed);
+  apply_target(h);
   h->tape_T = 0;
   drop_graph(h);
   if (h->fp64) {
@@ -500,6 +515,8 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
       return fail(SIM_E_INVAL, "T = %d exceeds max_tape_horizon = %d", T, h->cfg.max_tape_horizon);
     if (h->cfg.flags & (SIM_F_TERMINATE | SIM_F_AUTORESET))
       return fail(SIM_E_STATE, "differentiable rollouts need TERMINATE and AUTORESET off");
+    if (h->target_on)
+      return fail(SIM_E_STATE, "differentiable rollouts do not take a set point (sim_set_target)");
   }
   DeviceGuard g(h->device);
   int rc = sticky_error();
@@ -517,7 +534,9 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   // segments with (the recompute must reproduce the forward trajectory bit
   // for bit): the split-actor kernel for small fp32 batches, else the
   // quarter-lane kernel.
-  const int v = record_tape ? (taped_on_split(h->dc) ? SIM_V_FUSED_SPLIT : SIM_V_FUSED_MFMA4)
+  const TapedKernel tk = taped_kernel(h->dc);
+  const int v = record_tape ? (tk == TAPED_SPLIT ? SIM_V_FUSED_SPLIT
+                               : tk == TAPED_LANE ? SIM_V_FUSED_MFMA : SIM_V_FUSED_MFMA4)
                             : effective_variant(h);
   const int spl = effective_spl(h);
   float* tape = record_tape ? h->tape : nullptr;
@@ -702,8 +721,32 @@ int sim_set_reward(sim_handle* h, const double* C) {
   h->cfg.C_rab = C[5];
   h->cfg.C_rs = C[6];
   h->dc = make_devcfg(h->cfg, h->cfg.seed);
+  apply_target(h);
   if (h->fp64) h->pc = make_precise(h->cfg, h->cfg.seed);
   // captured graphs hold the old constants in their kernel arguments
+  drop_graph(h);
+  return SIM_OK;
+}
+
+int sim_set_target(sim_handle* h, const float* target, double pos_clip, double vel_clip,
+                   void* stream) {
+  if (!h) return fail(SIM_E_INVAL, "handle is NULL");
+  if (h->fp64) return fail(SIM_E_UNSUPPORTED, "not available on SIM_F_FP64 handles");
+  if (target && !(pos_clip > 0 && vel_clip > 0 && std::isfinite(pos_clip) && std::isfinite(vel_clip)))
+    return fail(SIM_E_INVAL, "clip bounds must be finite and positive");
+  DeviceGuard g(h->device);
+  int rc = sticky_error();
+  if (rc) return rc;
+  if (target) {
+    HIP_TRY(hipMemcpyAsync(h->target_buf, target, (size_t)h->N * 6 * 4, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    h->pos_clip = (float)pos_clip;
+    h->vel_clip = (float)vel_clip;
+  }
+  h->target_on = target != nullptr;
+  apply_target(h);
+  h->tape_T = 0;
+  // captured graphs hold the old configuration in their kernel arguments
   drop_graph(h);
   return SIM_OK;
 }

@@ -25,6 +25,15 @@ struct BwdBufs {
 };
 
 hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H);
+// Reverse sweep with one env per lane (qs_reverse1.hip) for one segment of n
+// steps from step t0: record rec, checkpoint ck (its episode index keys the
+// disturbance), adjoint carry lam [145][N], parameter gradients gth [8][N],
+// layer cotangents out to dz.  prepare: once per device (LDS size).
+hipError_t reverse1_prepare();
+hipError_t launch_reverse1(const DevCfg& c, const float* theta, const float* W, const float* ck,
+                           const float* rec, int n, int t0, const float* d_rewards,
+                           const float* d_states, float* lam, float* gth, float* dz,
+                           hipStream_t st);
 void bwd_free(BwdBufs& bw);
 // last_recorded: bw.seg[0] already holds the record of the last segment
 // (written by the taped rollout), so its recompute is skipped.

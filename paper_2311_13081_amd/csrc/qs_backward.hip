@@ -20,11 +20,9 @@
 #include "qs_actor.h"
 #include "qs_backward.h"
 #include "qs_forward.h"
+#include "qs_reverse.h"
 
 namespace qs {
-
-constexpr int DZ_F = NHID + NHID + NA;  // dz1 | dz2 | dz3 per (step, env)
-constexpr int LAM_F = NS + NH * NA;     // state and history adjoints
 
 static inline unsigned nb(int n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -68,9 +66,6 @@ constexpr int R_W3 = 0, R_W2P = R_W3 + NA * NHID, R_W1P = R_W2P + NHID * NHID,
 __host__ __device__ constexpr int r_phi(int c, int k) {
   return c < 5 ? (4 * c + k < 18 ? 4 * c + k : -1) : c < 37 ? 18 + 4 * (c - 5) + k : -1;
 }
-
-// Weight as the forward used it: rounded to bf16 under the bf16-actor flag.
-__device__ inline float fwd_weight(float w, bool bf16) { return bf16 ? (float)(__bf16)w : w; }
 
 __device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bool bf16) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -125,111 +120,6 @@ __device__ inline void load_step(StepIn<ZT>& in, const float* __restrict__ rec,
     in.dS[i] = d_states ? d_states[((size_t)t * NS + i) * N + eo] : 0.0f;
 }
 
-// Reverse of one step's dynamics: recomputes the RK4 stages from the recorded
-// state x and action a, then steps back through the reward, the quaternion
-// renormalisation and the four stages.  In: ls (state adjoint after the
-// step), lh_new (adjoint of the newest history slot, this lane's component).
-// Out: gx (state adjoint before the step, without the observation's share),
-// ga (action adjoint, the history coupling included); gth accumulates the
-// parameter gradients.
-__device__ __forceinline__ void reverse_dynamics(const DevCfg& c, const Body<float>& B,
-                                                 const float th[NP], bool renorm, const float x[NS],
-                                                 const float a[NA], float dR, const float ls[NS],
-                                                 float lh_new, int j, float gx[NS], float ga[NA],
-                                                 float gth[NP]) {
-  const float h = c.dt;
-  float u[NA];
-#pragma unroll
-  for (int i = 0; i < NA; ++i) u[i] = action_to_rpm(c, a[i]);
-  float x2[NS], x3[NS], x4[NS], kd[NS], acc[NS];
-  deriv<float>(B, c.arm, c.km, c.g, x, u, kd);
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    acc[i] = kd[i];
-    x2[i] = x[i] + 0.5f * h * kd[i];
-  }
-  deriv<float>(B, c.arm, c.km, c.g, x2, u, kd);
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    acc[i] += 2.0f * kd[i];
-    x3[i] = x[i] + 0.5f * h * kd[i];
-  }
-  deriv<float>(B, c.arm, c.km, c.g, x3, u, kd);
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    acc[i] += 2.0f * kd[i];
-    x4[i] = x[i] + h * kd[i];
-  }
-  deriv<float>(B, c.arm, c.km, c.g, x4, u, kd);
-  float sn[NS];  // post-step state (renormalised)
-#pragma unroll
-  for (int i = 0; i < NS; ++i) sn[i] = x[i] + (h / 6.0f) * (acc[i] + kd[i]);
-  float rn = 1.0f;
-  if (renorm) {
-    // the forward's reciprocal square root (rk4_step)
-    rn = rsqrt_r(sn[3] * sn[3] + sn[4] * sn[4] + sn[5] * sn[5] + sn[6] * sn[6]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) sn[3 + i] *= rn;
-  }
-
-  // --- reward and history coupling -----------------------------------------
-  float g[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) g[i] = ls[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    g[i] += -2.0f * c.C_rp * sn[i] * dR;
-    g[7 + i] += -2.0f * c.C_rv * sn[7 + i] * dR;
-    g[10 + i] += -2.0f * c.C_rw * sn[10 + i] * dR;
-  }
-  g[3] += 2.0f * c.C_rq * sn[3] * dR;
-  // newest history slot: component i lives in quarter i of the same env
-#pragma unroll
-  for (int i = 0; i < NA; ++i) {
-    const float hn =
-        __int_as_float(__builtin_amdgcn_ds_bpermute((j + 16 * i) << 2, __float_as_int(lh_new)));
-    ga[i] = -2.0f * c.C_ra * (a[i] - c.C_rab) * dR + hn;
-  }
-
-  // --- renormalisation ------------------------------------------------------
-  if (renorm) {
-    const float d = sn[3] * g[3] + sn[4] * g[4] + sn[5] * g[5] + sn[6] * g[6];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) g[3 + i] = (g[3 + i] - sn[3 + i] * d) * rn;
-  }
-
-  // --- RK4 stages in reverse ----------------------------------------------
-  float gk[NS], gs[NS], gu[NA] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    gx[i] = g[i];
-    gk[i] = (h / 6.0f) * g[i];
-    gs[i] = 0.0f;
-  }
-  deriv_vjp(B, th, c.arm, c.km, x4, u, gk, gs, gu, gth);  // k4 = f(x4)
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    gx[i] += gs[i];
-    gk[i] = (h / 3.0f) * g[i] + h * gs[i];
-    gs[i] = 0.0f;
-  }
-  deriv_vjp(B, th, c.arm, c.km, x3, u, gk, gs, gu, gth);  // k3 = f(x3)
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    gx[i] += gs[i];
-    gk[i] = (h / 3.0f) * g[i] + 0.5f * h * gs[i];
-    gs[i] = 0.0f;
-  }
-  deriv_vjp(B, th, c.arm, c.km, x2, u, gk, gs, gu, gth);  // k2 = f(x2)
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    gx[i] += gs[i];
-    gk[i] = (h / 6.0f) * g[i] + 0.5f * h * gs[i];
-  }
-  deriv_vjp(B, th, c.arm, c.km, x, u, gk, gx, gu, gth);   // k1 = f(x)
-#pragma unroll
-  for (int i = 0; i < NA; ++i) ga[i] += gu[i] * c.rpm_half_range;
-}
 
 // The observation's share of the adjoints, from do (dob: tile p, register r
 // of quarter k = the cotangent of feature PHI(4p + r, k)): shifts the
@@ -273,6 +163,10 @@ constexpr int R_XCH = (4 + 4 + 10) * 64 * 4;
 // Batches up to this size run the split sweep (four times the waves; the
 // quarter-lane sweep leaves most SIMDs idle there).
 constexpr int REVERSE_SPLIT_MAX_ENVS = 4096;
+// Batches from this size run the one-env-per-lane sweep (qs_reverse1.hip):
+// one wave of 64 envs per SIMD and no repeated dynamics adjoint; below it,
+// its waves would leave SIMDs idle.
+constexpr int REVERSE_LANE_MIN_ENVS = 65536;
 
 // Reverse sweep of one segment.  SPLIT = false: 16 envs per wave in the
 // quarter-lane layout.  SPLIT = true: 16 envs per workgroup of 4 waves, each
@@ -338,7 +232,13 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
     float* dzt = dz + (size_t)tl * DZ_F * rb_pad(N);
 
     float gx[NS], ga[NA];
-    reverse_dynamics(c, B, th, renorm, cur.x, cur.a, cur.dR, ls, lH[NH - 1], j, gx, ga, gth);
+    // newest history slot: component i lives in quarter i of the same env
+    float hn[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      hn[i] = __int_as_float(
+          __builtin_amdgcn_ds_bpermute((j + 16 * i) << 2, __float_as_int(lH[NH - 1])));
+    reverse_dynamics(c, B, th, renorm, cur.x, cur.a, cur.dR, ls, hn, gx, ga, gth);
 
     // --- actor VJP on matrix cores --------------------------------------------
     float d3[NA];
@@ -953,8 +853,11 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, R_TOTAL * 4)) !=
       hipSuccess)
     return e;
-  return hipFuncSetAttribute((const void*)k_bwd_reverse<true>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (R_TOTAL + R_XCH) * 4);
+  if ((e = hipFuncSetAttribute((const void*)k_bwd_reverse<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (R_TOTAL + R_XCH) * 4)) !=
+      hipSuccess)
+    return e;
+  return reverse1_prepare();
 }
 
 void bwd_free(BwdBufs& bw) {
@@ -1028,7 +931,10 @@ static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const Bwd
         BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
       }
     }
-    if (N <= REVERSE_SPLIT_MAX_ENVS)
+    if (N >= REVERSE_LANE_MIN_ENVS)
+      BWD_TRY(launch_reverse1(c, b.theta, W, tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0,
+                              d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf], st));
+    else if (N <= REVERSE_SPLIT_MAX_ENVS)
       hipLaunchKernelGGL(k_bwd_reverse<true>, dim3(nb(N, 16)), dim3(256), (R_TOTAL + R_XCH) * 4,
                          st, c, b.theta, W, tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0,
                          d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf]);

@@ -26,6 +26,34 @@ struct DevCfg {
   uint32_t seed_lo, seed_hi, dr_seed_lo, dr_seed_hi;
   float dist_force, dist_torque;  // per-component bounds of the episode disturbance
   float noise[4];                 // observation noise std: p, R entries, v, w
+  // Set-point shift of the actor's observation ([6][N]: position and
+  // velocity set points per env; NULL = none): the actor sees p - p_sp and
+  // v - v_sp, each component clipped to +-pos_clip, +-vel_clip.
+  const float* target;
+  float pos_clip, vel_clip;
+};
+
+// Set point of env e (zeros without a target), loaded once per launch.
+struct SetPoint {
+  float p[3], v[3];
+  __device__ inline void load(const DevCfg& c, int N, int e) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      p[i] = c.target ? c.target[(size_t)i * N + e] : 0.0f;
+      v[i] = c.target ? c.target[(size_t)(3 + i) * N + e] : 0.0f;
+    }
+  }
+  // Shifts the observed position f[0..2] and velocity f[12..14] of the 18
+  // state features (Sec. IV: a position controller follows a moving set point
+  // through this offset; clipping keeps the errors within the trained range).
+  __device__ inline void apply(const DevCfg& c, float f[18]) const {
+    if (!c.target) return;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      f[i] = fminf(fmaxf(f[i] - p[i], -c.pos_clip), c.pos_clip);
+      f[12 + i] = fminf(fmaxf(f[12 + i] - v[i], -c.vel_clip), c.vel_clip);
+    }
+  }
 };
 
 // Device state of the batch, struct-of-arrays, N = n_envs.

@@ -101,16 +101,27 @@ hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T
                         int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
                         hipStream_t st);
 // The kernel of taped rollouts and of their backward recompute (the two must
-// agree bit for bit): the split-actor kernel below 16384 envs with the fp32
-// actor (the quarter-lane kernel leaves SIMDs idle there), else the
-// quarter-lane kernel.
+// agree bit for bit): with the fp32 actor the split-actor kernel below 16384
+// envs (the quarter-lane kernel leaves SIMDs idle there), the one-env-per-lane
+// kernel from 65536 envs (one wave per SIMD, no repeated dynamics), the
+// quarter-lane kernel between them and for the bf16 actor.
 constexpr int TAPE_SPLIT_MAX_ENVS = 16384;
-inline bool taped_on_split(const DevCfg& c) {
-  return c.n_envs < TAPE_SPLIT_MAX_ENVS && !(c.flags & F_ACTOR_BF16);
+constexpr int TAPE_LANE_MIN_ENVS = 65536;
+enum TapedKernel { TAPED_SPLIT, TAPED_QUARTER, TAPED_LANE };
+inline TapedKernel taped_kernel(const DevCfg& c) {
+  if (c.flags & F_ACTOR_BF16) return TAPED_QUARTER;
+  if (c.n_envs < TAPE_SPLIT_MAX_ENVS) return TAPED_SPLIT;
+  return c.n_envs >= TAPE_LANE_MIN_ENVS ? TAPED_LANE : TAPED_QUARTER;
 }
 // One-env-per-lane fused kernel (qs_fused.hip), actor on fp32 MFMA or VALU.
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
                         float* states, hipStream_t st);
+// The same kernel (fp32 matrix-core actor) with the tape and record modes of
+// launch_fused4.
+hipError_t launch_fused_taped(const DevCfg& c, const SimBufs& b, const float* W, int T,
+                              int t_base, float* rewards, uint8_t* dones, float* states,
+                              float* tape, int ckpt_every, const float* ck_in, float* rec,
+                              int rec_from, int rec_n, hipStream_t st);
 
 }  // namespace qs

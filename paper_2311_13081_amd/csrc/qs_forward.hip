@@ -133,6 +133,9 @@ __global__ void __launch_bounds__(256) k_plain_obs(DevCfg c, SimBufs b, float* _
     f[12 + i] = b.state[(7 + i) * N + e];
     f[15 + i] = b.state[(10 + i) * N + e];
   }
+  SetPoint sp;
+  sp.load(c, N, e);
+  sp.apply(c, f);
   add_obs_noise(c, (uint32_t)e, (uint32_t)b.ep[e], b.t_ep[e], f);
 #pragma unroll
   for (int i = 0; i < 18; ++i) obs[i * N + e] = f[i];
@@ -258,6 +261,9 @@ __global__ void __launch_bounds__(256) k_observe(DevCfg c, SimBufs b, float* __r
     for (int i = 0; i < 6; ++i) cobs[(22 + i) * N + e] = d[i];
   }
   if (aobs) {
+    SetPoint sp;
+    sp.load(c, N, e);
+    sp.apply(c, f);
     add_obs_noise(c, (uint32_t)e, ep, b.t_ep[e], f);
 #pragma unroll
     for (int i = 0; i < 18; ++i) aobs[i * N + e] = f[i];
@@ -397,9 +403,17 @@ hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st) {
   // the kernel of taped rollouts, in record mode
-  if (taped_on_split(c))
-    return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T, st);
-  return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T, st);
+  switch (taped_kernel(c)) {
+    case TAPED_SPLIT:
+      return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T,
+                          st);
+    case TAPED_LANE:
+      return launch_fused_taped(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec,
+                                0, T, st);
+    default:
+      return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T,
+                           st);
+  }
 }
 
 }  // namespace qs

@@ -18,14 +18,23 @@ namespace qs {
 // state and history kept in registers.  Outputs indexed by t_base + t.  ext_act ([T][4][N]) replaces
 // the actor when non-NULL.  Inactive lanes of the last wave shadow the wave's
 // first env (read only) so every MFMA operand is finite.  EXTRAS (the
-// training extras are on): the episode disturbance enters the dynamics and
-// the actor sees its observation with noise; without them the kernel carries
-// none of that code.
-template <bool MFMA, bool EXTRAS, bool BF16>
+// training extras or a set point are on): the episode disturbance enters the
+// dynamics and the actor sees its observation with noise and the set-point
+// shift; without them the kernel carries none of that code.
+//
+// TAPE (fp32 matrix-core actor only): the differentiable modes of the
+// quarter-lane kernel.  With tape != NULL a CK_F-row checkpoint every
+// ckpt_every steps; with ck_in != NULL the launch starts from that
+// checkpoint and leaves the env state alone (the backward's recompute); with
+// rec != NULL the backward's record (blocked by 64 envs) of the steps
+// t_base + t >= rec_from, a segment of rec_n steps.  The taped forward and
+// the recompute run this same code, so they agree bit for bit.
+template <bool MFMA, bool EXTRAS, bool BF16, bool TAPE>
 __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
-        float* __restrict__ states) {
+        float* __restrict__ states, float* __restrict__ tape, int ckpt_every,
+        const float* __restrict__ ck_in, float* __restrict__ rec, int rec_from, int rec_n) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
   if (ext_act == nullptr) {
@@ -47,20 +56,45 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
   Body<float> B = make_body<float>(th);
   const bool renorm = (c.flags & F_RENORM_Q) != 0;
 
+  // from a checkpoint (the backward's recompute): no write-back of the env
+  // state or of the episode accumulators
+  const bool REC = TAPE && ck_in != nullptr;
   float x[NS];
   float H[NH * NA];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
-  const int head0 = b.head[e];
-#pragma unroll
-  for (int sl = 0; sl < NH; ++sl) {
-    const int slot = (head0 + sl) & (NH - 1);
-#pragma unroll
-    for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
-  }
-  int t_ep = b.t_ep[e], ep = b.ep[e];
+  int head0 = 0, t_ep = 0, ep = 0;
   EpAcc acc;
-  acc.load(b, N, e);
+  if (REC) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = ck_in[(size_t)i * N + e];
+#pragma unroll
+    for (int i = 0; i < NH * NA; ++i) H[i] = ck_in[(size_t)(NS + i) * N + e];
+    t_ep = __float_as_int(ck_in[(size_t)CK_TEP * N + e]);
+    ep = __float_as_int(ck_in[(size_t)CK_EP * N + e]);
+    acc.cur = acc.last = 0.0f, acc.len = 0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = b.state[i * N + e];
+    head0 = b.head[e];
+#pragma unroll
+    for (int sl = 0; sl < NH; ++sl) {
+      const int slot = (head0 + sl) & (NH - 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) H[sl * NA + a] = b.ring[(slot * NA + a) * N + e];
+    }
+    t_ep = b.t_ep[e];
+    ep = b.ep[e];
+    acc.load(b, N, e);
+  }
+  // record layout of the wave's 64-env block (TAPE): blocks bb of the
+  // matrix-core tiles holding envs of the batch
+  const int lane = threadIdx.x & 63;
+  const uint32_t colmask = (first + 0 * 16 + (lane & 15) < N ? 1u : 0u) |
+                           (first + 1 * 16 + (lane & 15) < N ? 2u : 0u) |
+                           (first + 2 * 16 + (lane & 15) < N ? 4u : 0u) |
+                           (first + 3 * 16 + (lane & 15) < N ? 8u : 0u);
+  const size_t rblk = (size_t)(first / RB) * REC_F * RB;
+  SetPoint sp;
+  if (EXTRAS) sp.load(c, N, e);
   if (EXTRAS) {
     float d[6];
     disturbance(c, (uint32_t)e, (uint32_t)ep, d);
@@ -85,6 +119,17 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
     const int gt = t_base + t;
+    if (TAPE && tape && (gt % ckpt_every) == 0 && active) {
+      float* ck = tape + (size_t)(gt / ckpt_every) * CK_F * N;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) ck[(size_t)i * N + eo] = x[i];
+#pragma unroll
+      for (int i = 0; i < NH * NA; ++i) ck[(size_t)(NS + i) * N + eo] = H[i];
+      ck[(size_t)CK_TEP * N + eo] = __int_as_float(t_ep);
+      ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
+    }
+    const int rt_step = gt - rec_from;
+    const bool rec_on = TAPE && opaque((rec && rt_step >= 0) ? 1u : 0u) != 0u;
     float a[NA];
     if (ext_act) {
 #pragma unroll
@@ -93,14 +138,16 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       float Rm[9];
       rotmat(x + 3, Rm);
       float z3[NA];
-      if constexpr (EXTRAS) {
-        // noisy copy of the observed state features
-        float so[NS];
+      // the observed state features (the set-point shift and the noise
+      // under EXTRAS)
+      float so[NS];
 #pragma unroll
-        for (int i = 0; i < NS; ++i) so[i] = x[i];
-        if (c.flags & F_OBS_NOISE) {
+      for (int i = 0; i < NS; ++i) so[i] = x[i];
+      if constexpr (EXTRAS) {
+        if ((c.flags & F_OBS_NOISE) || c.target) {
           float f[18] = {x[0],  x[1],  x[2],  Rm[0], Rm[1], Rm[2], Rm[3], Rm[4],  Rm[5],
                          Rm[6], Rm[7], Rm[8], x[7],  x[8],  x[9],  x[10], x[11], x[12]};
+          sp.apply(c, f);
           add_obs_noise(c, (uint32_t)e, (uint32_t)ep, t_ep, f);
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
@@ -111,22 +158,41 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
 #pragma unroll
           for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
         }
-        if constexpr (BF16)
-          actor_mfma_bf16(lds, so, Rm, H, z3);
-        else if (MFMA)
+      }
+      float* rt = rec_on ? rec + rec_step(rt_step, N) + rblk : nullptr;
+      if constexpr (BF16) {
+        actor_mfma_bf16(lds, so, Rm, H, z3);
+      } else if constexpr (MFMA) {
+        if (TAPE && rec_on)
+          actor_mfma<true>(lds, so, Rm, H, z3, rt + (size_t)REC_Z1 * RB, rt + (size_t)REC_Z2 * RB,
+                           colmask);
+        else
           actor_mfma(lds, so, Rm, H, z3);
-        else
-          actor_valu(lds, so, Rm, H, z3);
       } else {
-        if constexpr (BF16)
-          actor_mfma_bf16(lds, x, Rm, H, z3);
-        else if (MFMA)
-          actor_mfma(lds, x, Rm, H, z3);
-        else
-          actor_valu(lds, x, Rm, H, z3);
+        actor_valu(lds, so, Rm, H, z3);
       }
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
+      if (TAPE && rec_on && active) {
+        // own-env rows: x_t, a_t, the observed state features; the step's
+        // action (and, first, the checkpoint's history) on the action tape
+        const uint32_t lo = opaque((uint32_t)lane);
+        const float of[18] = {so[0], so[1], so[2],  Rm[0],  Rm[1],  Rm[2],  Rm[3],  Rm[4],  Rm[5],
+                              Rm[6], Rm[7], Rm[8], so[7], so[8], so[9], so[10], so[11], so[12]};
+#pragma unroll
+        for (int i = 0; i < NS; ++i) rt[(size_t)(REC_X + i) * RB + lo] = x[i];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) rt[(size_t)(REC_A + i) * RB + lo] = a[i];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) rt[(size_t)(REC_O + i) * RB + lo] = of[i];
+        float* act = rec + rec_act(rec_n, N) + (size_t)(first / RB) * ((NH + rec_n) * NA) * RB;
+        if (rt_step == 0) {
+#pragma unroll
+          for (int i = 0; i < NH * NA; ++i) act[(size_t)i * RB + lo] = H[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NA; ++i) act[(size_t)((NH + rt_step) * NA + i) * RB + lo] = a[i];
+      }
     }
     float u[NA];
 #pragma unroll
@@ -165,7 +231,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
         for (int i = 0; i < NS; ++i) states[((size_t)(gt + 1) * NS + i) * N + eo] = x[i];
     }
   }
-  if (!active) return;
+  if (!active || REC) return;
   const uint32_t ef = opaque((uint32_t)e);
 #pragma unroll
   for (int i = 0; i < NS; ++i) b.state[(size_t)i * N + ef] = x[i];
@@ -192,13 +258,26 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
                         float* states, hipStream_t st) {
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
-  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
   // the bf16 actor option runs on the matrix-core kernel
   const bool bf = mfma && (c.flags & F_ACTOR_BF16) != 0;
-  auto k = bf ? (ex ? k_fused<true, true, true> : k_fused<true, false, true>)
-              : mfma ? (ex ? k_fused<true, true, false> : k_fused<true, false, false>)
-                     : (ex ? k_fused<false, true, false> : k_fused<false, false, false>);
-  hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones, states);
+  auto k = bf ? (ex ? k_fused<true, true, true, false> : k_fused<true, false, true, false>)
+              : mfma ? (ex ? k_fused<true, true, false, false> : k_fused<true, false, false, false>)
+                     : (ex ? k_fused<false, true, false, false> : k_fused<false, false, false, false>);
+  hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones, states,
+                     nullptr, 1, nullptr, nullptr, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_taped(const DevCfg& c, const SimBufs& b, const float* W, int T,
+                              int t_base, float* rewards, uint8_t* dones, float* states,
+                              float* tape, int ckpt_every, const float* ck_in, float* rec,
+                              int rec_from, int rec_n, hipStream_t st) {
+  const dim3 g(nblk(c.n_envs, 256)), blk(256);
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
+  auto k = ex ? k_fused<true, true, false, true> : k_fused<true, false, false, true>;
+  hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, nullptr, T, t_base, rewards, dones, states, tape,
+                     ckpt_every, ck_in, rec, rec_from, rec_n);
   return hipGetLastError();
 }
 

@@ -289,6 +289,8 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     acc.cur = acc.last = 0.0f, acc.len = 0;
   else
     acc.load(b, N, e);
+  SetPoint sp;
+  if (EXTRAS) sp.load(c, N, e);
   bool was_reset = false;
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah = rpm_to_action(c, wh);
@@ -328,7 +330,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       }
     }
     // observation state part: 18 features, this quarter keeps 4c + k
-    quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F);
+    quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F, sp);
     float* rt = rec_on ? rec + rec_step(rt_step, N) : nullptr;
     float z3[NA];
     // per-lane part of record addresses, recomputed every step (see opaque())
@@ -427,7 +429,7 @@ hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int 
                          hipStream_t st) {
   const unsigned grid = (unsigned)((c.n_envs + 63) / 64);
   const bool bf = (c.flags & F_ACTOR_BF16) != 0;
-  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
   auto k = bf ? (ex ? k_fused4<true, true> : k_fused4<true, false>)
               : (ex ? k_fused4<false, true> : k_fused4<false, false>);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states,

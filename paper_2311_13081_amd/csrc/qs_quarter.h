@@ -51,12 +51,16 @@ __device__ inline void stage_q(const float* __restrict__ W, float* lds) {
 // F[c] = feature 4c + k (0 past the end).
 template <bool EXTRAS>
 __device__ inline void quarter_state_features(const DevCfg& c, uint32_t e, uint32_t ep, int t_ep,
-                                              int k, const float x[NS], float F[5]) {
+                                              int k, const float x[NS], float F[5],
+                                              const SetPoint& sp) {
   float Rm[9];
   rotmat(x + 3, Rm);
   float sf[20] = {x[0], x[1], x[2], Rm[0], Rm[1], Rm[2], Rm[3], Rm[4], Rm[5], Rm[6],
                   Rm[7], Rm[8], x[7], x[8], x[9], x[10], x[11], x[12], 0.0f, 0.0f};
-  if (EXTRAS) add_obs_noise(c, e, ep, t_ep, sf);
+  if (EXTRAS) {
+    sp.apply(c, sf);
+    add_obs_noise(c, e, ep, t_ep, sf);
+  }
 #pragma unroll
   for (int cc = 0; cc < 5; ++cc)
     F[cc] = k == 0 ? sf[4 * cc] : k == 1 ? sf[4 * cc + 1] : k == 2 ? sf[4 * cc + 2]

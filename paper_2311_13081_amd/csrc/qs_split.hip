@@ -139,6 +139,8 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     acc.cur = acc.last = 0.0f, acc.len = 0;
   else
     acc.load(b, N, e);
+  SetPoint sp;
+  if (EXTRAS) sp.load(c, N, e);
   bool was_reset = false;
   const float wh = hover_rpm(c, th[0], th[4], th[5], th[6]);
   const float ah = rpm_to_action(c, wh);
@@ -177,7 +179,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
         ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
       }
     }
-    quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F);
+    quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F, sp);
     float* rt = rec_on ? rec + rec_step(rt_step, N) : nullptr;
     const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
     float z3[NA];
@@ -267,7 +269,7 @@ hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T
                         int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
                         hipStream_t st) {
   const unsigned grid = (unsigned)((c.n_envs + 15) / 16);
-  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0;
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
   auto k = ex ? k_split<true> : k_split<false>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states,
                      tape, ckpt_every, ck_in, rec, rec_from, rec_n);

@@ -183,19 +183,32 @@ class QuadSim:
                  _stream()), "sim_backward_noalloc" if noalloc else "sim_backward")
         return ga, gp
 
-    def get_state(self):
+    def get_state(self, parts=None):
         """Snapshot: state [17][N], hist [32][4][N], t_ep [N], episode [N],
         returns [2][N] (current episode so far, last finished episode) and
-        last_len [N] (steps of the last finished episode)."""
-        s = self._f32(17, self.N)
-        hist = self._f32(32, 4, self.N)
-        t = torch.empty(self.N, dtype=torch.int32, device=self.device)
-        e = torch.empty(self.N, dtype=torch.int32, device=self.device)
-        ret = self._f32(2, self.N)
-        ln = torch.empty(self.N, dtype=torch.int32, device=self.device)
-        check(self.L.sim_get_state(self.h, _ptr(s), _ptr(hist), _ptr(t), _ptr(e), _ptr(ret),
-                                   _ptr(ln), _stream()), "sim_get_state")
-        return dict(state=s, hist=hist, t_ep=t, episode=e, returns=ret, last_len=ln)
+        last_len [N] (steps of the last finished episode).  parts: the keys
+        to fetch (default all)."""
+        want = set(parts) if parts is not None else {"state", "hist", "t_ep", "episode",
+                                                      "returns", "last_len"}
+        i32 = dict(dtype=torch.int32, device=self.device)
+        out = {}
+        if "state" in want:
+            out["state"] = self._f32(17, self.N)
+        if "hist" in want:
+            out["hist"] = self._f32(32, 4, self.N)
+        if "t_ep" in want:
+            out["t_ep"] = torch.empty(self.N, **i32)
+        if "episode" in want:
+            out["episode"] = torch.empty(self.N, **i32)
+        if "returns" in want:
+            out["returns"] = self._f32(2, self.N)
+        if "last_len" in want:
+            out["last_len"] = torch.empty(self.N, **i32)
+        g = out.get
+        check(self.L.sim_get_state(self.h, _ptr(g("state")), _ptr(g("hist")), _ptr(g("t_ep")),
+                                   _ptr(g("episode")), _ptr(g("returns")), _ptr(g("last_len")),
+                                   _stream()), "sim_get_state")
+        return out
 
     def set_state(self, state=None, hist=None, t_ep=None, episode=None, returns=None,
                   last_len=None):
@@ -225,6 +238,18 @@ class QuadSim:
         self.cfg.update({k: float(v) for k, v in constants.items()})
         C = (ctypes.c_double * 7)(*[float(self.cfg[k]) for k in self.REWARD_KEYS])
         check(self.L.sim_set_reward(self.h, C), "sim_set_reward")
+
+    def set_target(self, target=None, pos_clip: float = 0.2, vel_clip: float = 1.0):
+        """Set point of the actor's observation: target [6][N] = {p_sp, v_sp}
+        per env (None removes it); the actor then observes the clipped
+        position and velocity errors."""
+        t = None
+        if target is not None:
+            t = torch.as_tensor(target, dtype=torch.float32).to(self.device).contiguous()
+            self._need(t, (6, self.N), torch.float32, "target")
+        check(self.L.sim_set_target(self.h, _ptr(t), float(pos_clip), float(vel_clip), _stream()),
+              "sim_set_target")
+        self.tape_T = 0
 
     def reset_envs(self, mask: torch.Tensor):
         """Starts the next episode of every env with mask != 0 (uint8 or bool

@@ -426,3 +426,56 @@ def test_grad65536_dr_full_size(pkg, oracle_lib):
     assert ea < GRAD_TOL
     assert ep.max() < GRAD_TOL
     sim.close()
+
+
+def test_one_lane_reverse_sweep_ragged_batch(pkg, oracle_lib):
+    """From 65536 envs the reverse sweep runs one env per lane (64 envs per
+    wave, the actor VJP on matrix-core tiles, the history adjoint partly in
+    an LDS ring).  A ragged batch (65573 envs: the last wave has 37 envs)
+    with random reward and state cotangents on a sample of envs -- among them
+    the last 37 -- and zero elsewhere: the sample's actor gradient and every
+    env's parameter gradients match the oracle adjoint, the others' are
+    exactly zero."""
+    orc = oracle_lib
+    N, T, K = 65536 + 37, 20, 8
+    cfg = wl.crazyflie_config(n_envs=N, flags=wl.F_RENORM_Q, dr_enable=1, max_episode_steps=0,
+                              max_tape_horizon=T, ckpt_every=K)
+    sim = pkg.QuadSim(cfg)
+    W = wl.random_actor(4)
+    a = sim.actor_tensor(W)
+    rng = np.random.default_rng(21)
+    ids = np.unique(np.concatenate([np.arange(N - 37, N), np.arange(0, 8),
+                                    rng.choice(N - 37, 24, replace=False)])).astype(np.uint32)
+    ob = orc.Batch.init(cfg, len(ids), ids=ids)
+    s32, h32 = (x.astype(np.float32) for x in ob.soa())
+    st = {k: v.clone() for k, v in sim.get_state().items()}
+    idx = torch.as_tensor(ids.astype(np.int64)).cuda()
+    st["state"][:, idx] = torch.as_tensor(s32).cuda()
+    st["hist"][:, :, idx] = torch.as_tensor(h32).cuda()
+    sim.set_state(**st)
+    th = np_(sim.get_params())
+    dR = np.zeros((T, N), np.float32)
+    dS = np.zeros((T + 1, 17, N), np.float32)
+    dR[:, ids] = rng.uniform(0.5, 1.5, size=(T, len(ids)))
+    dS[:, :, ids] = rng.normal(size=(T + 1, 17, len(ids))) * 1e-2
+    dS[:, 13:17, :] *= 1e-4
+    sim.rollout(a, T, rewards=False, dones=False, record_tape=True)
+    ga, gp = sim.backward(a, d_rewards=torch.as_tensor(dR).cuda(),
+                          d_states=torch.as_tensor(dS).cuda())
+    ga = np_(ga).astype(np.float64)
+    gp = np_(gp).astype(np.float64)
+    rest = np.ones(N, bool)
+    rest[ids] = False
+    assert not gp[:, rest].any()
+    ref = orc.Batch(cfg, len(ids), ids=ids)
+    ref.set_soa(s32, h32, theta_soa=th[:, ids])
+    _, gW, gth = ref.grad(W, T, dR=dR[:, ids].astype(np.float64),
+                          dS=np.transpose(dS[:, :, ids], (0, 2, 1)).astype(np.float64), nthreads=8)
+    ea = np.linalg.norm(ga - gW) / np.linalg.norm(gW)
+    sc = param_scale(cfg, ref.theta)
+    ep = param_grad_err(gp[:, ids].T, gth, sc)
+    print(f"one-lane sweep, ragged {N}: actor rel err {ea:.2e}, params max rel err {ep.max():.2e} "
+          f"(last 37 envs: {ep[-37:].max():.2e})")
+    assert ea < GRAD_TOL
+    assert ep.max() < GRAD_TOL
+    sim.close()

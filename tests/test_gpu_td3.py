@@ -1,0 +1,75 @@
+"""The TD3 training loop's use of the environment, on a short run: the replay
+buffer holds post-step states (before the restart of finished envs), every
+stored reward equals the FP64 oracle's reward of its transition under the
+reward constants in force at the end (the buffer is re-scored after each
+curriculum round; without re-scoring the early transitions keep their old
+rewards), the curriculum reaches the env, and the evaluation rollouts (the
+policy inside the fused step kernel) report episode lengths in range.
+
+Bar: rewards |dr| / max(|r|, 1) <= 1e-5."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def td3():
+    import paper_2311_13081_amd as p
+    p.load()
+    from paper_2311_13081_amd import td3 as t
+    return t
+
+
+def _short(t, recalc):
+    cfg = t.TD3Config(total_steps=2500, n_envs=4, warmup=500, curriculum_every=1000,
+                      eval_every=1000, eval_envs=64, eval_steps=100, recalc_rewards=recalc,
+                      C_factor=dict(C_rp=1.5, C_ra=2.0), C_target=dict(C_rp=10.0, C_ra=1.0))
+    return cfg, t.train(cfg)
+
+
+def _oracle_rewards(oracle_lib, env_cfg, C, replay, ids):
+    c = dict(env_cfg, **C)
+    s = replay.s_next.cpu().numpy()
+    a = replay.a.cpu().numpy()
+    return np.array([oracle_lib.reward(c, s[:, i].astype(np.float64), a[i].astype(np.float64))
+                     for i in ids])
+
+
+def test_td3_short_run_mechanics(td3, oracle_lib):
+    cfg, out = _short(td3, True)
+    rec, buf = out["records"], out["replay"]
+    print("td3 short run", rec)
+    assert [r["step"] for r in rec] == [1000, 2000, 2500]
+    assert [r["stage"] for r in rec] == [0, 1, 2]
+    assert out["C"]["C_rp"] == pytest.approx(2.25) and out["C"]["C_ra"] == pytest.approx(0.04)
+    for r in rec:
+        assert 1 <= r["eval_len_mean"] <= 100 and np.isfinite(r["eval_ret_mean"])
+        assert r["train_episodes"] > 0
+    assert buf.size == 2500
+    ids = np.arange(0, 2500, 7)
+    ref = _oracle_rewards(oracle_lib, out["env_cfg"], out["C"], buf, ids)
+    r = buf.r.cpu().numpy()[ids].astype(np.float64)
+    err = float((np.abs(r - ref) / np.maximum(np.abs(ref), 1.0)).max())
+    print(f"stored rewards vs oracle under the final constants: {err:.2e}")
+    assert err < 1e-5
+    # terminal flags: terminated transitions left the box or went non-finite
+    s = buf.s_next.cpu().numpy()
+    term = buf.term.cpu().numpy()[:2500] != 0
+    out_box = (np.abs(s[0:3]) > np.float32(0.6)).any(axis=0) | \
+        (np.abs(s[7:10]) > np.float32(2.0)).any(axis=0) | \
+        ~np.isfinite(s).all(axis=0)
+    assert np.array_equal(term, out_box[:2500])
+
+
+def test_td3_without_recalculation_keeps_old_rewards(td3, oracle_lib):
+    cfg, out = _short(td3, False)
+    buf = out["replay"]
+    ids = np.arange(0, 2500, 7)
+    ref = _oracle_rewards(oracle_lib, out["env_cfg"], out["C"], buf, ids)
+    r = buf.r.cpu().numpy()[ids].astype(np.float64)
+    err = np.abs(r - ref) / np.maximum(np.abs(ref), 1.0)
+    late = ids >= 2000   # added under the final constants
+    assert err[late].max() < 1e-5
+    assert (err[~late] > 1e-4).mean() > 0.5
