@@ -180,11 +180,14 @@ __device__ inline void layer3_one_lane(const float* lds, int w3, int b3off, cons
 //  block in this step's record; register 4 bb + v (neuron 16 n + 4 lg + v of
 //  env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li, for the
 //  blocks bb whose bit is set in colmask (envs past the batch stay unwritten).
+//  mbits receives the lane's ReLU masks in the same layout (bit 16 n + 4 bb
+//  + v of word n / 2: layer 1, words 0-1; layer 2, words 2-3).
 template <bool REC = false>
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
                                   const float H[NH * NA], float z3out[NA],
                                   float* __restrict__ rz1 = nullptr,
-                                  float* __restrict__ rz2 = nullptr, uint32_t colmask = 0) {
+                                  float* __restrict__ rz2 = nullptr, uint32_t colmask = 0,
+                                  uint32_t* mbits = nullptr) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const f16 zero16 = {};
@@ -219,6 +222,12 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
         for (int v = 0; v < 4; ++v)
           if (colmask & (1u << bb))
             rz1[(size_t)(16 * n + 4 * lg + v) * 64 + 16 * bb + li] = acc1[n][4 * bb + v];
+    mbits[0] = mbits[1] = 0u;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        mbits[n >> 1] |= acc1[n][r] > 0.0f ? 1u << (16 * (n & 1) + r) : 0u;
   }
 #pragma unroll
   for (int n = 0; n < 4; ++n)
@@ -250,6 +259,14 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
         for (int r = 0; r < 4; ++r)
           if (colmask & (1u << bb))
             rz2[(size_t)(16 * n2 + 4 * lg + r) * 64 + 16 * bb + li] = acc2[n2][bb][r];
+    mbits[2] = mbits[3] = 0u;
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          mbits[2 + (n2 >> 1)] |= acc2[n2][bb][r] > 0.0f ? 1u << (16 * (n2 & 1) + 4 * bb + r) : 0u;
   }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)

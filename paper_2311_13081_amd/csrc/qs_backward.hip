@@ -163,10 +163,9 @@ constexpr int R_XCH = (4 + 4 + 10) * 64 * 4;
 // Batches up to this size run the split sweep (four times the waves; the
 // quarter-lane sweep leaves most SIMDs idle there).
 constexpr int REVERSE_SPLIT_MAX_ENVS = 4096;
-// Batches from this size run the one-env-per-lane sweep (qs_reverse1.hip):
-// one wave of 64 envs per SIMD and no repeated dynamics adjoint; below it,
-// its waves would leave SIMDs idle.
-constexpr int REVERSE_LANE_MIN_ENVS = 65536;
+// Segments recorded by the one-env-per-lane forward (taped_kernel) run the
+// one-env-per-lane sweep (qs_reverse1.hip), which reads that kernel's ReLU
+// mask rows: one wave of 64 envs per SIMD and no repeated dynamics adjoint.
 
 // Reverse sweep of one segment.  SPLIT = false: 16 envs per wave in the
 // quarter-lane layout.  SPLIT = true: 16 envs per workgroup of 4 waves, each
@@ -931,7 +930,7 @@ static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const Bwd
         BWD_TRY(hipStreamWaitEvent(st, bw.e_rec[buf], 0));
       }
     }
-    if (N >= REVERSE_LANE_MIN_ENVS)
+    if (taped_kernel(c) == TAPED_LANE)
       BWD_TRY(launch_reverse1(c, b.theta, W, tape + (size_t)j * CK_F * N, bw.seg[buf], n, t0,
                               d_rewards, d_states, bw.lam, bw.gth, bw.dz[buf], st));
     else if (N <= REVERSE_SPLIT_MAX_ENVS)

@@ -44,8 +44,13 @@ hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* ac
                               int T, float* rewards, uint8_t* dones, float* states,
                               hipStream_t st);
 // Per-step record of the backward recompute, REC_F rows per env: x_t (17),
-// a_t (4), layer-1 and layer-2 pre-activations (64 + 64) and the 18 state
-// features of the observation o_t (as the actor saw them, noise included).
+// a_t (4), layer-1 and layer-2 pre-activations (64 + 64), the 18 state
+// features of the observation o_t (as the actor saw them, noise included)
+// and 4 rows of ReLU masks written by the one-env-per-lane kernel only: in
+// that kernel's matrix-core tile layout, lane l of a 64-env block keeps bit
+// 16 n + 4 bb + v of word w = n / 2 (layer 1, words 0-1; layer 2, words 2-3)
+// set when neuron 16 n + 4 (l / 16) + v of env 16 bb + l % 16 of the block
+// has a positive pre-activation; the word sits in row REC_M + w, column l.
 // The 128 history features of o_t are not stored per step: they are the
 // actions of the 32 previous steps.  After the n step records of a segment
 // comes its action tape: per 64-env block, (NH + n) slots of NA rows, slot s
@@ -53,7 +58,7 @@ hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* ac
 // action of step t; the history slot sl of step t is tape slot t + sl.  One
 // block's tape is one contiguous span (48 KB for n = 16).
 constexpr int REC_X = 0, REC_A = REC_X + NS, REC_Z1 = REC_A + NA, REC_Z2 = REC_Z1 + NHID,
-              REC_O = REC_Z2 + NHID, REC_F = REC_O + 18;
+              REC_O = REC_Z2 + NHID, REC_M = REC_O + 18, REC_F = REC_M + 4;
 
 // Tape checkpoint of a differentiable rollout, CK_F rows of [N]: state (17),
 // history oldest first (128), then the step within the episode and the

@@ -163,11 +163,18 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       if constexpr (BF16) {
         actor_mfma_bf16(lds, so, Rm, H, z3);
       } else if constexpr (MFMA) {
-        if (TAPE && rec_on)
+        if (TAPE && rec_on) {
+          uint32_t mb[4];
           actor_mfma<true>(lds, so, Rm, H, z3, rt + (size_t)REC_Z1 * RB, rt + (size_t)REC_Z2 * RB,
-                           colmask);
-        else
+                           colmask, mb);
+          // every lane's words (its tiles may hold envs of the batch even
+          // where its own env is past the end)
+#pragma unroll
+          for (int w = 0; w < 4; ++w)
+            rt[(size_t)(REC_M + w) * RB + opaque((uint32_t)lane)] = __uint_as_float(mb[w]);
+        } else {
           actor_mfma(lds, so, Rm, H, z3);
+        }
       } else {
         actor_valu(lds, so, Rm, H, z3);
       }

@@ -9,15 +9,19 @@
 // per lane, and only the actor's input VJP is spread over the lanes of the
 // wave as matrix-core tiles:
 //   dz3 = ga (1 - a^2)                       own lane;
-//   dz2 = (W3^T dz3) [z2 > 0]                own lane, vector ALUs (K = 4);
-//   dz1 = (W2^T dz2) [z1 > 0]                4-block v_mfma_f32_16x16x1f32, one
-//        rank-1 update per layer-2 neuron with B = the lane's own dz2 value
-//        (the pattern of the forward's layer 1): register 4 bb + v of tile mt
-//        holds neuron 16 mt + 4 lg + v of env 16 bb + li (lane li + 16 lg);
-//   do  = W1^T dz1                            v_mfma_f32_16x16x4f32 chained over
-//        the dz1 registers as B operands (K-chunk = neurons 16 mt + 4 k + v),
+//   dz2 = (W3^T dz3) [z2 > 0]                4-block v_mfma_f32_16x16x1f32, one
+//        rank-1 update per action with B = the lane's own dz3 value (the
+//        pattern of the forward's layer 1): register 4 bb + v of tile n
+//        holds neuron 16 n + 4 lg + v of env 16 bb + li (lane li + 16 lg);
+//   dz1 = (W2^T dz2) [z1 > 0]                v_mfma_f32_16x16x4f32 chained over
+//        the dz2 registers as B operands (K-chunk = neurons 16 n + 4 k + v),
+//        the same tile layout out;
+//   do  = W1^T dz1                            the same over the dz1 registers,
 //        ten 16-feature tiles; register r of block bb holds feature
 //        16 p + 4 lg + r of env 16 bb + li;
+// the ReLU masks come as bits in that tile layout from the one-lane
+// forward's record (4 words per lane and step), so the sweep loads no
+// pre-activations;
 // and a 4 x 4 transpose across the lane groups (two permlane32 and two
 // permlane16 swaps per register) brings every feature of a tile to the lane
 // of its env, where the observation's share joins the state and history
@@ -33,11 +37,9 @@ namespace qs {
 
 // LDS (floats):
 //   L_W3T[n][i]             = W3[i][n] (one 16-byte read: the 4 output weights of neuron n);
-//   L_W2T[m][k]             = W2[k][m], rows padded to 68 (16 rows read together hit
-//                             distinct banks);
+//   L_W2Q[mt][n][g][i][v]   = W2[16 n + 4 g + v][16 mt + i];
 //   L_W1Q[p][mt][g][i][v]   = W1[16 mt + 4 g + v][16 p + i] (0 past feature 145).
-constexpr int L_W2_LD = 68;
-constexpr int L_W3T = 0, L_W2T = L_W3T + NHID * NA, L_W1Q = L_W2T + NHID * L_W2_LD,
+constexpr int L_W3T = 0, L_W2Q = L_W3T + NHID * NA, L_W1Q = L_W2Q + NHID * NHID,
               L_TOTAL = L_W1Q + 10 * 4 * 4 * 16 * 4;
 // History adjoint: the older HR slots of each env in a per-wave ring in LDS
 // ([HR][4][64 lanes] after the weights: moving the slots one step older is a
@@ -54,9 +56,9 @@ __device__ inline void stage_reverse1(const float* __restrict__ W, float* lds, b
     const int n = i >> 2, a = i & 3;
     lds[L_W3T + i] = fwd_weight(W[OFF_W3 + a * NHID + n], bf16);
   }
-  for (int i = tid; i < NHID * L_W2_LD; i += nt) {
-    const int m = i / L_W2_LD, k = i % L_W2_LD;
-    lds[L_W2T + i] = k < NHID ? fwd_weight(W[OFF_W2 + k * NHID + m], bf16) : 0.0f;
+  for (int i = tid; i < NHID * NHID; i += nt) {
+    const int v = i & 3, li = (i >> 2) & 15, g = (i >> 6) & 3, n = (i >> 8) & 3, mt = i >> 10;
+    lds[L_W2Q + i] = fwd_weight(W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * mt + li], bf16);
   }
   for (int i = tid; i < 10 * 4 * 4 * 16 * 4; i += nt) {
     const int v = i & 3, li = (i >> 2) & 15, g = (i >> 6) & 3, mt = (i >> 8) & 3, p = i >> 10;
@@ -65,15 +67,19 @@ __device__ inline void stage_reverse1(const float* __restrict__ W, float* lds, b
   }
 }
 
-// Own-env inputs of one reverse step.
+// Inputs of one reverse step: the own env's recorded state and action and
+// cotangents, and the lane's ReLU mask words (column lane of the block).
 struct StepIn1 {
   float x[NS], a[NA], dS[NS], dR;
+  uint32_t m[4];
 };
 
 __device__ inline void load_step1(StepIn1& in, const float* __restrict__ rt, size_t roff,
-                                  const float* __restrict__ d_rewards,
+                                  size_t moff, const float* __restrict__ d_rewards,
                                   const float* __restrict__ d_states, int t, int N, int e) {
   const uint32_t eo = opaque((uint32_t)e);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) in.m[w] = __float_as_uint(rt[(size_t)(REC_M + w) * RB + moff]);
 #pragma unroll
   for (int i = 0; i < NS; ++i) in.x[i] = rt[(size_t)(REC_X + i) * RB + roff];
 #pragma unroll
@@ -115,6 +121,7 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
   const size_t rbase = (size_t)(env0 / RB) * REC_F * RB;  // block in a step's record
   const size_t zbase = (size_t)(env0 / RB) * DZ_F * RB;   // block in a step's cotangents
   const size_t roff = rbase + (size_t)(e - env0);
+  const size_t moff = rbase + (size_t)lane;
 
   float th[NP];
 #pragma unroll
@@ -149,7 +156,7 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
   for (int i = 0; i < NP; ++i) gth[i] = gth_io[(size_t)i * N + e];
 
   StepIn1 cur, nxt;
-  load_step1(cur, rec + rec_step(n - 1, N), roff, d_rewards, d_states, t0 + n - 1, N, e);
+  load_step1(cur, rec + rec_step(n - 1, N), roff, moff, d_rewards, d_states, t0 + n - 1, N, e);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
     const float* rt = rec + rec_step(tl, N);
@@ -158,9 +165,8 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
 
     float gx[NS], ga[NA];
     reverse_dynamics(c, B, th, renorm, cur.x, cur.a, cur.dR, ls, lR[NH - HR - 1], gx, ga, gth);
-    // (the loads below stay after the dynamics: hoisted above them they
-    // would hold 64 registers through its peak)
-    __asm__ volatile("" ::: "memory");
+    // the next step's inputs, in flight during the input VJP below
+    load_step1(nxt, rec + rec_step(tp, N), roff, moff, d_rewards, d_states, t0 + tp, N, e);
     const uint32_t own = opaque((uint32_t)(zbase + lane));
     float d3[NA];
 #pragma unroll
@@ -168,57 +174,57 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
       d3[i] = ga[i] * (1.0f - cur.a[i] * cur.a[i]);
       if (active) dzt[(size_t)(2 * NHID + i) * RB + own] = d3[i];
     }
-    // dz2 = (W3^T dz3) [z2 > 0] (own env, four neurons at a time, each group
-    // just before its rank-1 updates), and dz1 = (W2^T dz2) [z1 > 0]: one
-    // rank-1 update per layer-2 neuron k
-    f16 acc[4];
+    // dz2 = (W3^T dz3) [z2 > 0]: one rank-1 update per action
+    f16 d2[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = f16{};
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const f4 w3 = *reinterpret_cast<const f4*>(&lds[L_W3T + 4 * (16 * n2 + li)]);
+      d2[n2] = f16{};
 #pragma unroll
-    for (int kc = 0; kc < NHID / 4; ++kc) {
-      float dz2[4];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int k = 4 * kc + kk;
-        const float z2 = rt[(size_t)(REC_Z2 + k) * RB + roff];
-        const f4 w3 = *reinterpret_cast<const f4*>(&lds[L_W3T + 4 * k]);
-        const float v = w3[0] * d3[0] + w3[1] * d3[1] + w3[2] * d3[2] + w3[3] * d3[3];
-        dz2[kk] = z2 > 0.0f ? v : 0.0f;
-        if (active) dzt[(size_t)(NHID + k) * RB + own] = dz2[kk];
-      }
-      f4 w[4];
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        w[mt] = *reinterpret_cast<const f4*>(&lds[L_W2T + (16 * mt + li) * L_W2_LD + 4 * kc]);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[mt][kk], dz2[kk], acc[mt], 0, 0, 0);
+      for (int i = 0; i < NA; ++i)
+        d2[n2] = __builtin_amdgcn_mfma_f32_16x16x1f32(w3[i], d3[i], d2[n2], 0, 0, 0);
     }
-    __asm__ volatile("" ::: "memory");
-    // layer-1 pre-activations in the tile layout: register 4 bb + v of tile
-    // mt = neuron 16 mt + 4 lg + v of env 16 bb + li
-    float z1[4][16];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          z1[mt][4 * bb + v] = rt[rbase + (size_t)(REC_Z1 + 16 * mt + 4 * lg + v) * RB + col[bb]];
-    // the next step's own-env inputs, in flight during the input VJP below
-    load_step1(nxt, rec + rec_step(tp, N), roff, d_rewards, d_states, t0 + tp, N, e);
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 4 * bb + v;
-          acc[mt][r] = z1[mt][r] > 0.0f ? acc[mt][r] : 0.0f;
+          const bool on = (cur.m[2 + (n2 >> 1)] >> (16 * (n2 & 1) + r)) & 1u;
+          d2[n2][r] = on ? d2[n2][r] : 0.0f;
           if (col_ok[bb])
-            dzt[zbase + (size_t)(16 * mt + 4 * lg + v) * RB + 16 * bb + li] = acc[mt][r];
+            dzt[zbase + (size_t)(NHID + 16 * n2 + 4 * lg + v) * RB + 16 * bb + li] = d2[n2][r];
+        }
+    // dz1 = (W2^T dz2) [z1 > 0]: chains over the dz2 registers, 16 per
+    // (tile, block)
+    f4 d1[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) d1[mt][bb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int n2 = 0; n2 < 4; ++n2) {
+        const f4 wv =
+            *reinterpret_cast<const f4*>(&lds[L_W2Q + (((mt * 4 + n2) * 4 + lg) * 16 + li) * 4]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb)
+            d1[mt][bb] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], d2[n2][4 * bb + v], d1[mt][bb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const bool on = (cur.m[mt >> 1] >> (16 * (mt & 1) + 4 * bb + r)) & 1u;
+          d1[mt][bb][r] = on ? d1[mt][bb][r] : 0.0f;
+          if (col_ok[bb])
+            dzt[zbase + (size_t)(16 * mt + 4 * lg + r) * RB + 16 * bb + li] = d1[mt][bb][r];
         }
 
     // the history adjoint moves one slot older: H_t[s] feeds H_{t+1}[s - 1]
@@ -253,8 +259,7 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
         for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int bb = 0; bb < 4; ++bb)
-            o[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], acc[mt][4 * bb + v], o[bb], 0, 0,
-                                                         0);
+            o[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[v], d1[mt][bb][v], o[bb], 0, 0, 0);
       }
       // o[bb][r] in lane li + 16 lg: feature 16 p + 4 lg + r of env 16 bb + li.
       // Swapping the upper half of o[0] with the lower half of o[2] (and o[1]
