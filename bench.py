@@ -110,6 +110,8 @@ def parse():
     ap.add_argument("--only-fwd-bwd", action="store_true",
                     help="run only the forward+backward legs and print them (for profiling "
                          "the backward kernels)")
+    ap.add_argument("--fwd-bwd-legs", default=None,
+                    help="comma-separated forward+backward legs to run (default: all)")
     ap.add_argument("--variant", default="auto", choices=["auto", "mfma4", "mfma", "valu", "split"],
                     help="auto = run the autotuner; otherwise a fixed fused kernel, one launch "
                          "per rollout (used for profiling so only timed launches appear)")
@@ -262,6 +264,7 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
     workload; returns env-steps/s of the pair (N x H per fwd+bwd).  bf16:
     the actor on bf16 matrix cores (SIM_F_ACTOR_BF16)."""
     cfg = wl.workload_config(name)
+    cfg["ckpt_every"] = K
     if bf16:
         cfg["flags"] |= wl.F_ACTOR_BF16
     H = wl.workload_steps(name)
@@ -342,17 +345,22 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
             "roofline": roof, "memory": mem}
 
 
-def fwd_bwd_legs(torch, pkg, W):
+def fwd_bwd_legs(torch, pkg, W, only=None):
     """The differentiable workloads: the policy gradient on 1024 nominal envs
     over 64 steps, the same on 65536 randomised envs (the hover-biased
     policy, which keeps every body's rates bounded over the horizon),
     and system identification on 16384 randomised envs over 256 steps (fp32
-    and bf16 actor), checkpoints every 16 steps."""
-    return {"grad1024": fwd_bwd(torch, pkg, "grad1024", 16, W),
-            "grad65536_dr": fwd_bwd(torch, pkg, "grad65536_dr", 16, wl.sysid_actor(0)),
-            "sysid16384": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0)),
-            "sysid16384_bf16": fwd_bwd(torch, pkg, "sysid16384", 16, wl.sysid_actor(0),
-                                       bf16=True)}
+    and bf16 actor), checkpoints every 16 steps.  grad65536_dr_rec64 is the
+    65536-env policy gradient with one 64-step segment: the taped forward
+    records the whole horizon (3 GB in HBM) and the backward recomputes
+    nothing.  only: names of the legs to run (all when None)."""
+    legs = {"grad1024": ("grad1024", 16, W, False),
+            "grad65536_dr": ("grad65536_dr", 16, wl.sysid_actor(0), False),
+            "grad65536_dr_rec64": ("grad65536_dr", 64, wl.sysid_actor(0), False),
+            "sysid16384": ("sysid16384", 16, wl.sysid_actor(0), False),
+            "sysid16384_bf16": ("sysid16384", 16, wl.sysid_actor(0), True)}
+    return {k: fwd_bwd(torch, pkg, name, K, actor, bf16=bf16)
+            for k, (name, K, actor, bf16) in legs.items() if only is None or k in only}
 
 
 def fixed_episodes(torch, pkg, actor):
@@ -430,7 +438,8 @@ def main():
     N = cfg["n_envs"]
     W = wl.xavier_actor(0)
     if args.only_fwd_bwd:
-        print(json.dumps({"fwd_bwd": fwd_bwd_legs(torch, pkg, W)}), flush=True)
+        only = args.fwd_bwd_legs.split(",") if args.fwd_bwd_legs else None
+        print(json.dumps({"fwd_bwd": fwd_bwd_legs(torch, pkg, W, only)}), flush=True)
         return
 
     if args.copy_probe_mib:
@@ -510,6 +519,9 @@ def main():
                                            "ms_per_env_step": w3 * 1e3 / (2 * args.plain_steps)}
         s3.close()
         extras["fused_vs_plain_speedup"] = value / extras["plain_graph"]["env_steps_per_s"]
+        # against the best any unfused path with these intermediates could do:
+        # the plain step's algorithmic bytes moved at the HBM peak
+        extras["fused_vs_plain_hbm_roof"] = value / (PEAK_HBM / PLAIN_BYTES_PER_ENV_STEP)
         # the same kernel as a hipGraph-captured rollout of 100-step launches
         # (ten kernel nodes replayed per rollout)
         sim.set_variant(v, 100, True)

@@ -176,18 +176,28 @@ __device__ inline void layer3_one_lane(const float* lds, int w3, int b3off, cons
 //           neurons; two swap-and-add rounds across 32 and 16 lanes add the
 //           quarters and leave output o of env (lane) in every lane.
 //  REC: also store the layer pre-activations into the backward's blocked
-//  record: rz1 / rz2 point at the first z1 / z2 row of the wave's 64-env
-//  block in this step's record; register 4 bb + v (neuron 16 n + 4 lg + v of
-//  env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li, for the
-//  blocks bb whose bit is set in colmask (envs past the batch stay unwritten).
-//  mbits receives the lane's ReLU masks in the same layout (bit 16 n + 4 bb
-//  + v of word n / 2: layer 1, words 0-1; layer 2, words 2-3).
+//  record (zr: the record span, the byte offsets of the z1 and z2 rows of
+//  the wave's 64-env block in this step's record, and the lane's offset
+//  4 (4 lg 64 + li) in a tile row); register 4 bb + v (neuron 16 n + 4 lg + v
+//  of env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li.  Every
+//  column is written, those of envs past the batch with the values of the
+//  lanes that shadow them.  mbits receives the lane's ReLU masks in the same
+//  layout (bit 16 n + 4 bb + v of word n / 2: layer 1, words 0-1; layer 2,
+//  words 2-3).
+struct ZRec {
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t s1, s2, v;
+};
+// Sets bit 16 h + r of w (r = 15 .. 0 in turn, w shifted left each time) when
+// z[r] > 0: the two halves of a mask word are filled high half first.
+__device__ inline uint32_t push_mask_bit(uint32_t w, float z) {
+  return (w << 1) | (z > 0.0f ? 1u : 0u);
+}
+
 template <bool REC = false>
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
                                   const float H[NH * NA], float z3out[NA],
-                                  float* __restrict__ rz1 = nullptr,
-                                  float* __restrict__ rz2 = nullptr, uint32_t colmask = 0,
-                                  uint32_t* mbits = nullptr) {
+                                  const ZRec* zr = nullptr, uint32_t* mbits = nullptr) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const f16 zero16 = {};
@@ -220,14 +230,16 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (colmask & (1u << bb))
-            rz1[(size_t)(16 * n + 4 * lg + v) * 64 + 16 * bb + li] = acc1[n][4 * bb + v];
-    mbits[0] = mbits[1] = 0u;
+          bst1(acc1[n][4 * bb + v], zr->r, zr->v, zr->s1 + 4u * ((16 * n + v) * 64 + 16 * bb));
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int w = 0; w < 2; ++w) {
+      uint32_t m = 0u;
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        mbits[n >> 1] |= acc1[n][r] > 0.0f ? 1u << (16 * (n & 1) + r) : 0u;
+      for (int h = 1; h >= 0; --h)
+#pragma unroll
+        for (int r = 15; r >= 0; --r) m = push_mask_bit(m, acc1[2 * w + h][r]);
+      mbits[w] = m;
+    }
   }
 #pragma unroll
   for (int n = 0; n < 4; ++n)
@@ -257,16 +269,16 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (colmask & (1u << bb))
-            rz2[(size_t)(16 * n2 + 4 * lg + r) * 64 + 16 * bb + li] = acc2[n2][bb][r];
-    mbits[2] = mbits[3] = 0u;
+          bst1(acc2[n2][bb][r], zr->r, zr->v, zr->s2 + 4u * ((16 * n2 + r) * 64 + 16 * bb));
 #pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2)
+    for (int w = 0; w < 2; ++w) {
+      uint32_t m = 0u;
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
+      for (int h = 1; h >= 0; --h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          mbits[2 + (n2 >> 1)] |= acc2[n2][bb][r] > 0.0f ? 1u << (16 * (n2 & 1) + 4 * bb + r) : 0u;
+        for (int q = 15; q >= 0; --q) m = push_mask_bit(m, acc2[2 * w + h][q >> 2][q & 3]);
+      mbits[2 + w] = m;
+    }
   }
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2)

@@ -546,8 +546,10 @@ __device__ inline void dw_read_a(DwA& a, const float* sA, int q, int li, int lg)
 
 // ReLU of the pre-activation columns, the constant columns (ones at the bias
 // column, zeros beyond) and the forward's bf16 rounding of its inputs.  Envs
-// >= N of the last block need nothing:
-// their record and dz slots are zero (cleared at allocation, never written).
+// >= N of the last block need nothing: their dz slots are zero (cleared at
+// allocation; the one-env-per-lane sweep writes zeros there) and their
+// record slots are zero or finite copies of a batch env's values (the
+// one-env-per-lane forward writes those), so they add nothing.
 template <int G, bool BF16>
 __device__ inline void dw_prepare(DwOps<G>& o, int li) {
 #pragma unroll
@@ -826,8 +828,9 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   bw.n_parts = chunks * S;
   hipError_t e;
   for (int i = 0; i < BWD_NBUF; ++i) {
-    // zeroed once: the slots of envs >= N in the last 64-env block are never
-    // written and must read as zero in the weight-gradient pass
+    // zeroed once: the quarter-lane and split kernels never write the slots
+    // of envs >= N in the last 64-env block, which must then read as finite
+    // (record) and zero (cotangents) in the weight-gradient pass
     if ((e = hipMalloc(&bw.seg[i], rec_floats(K, N) * 4)) != hipSuccess) return e;
     if ((e = hipMemset(bw.seg[i], 0, rec_floats(K, N) * 4)) != hipSuccess) return e;
     if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
@@ -1004,8 +1007,8 @@ hipError_t run_backward_in(const DevCfg& c, const SimBufs& b, const BwdBufs& bw,
   p += up64((size_t)bw.n_parts * DW_SLOT);
   sb.gsum = p;
   // the array keeps whatever the last call on this device left in it; the
-  // record and cotangent slots of envs >= N in the last 64-env block are
-  // never written here and must read as zero
+  // record and cotangent slots of envs >= N in the last 64-env block may go
+  // unwritten here and must read as finite and zero
   // (k_fill: one float per thread; both sizes are below 2^31 by the
   // scratch bound the caller checked)
   hipLaunchKernelGGL(k_fill, dim3(nb((int)f_rec, 256)), dim3(256), 0, st, sb.seg[0], f_rec, 0.0f);

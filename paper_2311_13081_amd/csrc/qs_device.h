@@ -454,6 +454,20 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// Raw buffer view of a device span below 4 GiB: a load or store takes a
+// 32-bit per-lane byte offset and a wave-uniform byte offset, so the per-row
+// and per-step parts of an address stay in scalar registers and no 64-bit
+// address is formed per access.
+__device__ inline __amdgpu_buffer_rsrc_t span_rsrc(const float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline float bld1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline void bst1(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
 // tanh of the actor output without branches: tanh|x| = (1 - e) / (1 + e),
 // e = exp(-2|x|), on the hardware exponential and reciprocal; absolute error
 // about 2e-7 over the whole range.

@@ -29,7 +29,14 @@ namespace qs {
 // rec != NULL the backward's record (blocked by 64 envs) of the steps
 // t_base + t >= rec_from, a segment of rec_n steps.  The taped forward and
 // the recompute run this same code, so they agree bit for bit.
-template <bool MFMA, bool EXTRAS, bool BF16, bool TAPE>
+//
+// EXT: the actions come from ext_act and the kernel holds no actor; without
+// it the loop issues no vector-memory load at all.  (Vector loads and stores
+// share one completion counter: a wait for a load issued in the loop would
+// also wait for every record and output store issued before it -- with the
+// external-action loads only on a runtime branch, the waits at the branch's
+// join would drain the step's stores on every step.)
+template <bool MFMA, bool EXTRAS, bool BF16, bool TAPE, bool EXT = false>
 __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
@@ -37,7 +44,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
         const float* __restrict__ ck_in, float* __restrict__ rec, int rec_from, int rec_n) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
-  if (ext_act == nullptr) {
+  if constexpr (!EXT) {
     if constexpr (BF16)
       stage_actor_bf16(W, lds);
     else
@@ -85,14 +92,19 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     ep = b.ep[e];
     acc.load(b, N, e);
   }
-  // record layout of the wave's 64-env block (TAPE): blocks bb of the
-  // matrix-core tiles holding envs of the batch
+  // record (TAPE): byte offsets of the wave's 64-env block within a step's
+  // record and within the segment's action tape (wave uniform), of the
+  // lane's own column, and of its place in a matrix-core tile row.  Lanes of
+  // envs past the batch write their slots too (copies of the first env's
+  // values): the backward's cotangents there are zero.
   const int lane = threadIdx.x & 63;
-  const uint32_t colmask = (first + 0 * 16 + (lane & 15) < N ? 1u : 0u) |
-                           (first + 1 * 16 + (lane & 15) < N ? 2u : 0u) |
-                           (first + 2 * 16 + (lane & 15) < N ? 4u : 0u) |
-                           (first + 3 * 16 + (lane & 15) < N ? 8u : 0u);
-  const size_t rblk = (size_t)(first / RB) * REC_F * RB;
+  const uint32_t blk = __builtin_amdgcn_readfirstlane((uint32_t)(first / RB));
+  const uint32_t rstride = 4u * REC_F * (uint32_t)rb_pad(N);  // bytes per recorded step
+  const uint32_t s_rblk = 4u * blk * (REC_F * RB);
+  const uint32_t s_act = (uint32_t)rec_n * rstride + 4u * blk * (uint32_t)((NH + rec_n) * NA * RB);
+  const uint32_t v_own = 4u * (uint32_t)lane, v_tile = 4u * (uint32_t)(4 * (lane >> 4) * RB + (lane & 15));
+  const __amdgpu_buffer_rsrc_t rrec =
+      span_rsrc(rec, TAPE && rec ? 4u * (uint32_t)rec_floats(rec_n, N) : 0u);
   SetPoint sp;
   if (EXTRAS) sp.load(c, N, e);
   if (EXTRAS) {
@@ -131,7 +143,7 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     const int rt_step = gt - rec_from;
     const bool rec_on = TAPE && opaque((rec && rt_step >= 0) ? 1u : 0u) != 0u;
     float a[NA];
-    if (ext_act) {
+    if constexpr (EXT) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = ext_act[((size_t)t * NA + i) * N + eo];
     } else {
@@ -159,19 +171,19 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
           for (int i = 0; i < 9; ++i) Rm[i] = f[3 + i];
         }
       }
-      float* rt = rec_on ? rec + rec_step(rt_step, N) + rblk : nullptr;
+      // the step's block in the record
+      const uint32_t s_rt =
+          __builtin_amdgcn_readfirstlane((uint32_t)(rt_step > 0 ? rt_step : 0) * rstride + s_rblk);
       if constexpr (BF16) {
         actor_mfma_bf16(lds, so, Rm, H, z3);
       } else if constexpr (MFMA) {
         if (TAPE && rec_on) {
           uint32_t mb[4];
-          actor_mfma<true>(lds, so, Rm, H, z3, rt + (size_t)REC_Z1 * RB, rt + (size_t)REC_Z2 * RB,
-                           colmask, mb);
-          // every lane's words (its tiles may hold envs of the batch even
-          // where its own env is past the end)
+          const ZRec zr{rrec, s_rt + 4u * REC_Z1 * RB, s_rt + 4u * REC_Z2 * RB, v_tile};
+          actor_mfma<true>(lds, so, Rm, H, z3, &zr, mb);
 #pragma unroll
           for (int w = 0; w < 4; ++w)
-            rt[(size_t)(REC_M + w) * RB + opaque((uint32_t)lane)] = __uint_as_float(mb[w]);
+            bst1(__uint_as_float(mb[w]), rrec, v_own, s_rt + 4u * (REC_M + w) * RB);
         } else {
           actor_mfma(lds, so, Rm, H, z3);
         }
@@ -180,25 +192,25 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       }
 #pragma unroll
       for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
-      if (TAPE && rec_on && active) {
+      if (TAPE && rec_on) {
         // own-env rows: x_t, a_t, the observed state features; the step's
         // action (and, first, the checkpoint's history) on the action tape
-        const uint32_t lo = opaque((uint32_t)lane);
         const float of[18] = {so[0], so[1], so[2],  Rm[0],  Rm[1],  Rm[2],  Rm[3],  Rm[4],  Rm[5],
                               Rm[6], Rm[7], Rm[8], so[7], so[8], so[9], so[10], so[11], so[12]};
 #pragma unroll
-        for (int i = 0; i < NS; ++i) rt[(size_t)(REC_X + i) * RB + lo] = x[i];
+        for (int i = 0; i < NS; ++i) bst1(x[i], rrec, v_own, s_rt + 4u * (REC_X + i) * RB);
 #pragma unroll
-        for (int i = 0; i < NA; ++i) rt[(size_t)(REC_A + i) * RB + lo] = a[i];
+        for (int i = 0; i < NA; ++i) bst1(a[i], rrec, v_own, s_rt + 4u * (REC_A + i) * RB);
 #pragma unroll
-        for (int i = 0; i < 18; ++i) rt[(size_t)(REC_O + i) * RB + lo] = of[i];
-        float* act = rec + rec_act(rec_n, N) + (size_t)(first / RB) * ((NH + rec_n) * NA) * RB;
+        for (int i = 0; i < 18; ++i) bst1(of[i], rrec, v_own, s_rt + 4u * (REC_O + i) * RB);
         if (rt_step == 0) {
 #pragma unroll
-          for (int i = 0; i < NH * NA; ++i) act[(size_t)i * RB + lo] = H[i];
+          for (int i = 0; i < NH * NA; ++i) bst1(H[i], rrec, v_own, s_act + 4u * i * RB);
         }
+        const uint32_t s_a =
+            __builtin_amdgcn_readfirstlane(s_act + 4u * (uint32_t)(NH + rt_step) * (NA * RB));
 #pragma unroll
-        for (int i = 0; i < NA; ++i) act[(size_t)((NH + rt_step) * NA + i) * RB + lo] = a[i];
+        for (int i = 0; i < NA; ++i) bst1(a[i], rrec, v_own, s_a + 4u * i * RB);
       }
     }
     float u[NA];
@@ -268,9 +280,11 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
   // the bf16 actor option runs on the matrix-core kernel
   const bool bf = mfma && (c.flags & F_ACTOR_BF16) != 0;
-  auto k = bf ? (ex ? k_fused<true, true, true, false> : k_fused<true, false, true, false>)
-              : mfma ? (ex ? k_fused<true, true, false, false> : k_fused<true, false, false, false>)
-                     : (ex ? k_fused<false, true, false, false> : k_fused<false, false, false, false>);
+  auto k = ext_act ? (ex ? k_fused<false, true, false, false, true>
+                         : k_fused<false, false, false, false, true>)
+           : bf ? (ex ? k_fused<true, true, true, false> : k_fused<true, false, true, false>)
+           : mfma ? (ex ? k_fused<true, true, false, false> : k_fused<true, false, false, false>)
+                  : (ex ? k_fused<false, true, false, false> : k_fused<false, false, false, false>);
   hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones, states,
                      nullptr, 1, nullptr, nullptr, 0, 0);
   return hipGetLastError();

@@ -67,6 +67,12 @@ __device__ inline void stage_reverse1(const float* __restrict__ W, float* lds, b
   }
 }
 
+// v where bit b of the mask word m is set, +0 elsewhere (the sign-extended
+// one-bit field is all ones or zero)
+__device__ inline float keep_if(float v, uint32_t m, int b) {
+  return __uint_as_float(__float_as_uint(v) & (uint32_t)__builtin_amdgcn_sbfe((int)m, b, 1));
+}
+
 // Inputs of one reverse step: the own env's recorded state and action and
 // cotangents, and the lane's ReLU mask words (column lane of the block).
 struct StepIn1 {
@@ -74,16 +80,20 @@ struct StepIn1 {
   uint32_t m[4];
 };
 
-__device__ inline void load_step1(StepIn1& in, const float* __restrict__ rt, size_t roff,
-                                  size_t moff, const float* __restrict__ d_rewards,
+// sr: byte offset of the step's block in the record; vown / vlane: the
+// lane's byte offsets of its env's column and of its own column.
+__device__ inline void load_step1(StepIn1& in, __amdgpu_buffer_rsrc_t rrec, uint32_t sr,
+                                  uint32_t vown, uint32_t vlane,
+                                  const float* __restrict__ d_rewards,
                                   const float* __restrict__ d_states, int t, int N, int e) {
   const uint32_t eo = opaque((uint32_t)e);
 #pragma unroll
-  for (int w = 0; w < 4; ++w) in.m[w] = __float_as_uint(rt[(size_t)(REC_M + w) * RB + moff]);
+  for (int w = 0; w < 4; ++w)
+    in.m[w] = __float_as_uint(bld1(rrec, vlane, sr + 4u * (REC_M + w) * RB));
 #pragma unroll
-  for (int i = 0; i < NS; ++i) in.x[i] = rt[(size_t)(REC_X + i) * RB + roff];
+  for (int i = 0; i < NS; ++i) in.x[i] = bld1(rrec, vown, sr + 4u * (REC_X + i) * RB);
 #pragma unroll
-  for (int i = 0; i < NA; ++i) in.a[i] = rt[(size_t)(REC_A + i) * RB + roff];
+  for (int i = 0; i < NA; ++i) in.a[i] = bld1(rrec, vown, sr + 4u * (REC_A + i) * RB);
   in.dR = d_rewards ? d_rewards[(size_t)t * N + eo] : 1.0f;
 #pragma unroll
   for (int i = 0; i < NS; ++i)
@@ -110,18 +120,16 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
   const int env = env0 + lane;
   const bool active = env < N;
   const int e = active ? env : env0;
-  // column env of block bb in the matrix-core tiles (shadowed past N)
-  uint32_t col[4];
-  bool col_ok[4];
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb) {
-    col_ok[bb] = env0 + 16 * bb + li < N;
-    col[bb] = col_ok[bb] ? 16 * bb + li : 0;
-  }
-  const size_t rbase = (size_t)(env0 / RB) * REC_F * RB;  // block in a step's record
-  const size_t zbase = (size_t)(env0 / RB) * DZ_F * RB;   // block in a step's cotangents
-  const size_t roff = rbase + (size_t)(e - env0);
-  const size_t moff = rbase + (size_t)lane;
+  // byte offsets: the block's record and cotangent spans within a step (wave
+  // uniform), the lane's env column, its own column, and its place in a
+  // matrix-core tile row (row 4 lg, column li)
+  const uint32_t rbp = (uint32_t)rb_pad(N);
+  const uint32_t blk = __builtin_amdgcn_readfirstlane(env0 / RB);
+  const uint32_t s_rblk = 4u * blk * (REC_F * RB), s_zblk = 4u * blk * (DZ_F * RB);
+  const uint32_t vown = 4u * (uint32_t)(e - env0), vlane = 4u * (uint32_t)lane;
+  const uint32_t vtile = 4u * (uint32_t)(4 * lg * RB + li);
+  const __amdgpu_buffer_rsrc_t rrec = span_rsrc(rec, 4u * (uint32_t)rec_floats(n, N));
+  const __amdgpu_buffer_rsrc_t rdz = span_rsrc(dz, 4u * (uint32_t)n * DZ_F * rbp);
 
   float th[NP];
 #pragma unroll
@@ -156,23 +164,27 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
   for (int i = 0; i < NP; ++i) gth[i] = gth_io[(size_t)i * N + e];
 
   StepIn1 cur, nxt;
-  load_step1(cur, rec + rec_step(n - 1, N), roff, moff, d_rewards, d_states, t0 + n - 1, N, e);
+  load_step1(cur, rrec, 4u * (uint32_t)(n - 1) * (REC_F * rbp) + s_rblk, vown, vlane, d_rewards,
+             d_states, t0 + n - 1, N, e);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
-    const float* rt = rec + rec_step(tl, N);
-    float* dzt = dz + (size_t)tl * DZ_F * rb_pad(N);
+    const uint32_t sz = 4u * (uint32_t)tl * (DZ_F * rbp) + s_zblk;  // the step's cotangents
     const int tp = tl > 0 ? tl - 1 : 0;
 
     float gx[NS], ga[NA];
     reverse_dynamics(c, B, th, renorm, cur.x, cur.a, cur.dR, ls, lR[NH - HR - 1], gx, ga, gth);
     // the next step's inputs, in flight during the input VJP below
-    load_step1(nxt, rec + rec_step(tp, N), roff, moff, d_rewards, d_states, t0 + tp, N, e);
-    const uint32_t own = opaque((uint32_t)(zbase + lane));
+    load_step1(nxt, rrec, 4u * (uint32_t)tp * (REC_F * rbp) + s_rblk, vown, vlane, d_rewards,
+               d_states, t0 + tp, N, e);
+    // Lanes of envs >= N take dz3 = 0: the layer products keep envs apart
+    // (one env per column), so their columns of dz2 and dz1 are zero too and
+    // every lane stores unconditionally -- zeros into the slots of envs >= N,
+    // which the weight-gradient pass expects there.
     float d3[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      d3[i] = ga[i] * (1.0f - cur.a[i] * cur.a[i]);
-      if (active) dzt[(size_t)(2 * NHID + i) * RB + own] = d3[i];
+      d3[i] = active ? ga[i] * (1.0f - cur.a[i] * cur.a[i]) : 0.0f;
+      bst1(d3[i], rdz, vlane, sz + 4u * (2 * NHID + i) * RB);
     }
     // dz2 = (W3^T dz3) [z2 > 0]: one rank-1 update per action
     f16 d2[4];
@@ -191,10 +203,8 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 4 * bb + v;
-          const bool on = (cur.m[2 + (n2 >> 1)] >> (16 * (n2 & 1) + r)) & 1u;
-          d2[n2][r] = on ? d2[n2][r] : 0.0f;
-          if (col_ok[bb])
-            dzt[zbase + (size_t)(NHID + 16 * n2 + 4 * lg + v) * RB + 16 * bb + li] = d2[n2][r];
+          d2[n2][r] = keep_if(d2[n2][r], cur.m[2 + (n2 >> 1)], 16 * (n2 & 1) + r);
+          bst1(d2[n2][r], rdz, vtile, sz + 4u * ((NHID + 16 * n2 + v) * RB + 16 * bb));
         }
     // dz1 = (W2^T dz2) [z1 > 0]: chains over the dz2 registers, 16 per
     // (tile, block)
@@ -221,10 +231,8 @@ k_bwd_reverse1(DevCfg c, const float* __restrict__ theta, const float* __restric
       for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const bool on = (cur.m[mt >> 1] >> (16 * (mt & 1) + 4 * bb + r)) & 1u;
-          d1[mt][bb][r] = on ? d1[mt][bb][r] : 0.0f;
-          if (col_ok[bb])
-            dzt[zbase + (size_t)(16 * mt + 4 * lg + r) * RB + 16 * bb + li] = d1[mt][bb][r];
+          d1[mt][bb][r] = keep_if(d1[mt][bb][r], cur.m[mt >> 1], 16 * (mt & 1) + 4 * bb + r);
+          bst1(d1[mt][bb][r], rdz, vtile, sz + 4u * ((16 * mt + r) * RB + 16 * bb));
         }
 
     // the history adjoint moves one slot older: H_t[s] feeds H_{t+1}[s - 1]

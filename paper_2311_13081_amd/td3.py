@@ -331,6 +331,9 @@ def main(argv=None):
     ap.add_argument("--no-recalc", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None, help="JSON lines of the evaluation records")
+    ap.add_argument("--save", default=None, help="file for the trained actor's flat parameters")
+    ap.add_argument("--track", action="store_true",
+                    help="after training, the Lissajous tracking errors of the trained actor")
     a = ap.parse_args(argv)
     cfg = TD3Config(total_steps=a.steps, n_envs=a.n_envs,
                     updates_per_env_step=a.updates_per_env_step, eval_every=a.eval_every,
@@ -345,7 +348,13 @@ def main(argv=None):
             fh.write(line + "\n")
             fh.flush()
     print(json.dumps({"config": asdict(cfg)}), flush=True)
-    train(cfg, log)
+    res = train(cfg, log)
+    flat = res["actor"].flat().detach()
+    if a.save:
+        torch.save(flat.cpu(), a.save)
+    if a.track:
+        from .tracking import tracking_table
+        log({"tracking": tracking_table(flat, res["env_cfg"])})
     if fh:
         fh.close()
 

@@ -227,18 +227,21 @@ def test_split_kernels_match_quarter_lane_bitwise(pkg, oracle_lib):
     assert np.array_equal(gps[0], gps[1])
 
 
-@pytest.mark.parametrize("T,K", [(24, 8), (40, 8)])
-def test_backward_twice_on_one_tape(pkg, oracle_lib, T, K):
+@pytest.mark.parametrize("n,T,K", [(300, 24, 8), (300, 40, 8), (65573, 40, 8)])
+def test_backward_twice_on_one_tape(pkg, oracle_lib, n, T, K):
     """The taped rollout writes the backward's record of its last segment, so
     the first backward skips that recompute.  With more segments than record
     buffers (40 / 8 = 5 > 3) the backward reuses that buffer and a second
     backward on the same tape recomputes the segment; with 3 segments it
-    still holds it.  Either way the gradients repeat bit for bit."""
-    cfg, sim, ref, th = setup(pkg, oracle_lib, 300, T, K, dr=1)
-    a = sim.actor_tensor(wl.xavier_actor(0))
+    still holds it.  Either way the gradients repeat bit for bit: the
+    recompute reproduces the taped forward's record exactly.  65573 envs
+    (a ragged last wave) run the one-env-per-lane taped kernel and sweep."""
+    cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
+    a = sim.actor_tensor(wl.sysid_actor(0) if n > 16384 else wl.xavier_actor(0))
     sim.rollout(a, T, rewards=False, dones=False, states=False, record_tape=True)
-    g1 = [np_(x) for x in sim.backward(a)]
+    g1 = [np_(x).copy() for x in sim.backward(a)]
     g2 = [np_(x) for x in sim.backward(a)]
+    assert np.all(np.isfinite(g1[0])) and np.all(np.isfinite(g1[1]))
     assert np.array_equal(g1[0], g2[0]) and np.array_equal(g1[1], g2[1])
     sim.close()
 
@@ -374,9 +377,11 @@ def test_sysid16384_full_size(pkg, oracle_lib):
     sim.close()
 
 
-def test_grad65536_dr_full_size(pkg, oracle_lib):
+@pytest.mark.parametrize("K", [16, 64])
+def test_grad65536_dr_full_size(pkg, oracle_lib, K):
     """Policy gradient at the large batch's size: 65536 randomised envs,
-    horizon 64, checkpoints every 16, the hover-biased policy.  The backward
+    horizon 64, checkpoints every K, the hover-biased policy (K = 64: one
+    segment, recorded whole by the taped forward, nothing recomputed).  The backward
     is linear in its cotangents and the envs are independent, so with reward
     cotangent one on a sample of envs and zero elsewhere the actor gradient
     is the sample's own and every other env's parameter gradient is exactly
@@ -384,7 +389,7 @@ def test_grad65536_dr_full_size(pkg, oracle_lib):
     With the full cotangent the gradients are finite and a second backward
     on the same tape repeats them bit for bit."""
     orc = oracle_lib
-    cfg = wl.workload_config("grad65536_dr")
+    cfg = wl.workload_config("grad65536_dr", ckpt_every=K)
     H = wl.workload_steps("grad65536_dr")
     N = cfg["n_envs"]
     sim = pkg.QuadSim(cfg)
@@ -421,7 +426,7 @@ def test_grad65536_dr_full_size(pkg, oracle_lib):
     gps = gp[:, ids].T
     sc = param_scale(cfg, ref.theta)
     ep = param_grad_err(gps, gth, sc)
-    print(f"grad65536_dr sample of {len(ids)}: actor rel err {ea:.2e}, "
+    print(f"grad65536_dr K={K} sample of {len(ids)}: actor rel err {ea:.2e}, "
           f"params max rel err {ep.max():.2e}")
     assert ea < GRAD_TOL
     assert ep.max() < GRAD_TOL
