@@ -437,11 +437,6 @@ def main():
     T = wl.workload_steps(name)
     N = cfg["n_envs"]
     W = wl.xavier_actor(0)
-    if args.only_fwd_bwd:
-        only = args.fwd_bwd_legs.split(",") if args.fwd_bwd_legs else None
-        print(json.dumps({"fwd_bwd": fwd_bwd_legs(torch, pkg, W, only)}), flush=True)
-        return
-
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -450,6 +445,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_fwd_bwd:
+        only = args.fwd_bwd_legs.split(",") if args.fwd_bwd_legs else None
+        print(json.dumps({"fwd_bwd": fwd_bwd_legs(torch, pkg, W, only)}), flush=True)
+        return
     sim = pkg.QuadSim(cfg)
     actor = sim.actor_tensor(W)
     if args.variant == "auto":

@@ -47,43 +47,34 @@ constexpr int LDS_FLOATS = LDS_FLOATS_F32 > MB_TOTAL ? LDS_FLOATS_F32 : MB_TOTAL
 
 template <bool MFMA>
 __device__ inline void stage_actor(const float* __restrict__ W, float* lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
   if (MFMA) {
-    for (int i = tid; i < NHID * M_W1_LD; i += nt) {
+    // W1 with the bias as column 0, rows padded to M_W1_LD
+    stage_lds(lds + M_W1, NHID * M_W1_LD, W, [](int i) {
       const int r = i / M_W1_LD, k = i % M_W1_LD;
-      lds[M_W1 + i] = k == 0 ? W[OFF_B1 + r] : k <= NO ? W[OFF_W1 + r * NO + k - 1] : 0.0f;
-    }
-    for (int i = tid; i < NHID * M_W2_LD; i += nt) {
+      return k == 0 ? OFF_B1 + r : k <= NO ? OFF_W1 + r * NO + k - 1 : -1;
+    });
+    stage_lds(lds + M_W2, NHID * M_W2_LD, W, [](int i) {
       const int r = i / M_W2_LD, k = i % M_W2_LD;
-      lds[M_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
-    }
-    for (int i = tid; i < NA * M_W2_LD; i += nt) {
+      return k < NHID ? OFF_W2 + r * NHID + k : -1;
+    });
+    stage_lds(lds + M_W3, NA * M_W2_LD, W, [](int i) {
       const int r = i / M_W2_LD, k = i % M_W2_LD;
-      lds[M_W3 + i] = k < NHID ? W[OFF_W3 + r * NHID + k] : 0.0f;
-    }
-    for (int i = tid; i < NHID; i += nt) {
-      lds[M_B1 + i] = W[OFF_B1 + i];
-      lds[M_B2 + i] = W[OFF_B2 + i];
-    }
-    for (int i = tid; i < 4; i += nt) lds[M_B3 + i] = W[OFF_B3 + i];
+      return k < NHID ? OFF_W3 + r * NHID + k : -1;
+    });
+    stage_lds(lds + M_B1, NHID, W, [](int i) { return OFF_B1 + i; });
+    stage_lds(lds + M_B2, NHID, W, [](int i) { return OFF_B2 + i; });
+    stage_lds(lds + M_B3, NA, W, [](int i) { return OFF_B3 + i; });
   } else {
-    for (int i = tid; i < NO * NHID; i += nt) {
-      const int k = i / NHID, n = i % NHID;
-      lds[V_W1T + i] = W[OFF_W1 + n * NO + k];
-    }
-    for (int i = tid; i < NHID * NHID; i += nt) {
-      const int k = i / NHID, n = i % NHID;
-      lds[V_W2T + i] = W[OFF_W2 + n * NHID + k];
-    }
-    for (int i = tid; i < NHID * NA; i += nt) {
-      const int k = i / NA, n = i % NA;
-      lds[V_W3T + i] = W[OFF_W3 + n * NHID + k];
-    }
-    for (int i = tid; i < NHID; i += nt) {
-      lds[V_B1 + i] = W[OFF_B1 + i];
-      lds[V_B2 + i] = W[OFF_B2 + i];
-    }
-    for (int i = tid; i < NA; i += nt) lds[V_B3 + i] = W[OFF_B3 + i];
+    // transposed: [input][neuron]
+    stage_lds(lds + V_W1T, NO * NHID, W,
+              [](int i) { return OFF_W1 + (i % NHID) * NO + i / NHID; });
+    stage_lds(lds + V_W2T, NHID * NHID, W,
+              [](int i) { return OFF_W2 + (i % NHID) * NHID + i / NHID; });
+    stage_lds(lds + V_W3T, NHID * NA, W,
+              [](int i) { return OFF_W3 + (i % NA) * NHID + i / NA; });
+    stage_lds(lds + V_B1, NHID, W, [](int i) { return OFF_B1 + i; });
+    stage_lds(lds + V_B2, NHID, W, [](int i) { return OFF_B2 + i; });
+    stage_lds(lds + V_B3, NA, W, [](int i) { return OFF_B3 + i; });
   }
 }
 
@@ -175,18 +166,19 @@ __device__ inline void layer3_one_lane(const float* lds, int w3, int b3off, cons
 //           Each lane group ends with a partial sum over its quarter of the
 //           neurons; two swap-and-add rounds across 32 and 16 lanes add the
 //           quarters and leave output o of env (lane) in every lane.
-//  REC: also store the layer pre-activations into the backward's blocked
-//  record (zr: the record span, the byte offsets of the z1 and z2 rows of
-//  the wave's 64-env block in this step's record, and the lane's offset
-//  4 (4 lg 64 + li) in a tile row); register 4 bb + v (neuron 16 n + 4 lg + v
-//  of env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li.  Every
-//  column is written, those of envs past the batch with the values of the
-//  lanes that shadow them.  mbits receives the lane's ReLU masks in the same
-//  layout (bit 16 n + 4 bb + v of word n / 2: layer 1, words 0-1; layer 2,
-//  words 2-3).
+//  REC: when rec_on (wave uniform), also store the layer pre-activations
+//  and the ReLU masks into the backward's blocked record (zr: the record
+//  span, the byte offsets of the z1, z2 and mask rows of the wave's 64-env
+//  block in this step's record, the lane's offset 4 (4 lg 64 + li) in a tile
+//  row and its own column's offset).  Register 4 bb + v (neuron 16 n + 4 lg
+//  + v of env 16 bb + li) goes to row 16 n + 4 lg + v, column 16 bb + li.
+//  Every column is written, those of envs past the batch with the values of
+//  the lanes that shadow them.  The mask words, in the same layout (bit 16 n
+//  + 4 bb + v of word n / 2: layer 1, words 0-1; layer 2, words 2-3), go to
+//  the lane's own column of the mask rows.
 struct ZRec {
   __amdgpu_buffer_rsrc_t r;
-  uint32_t s1, s2, v;
+  uint32_t s1, s2, v, sm, vo;
 };
 // Sets bit 16 h + r of w (r = 15 .. 0 in turn, w shifted left each time) when
 // z[r] > 0: the two halves of a mask word are filled high half first.
@@ -197,7 +189,7 @@ __device__ inline uint32_t push_mask_bit(uint32_t w, float z) {
 template <bool REC = false>
 __device__ inline void actor_mfma(const float* lds, const float s[NS], const float Rm[9],
                                   const float H[NH * NA], float z3out[NA],
-                                  const ZRec* zr = nullptr, uint32_t* mbits = nullptr) {
+                                  const ZRec* zr = nullptr, bool rec_on = false) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const f16 zero16 = {};
@@ -223,7 +215,7 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       }
     }
   }
-  if (REC) {
+  if (REC && rec_on) {
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
@@ -238,7 +230,7 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       for (int h = 1; h >= 0; --h)
 #pragma unroll
         for (int r = 15; r >= 0; --r) m = push_mask_bit(m, acc1[2 * w + h][r]);
-      mbits[w] = m;
+      bst1(__uint_as_float(m), zr->r, zr->vo, zr->sm + 4u * w * 64);
     }
   }
 #pragma unroll
@@ -261,7 +253,7 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
           acc2[n2][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
               w[v], acc1[n][4 * bb + v], (n == 0 && v == 0) ? b2 : acc2[n2][bb], 0, 0, 0);
     }
-  if (REC) {
+  if (REC && rec_on) {
     // register r of acc2[n2][bb]: neuron 16 n2 + 4 lg + r of env 16 bb + li
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2)
@@ -277,7 +269,7 @@ __device__ inline void actor_mfma(const float* lds, const float s[NS], const flo
       for (int h = 1; h >= 0; --h)
 #pragma unroll
         for (int q = 15; q >= 0; --q) m = push_mask_bit(m, acc2[2 * w + h][q >> 2][q & 3]);
-      mbits[2 + w] = m;
+      bst1(__uint_as_float(m), zr->r, zr->vo, zr->sm + 4u * (2 + w) * 64);
     }
   }
 #pragma unroll

@@ -68,20 +68,18 @@ __host__ __device__ constexpr int r_phi(int c, int k) {
 }
 
 __device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bool bf16) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < NA * NHID; i += nt) lds[R_W3 + i] = fwd_weight(W[OFF_W3 + i], bf16);
-  for (int idx = tid; idx < NHID * NHID; idx += nt) {
+  stage_lds(lds + R_W3, NA * NHID, W, [](int i) { return OFF_W3 + i; }, bf16);
+  stage_lds(lds + R_W2P, NHID * NHID, W, [](int idx) {
     const int v = idx & 3, i = (idx >> 2) & 15, m = (idx >> 6) & 3, g = (idx >> 8) & 3,
               n = idx >> 10;
-    lds[R_W2P + idx] = fwd_weight(W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i], bf16);
-  }
-  for (int idx = tid; idx < 10 * 16 * NHID; idx += nt) {
+    return OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * m + i;
+  }, bf16);
+  stage_lds(lds + R_W1P, 10 * 16 * NHID, W, [](int idx) {
     const int v = idx & 3, i = (idx >> 2) & 15, rest = idx >> 6;  // rest = (m*4 + g)*10 + p
     const int p = rest % 10, g = (rest / 10) & 3, m = rest / 40;
     const int feat = r_phi(4 * p + (i & 3), i >> 2);
-    lds[R_W1P + idx] =
-        feat >= 0 ? fwd_weight(W[OFF_W1 + (16 * m + 4 * g + v) * NO + feat], bf16) : 0.0f;
-  }
+    return feat >= 0 ? OFF_W1 + (16 * m + 4 * g + v) * NO + feat : -1;
+  }, bf16);
 }
 
 // Inputs of one reverse step: the recorded state and action, this lane's

@@ -454,6 +454,33 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// Stages weights into LDS: dst[i] = W[src] with src = index(i) (rounded to
+// bf16 when bf16), or 0 where index(i) < 0, for i < n; the workgroup's
+// threads stride over i, eight elements at a time: each thread issues its
+// eight (unconditional, in-bounds) loads before it waits for the first,
+// instead of one load and one wait per element.
+template <typename Index>
+__device__ inline void stage_lds(float* dst, int n, const float* __restrict__ W, Index index,
+                                 bool bf16 = false) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int base = tid; base < n; base += 8 * nt) {
+    float v[8];
+    int src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j * nt;
+      src[j] = index(i < n ? i : n - 1);
+      v[j] = W[src[j] >= 0 ? src[j] : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j * nt;
+      const float w = bf16 ? (float)(__bf16)v[j] : v[j];
+      if (i < n) dst[i] = src[j] >= 0 ? w : 0.0f;
+    }
+  }
+}
+
 // Raw buffer view of a device span below 4 GiB: a load or store takes a
 // 32-bit per-lane byte offset and a wave-uniform byte offset, so the per-row
 // and per-step parts of an address stay in scalar registers and no 64-bit

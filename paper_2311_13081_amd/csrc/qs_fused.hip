@@ -141,7 +141,9 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
     }
     const int rt_step = gt - rec_from;
-    const bool rec_on = TAPE && opaque((rec && rt_step >= 0) ? 1u : 0u) != 0u;
+    // wave uniform: the record branches below are scalar branches around one
+    // copy of the actor
+    const bool rec_on = TAPE && rec != nullptr && rt_step >= 0;
     float a[NA];
     if constexpr (EXT) {
 #pragma unroll
@@ -177,13 +179,10 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       if constexpr (BF16) {
         actor_mfma_bf16(lds, so, Rm, H, z3);
       } else if constexpr (MFMA) {
-        if (TAPE && rec_on) {
-          uint32_t mb[4];
-          const ZRec zr{rrec, s_rt + 4u * REC_Z1 * RB, s_rt + 4u * REC_Z2 * RB, v_tile};
-          actor_mfma<true>(lds, so, Rm, H, z3, &zr, mb);
-#pragma unroll
-          for (int w = 0; w < 4; ++w)
-            bst1(__uint_as_float(mb[w]), rrec, v_own, s_rt + 4u * (REC_M + w) * RB);
+        if constexpr (TAPE) {
+          const ZRec zr{rrec, s_rt + 4u * REC_Z1 * RB, s_rt + 4u * REC_Z2 * RB, v_tile,
+                        s_rt + 4u * REC_M * RB, v_own};
+          actor_mfma<true>(lds, so, Rm, H, z3, &zr, rec_on);
         } else {
           actor_mfma(lds, so, Rm, H, z3);
         }

@@ -23,26 +23,23 @@ __host__ __device__ constexpr int q_phi(int c, int k) {
 }
 
 __device__ inline void stage_q(const float* __restrict__ W, float* lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
   // W1 in PHI order: [quarter][neuron][chunk], pitch Q_W1_P
-  for (int idx = tid; idx < NHID * 4 * Q_W1_P; idx += nt) {
+  stage_lds(lds + Q_W1, NHID * 4 * Q_W1_P, W, [](int idx) {
     const int c = idx % Q_W1_P, rest = idx / Q_W1_P, nrn = rest % NHID, k = rest / NHID;
     const int f = c < Q_C ? q_phi(c, k) : -1;
-    lds[Q_W1 + idx] = f >= 0 ? W[OFF_W1 + nrn * NO + f] : 0.0f;
-  }
-  for (int i = tid; i < NHID * 68; i += nt) {
+    return f >= 0 ? OFF_W1 + nrn * NO + f : -1;
+  });
+  stage_lds(lds + Q_W2, NHID * 68, W, [](int i) {
     const int r = i / 68, k = i % 68;
-    lds[Q_W2 + i] = k < NHID ? W[OFF_W2 + r * NHID + k] : 0.0f;
-  }
-  for (int i = tid; i < NA * 68; i += nt) {
+    return k < NHID ? OFF_W2 + r * NHID + k : -1;
+  });
+  stage_lds(lds + Q_W3, NA * 68, W, [](int i) {
     const int r = i / 68, k = i % 68;
-    lds[Q_W3 + i] = k < NHID ? W[OFF_W3 + r * NHID + k] : 0.0f;
-  }
-  for (int i = tid; i < NHID; i += nt) {
-    lds[Q_B1 + i] = W[OFF_B1 + i];
-    lds[Q_B2 + i] = W[OFF_B2 + i];
-  }
-  for (int i = tid; i < NA; i += nt) lds[Q_B3 + i] = W[OFF_B3 + i];
+    return k < NHID ? OFF_W3 + r * NHID + k : -1;
+  });
+  stage_lds(lds + Q_B1, NHID, W, [](int i) { return OFF_B1 + i; });
+  stage_lds(lds + Q_B2, NHID, W, [](int i) { return OFF_B2 + i; });
+  stage_lds(lds + Q_B3, NA, W, [](int i) { return OFF_B3 + i; });
 }
 
 

@@ -43,28 +43,29 @@ constexpr int L_W3T = 0, L_W2Q = L_W3T + NHID * NA, L_W1Q = L_W2Q + NHID * NHID,
               L_TOTAL = L_W1Q + 10 * 4 * 4 * 16 * 4;
 // History adjoint: the older HR slots of each env in a per-wave ring in LDS
 // ([HR][4][64 lanes] after the weights: moving the slots one step older is a
-// turn of the ring), the newest NH - HR in registers.  HR = 24 fills the
-// LDS with four waves per workgroup; all 32 in registers would not fit.
-constexpr int HR = 24;
+// turn of the ring), the newest NH - HR in registers.  Each step adds the
+// observation's share into every slot: in the ring that is a read, an add
+// and a write of LDS per value, in registers an accumulator-register move or
+// two.  Of HR = 4, 8, 16 and 24 (the largest the LDS holds for four waves),
+// 8 measured fastest (377 us per 16-step segment at 65536 envs against 395
+// for 24); with fewer the registers no longer fit beside the rest.
+constexpr int HR = 8;
 constexpr int L_RING = HR * NA * 64;
 constexpr int L_BYTES = (L_TOTAL + 4 * L_RING) * 4;
 static_assert(L_BYTES <= 160 * 1024, "weights and four history rings must fit in LDS");
 
 __device__ inline void stage_reverse1(const float* __restrict__ W, float* lds, bool bf16) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < NHID * NA; i += nt) {
-    const int n = i >> 2, a = i & 3;
-    lds[L_W3T + i] = fwd_weight(W[OFF_W3 + a * NHID + n], bf16);
-  }
-  for (int i = tid; i < NHID * NHID; i += nt) {
+  stage_lds(lds + L_W3T, NHID * NA, W,
+            [](int i) { return OFF_W3 + (i & 3) * NHID + (i >> 2); }, bf16);
+  stage_lds(lds + L_W2Q, NHID * NHID, W, [](int i) {
     const int v = i & 3, li = (i >> 2) & 15, g = (i >> 6) & 3, n = (i >> 8) & 3, mt = i >> 10;
-    lds[L_W2Q + i] = fwd_weight(W[OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * mt + li], bf16);
-  }
-  for (int i = tid; i < 10 * 4 * 4 * 16 * 4; i += nt) {
+    return OFF_W2 + (16 * n + 4 * g + v) * NHID + 16 * mt + li;
+  }, bf16);
+  stage_lds(lds + L_W1Q, 10 * 4 * 4 * 16 * 4, W, [](int i) {
     const int v = i & 3, li = (i >> 2) & 15, g = (i >> 6) & 3, mt = (i >> 8) & 3, p = i >> 10;
     const int f = 16 * p + li, neuron = 16 * mt + 4 * g + v;
-    lds[L_W1Q + i] = f < NO ? fwd_weight(W[OFF_W1 + neuron * NO + f], bf16) : 0.0f;
-  }
+    return f < NO ? OFF_W1 + neuron * NO + f : -1;
+  }, bf16);
 }
 
 // v where bit b of the mask word m is set, +0 elsewhere (the sign-extended
