@@ -148,11 +148,12 @@ def cpu_baseline(cfg, W, seconds):
     oracle.build(force=False)
     nthreads = min(os.cpu_count() or 1, 64)
     N = cfg["n_envs"]
-    probe_ids = np.linspace(0, N - 1, nthreads * 4).astype(np.uint32)
+    # rate probe large enough that thread start-up does not dominate it
+    probe_ids = np.linspace(0, N - 1, min(N, nthreads * 32)).astype(np.uint32)
     b = oracle.Batch.init(cfg, len(probe_ids), ids=probe_ids)
     t0 = time.perf_counter()
-    b.rollout(W, 20, nthreads=nthreads)
-    rate = len(probe_ids) * 20 / max(time.perf_counter() - t0, 1e-6)
+    b.rollout(W, 40, nthreads=nthreads)
+    rate = len(probe_ids) * 40 / max(time.perf_counter() - t0, 1e-6)
     n = int(max(nthreads, min(N, rate * seconds / 200)))
     steps = int(max(20, min(1000, rate * seconds / n)))
     ids = np.linspace(0, N - 1, n).astype(np.uint32)
@@ -161,6 +162,7 @@ def cpu_baseline(cfg, W, seconds):
     b.rollout(W, steps, nthreads=nthreads)
     dt = time.perf_counter() - t0
     # one thread, on a tenth of the time budget
+    probe_ids = probe_ids[:64]
     n1 = len(probe_ids)
     steps1 = int(max(20, min(1000, n * steps / dt / nthreads * seconds / 10 / n1)))
     b1 = oracle.Batch.init(cfg, n1, ids=probe_ids)
@@ -334,12 +336,13 @@ def fwd_bwd(torch, pkg, name, K, W, warmup=1, bf16=False):
     roof["flop_per_env_step"] = FLOP_FWD_BWD_ENV_STEP
     K = cfg["ckpt_every"]
     # checkpoints of (state, history, counters): 147 floats per env; the
-    # backward's record: 171 floats per env and step (state features, x, a,
-    # both layers' pre-activations, the step's action) and the 128-float
-    # action history at the start of the recorded span
+    # backward's record: 171 floats per env and step (x, a, both layers'
+    # pre-activations, the 18 observed state features, 4 ReLU mask words)
+    # plus the action tape: the 128-float history at the start of the
+    # recorded span and 4 floats per step
     mem = {"device_bytes_of_handle": handle_bytes,
            "tape_bytes": (H // K + 1) * 147 * N * 4,
-           "records_of_whole_horizon_bytes": (H * 171 + 128) * N * 4}
+           "records_of_whole_horizon_bytes": (H * (171 + 4) + 128) * N * 4}
     return {"env_steps_per_s": rate, "ms_per_fwd_bwd": dt * 1e3, "n_envs": N,
             "horizon": H, "ckpt_every": K, "actor": "bf16" if bf16 else "f32",
             "roofline": roof, "memory": mem}
