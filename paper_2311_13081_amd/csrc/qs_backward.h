@@ -10,7 +10,8 @@ namespace qs {
 constexpr int BWD_NBUF = 3;
 struct BwdBufs {
   int N = 0, K = 0, H = 0;
-  int n_parts = 0;                    // partial slots of the weight gradients (chunks x groups)
+  int n_parts = 0;                    // partial slots of the weight gradients (dw_gx x groups)
+  int dw_gx = 1;                      // weight-gradient workgroups along the 64-env chunks
   int dw_groups = 1;                  // step groups per 64-env chunk
   int n_cu = 0;                       // compute units of the device
   float* seg[BWD_NBUF] = {};          // [K] steps of REC_F blocked rows (rb_at) per env: record

@@ -454,9 +454,21 @@ __device__ inline f4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff
 // (the source step depends on the column).
 __host__ __device__ constexpr bool dw_hist(int t) { return t >= 1 && t < 10; }
 
+// Tiles 2..9 hold action-tape values only.  Their B operands come from an
+// LDS copy of the block's tape window: the DW_CH steps [w0, w0 + DW_CH)
+// observe slots w0 .. w0 + DW_CH + NH - 2, which the workgroup copies in
+// (rows (slot - w0) * NA + a, pitch DW_AP) and refills every DW_CH steps, so
+// each tape value is read from memory once per window instead of once for
+// each of the 32 steps that observe it.  Tile 1 mixes the last two state
+// features with history and stays on the record.
+constexpr int DW_CH = 16, DW_TW = (DW_CH + NH) * NA, DW_TBUF = DW_TW * DW_AP;
+static_assert(DW_CH % 2 == 0, "a window holds whole iterations (one step per half)");
+__host__ __device__ constexpr bool dw_tape(int t) { return t >= 2 && t < 10; }
+
 // Addressing of one step, in bytes from the dz and record buffers: uniform
 // offsets of this step's block, and the per-lane offsets of the history
-// tiles.
+// tiles (in floats from the LDS tape window for tiles 2..9, w0 its first
+// slot).
 template <int G>
 struct DwAddr {
   uint32_t dzs, rs;
@@ -464,7 +476,8 @@ struct DwAddr {
 };
 
 template <int G>
-__device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, int li, int lg) {
+__device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, int li, int lg,
+                               int w0) {
   const uint32_t rbp = (uint32_t)rb_pad(N), rstep = (uint32_t)REC_F * rbp;
   d.dzs = 4u * ((uint32_t)tl * (DZ_F * rbp) + (uint32_t)chunk * (DZ_F * RB));
   d.rs = 4u * ((uint32_t)tl * rstep + (uint32_t)chunk * (REC_F * RB));
@@ -477,6 +490,13 @@ __device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, in
     const int t = dw_tile(G, i);
     if (!dw_hist(t)) continue;
     const int col = 16 * t + li;
+    if (dw_tape(t)) {
+      // columns past the features (bias, padding) read a valid row; their
+      // values are replaced before use
+      const int hc = col < NO ? col - 18 : NH * NA - 1;
+      d.h[i] = (uint32_t)(((tl - w0) * NA + hc) * DW_AP + 4 * lg);
+      continue;
+    }
     const int hc = col < 18 ? 0 : col < NO ? col - 18 : 0;
     const uint32_t o_hist = tape + (uint32_t)((tl + (hc >> 2)) * NA + (hc & 3)) * RB;
     d.h[i] = 4u * (col < 18 ? rbo + (REC_O + col) * RB : col < NO ? o_hist : rbo);
@@ -494,13 +514,48 @@ __device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec, co
 #pragma unroll
   for (int i = 0; i < dw_ntile(G); ++i) {
     const int t = dw_tile(G, i);
-    if (dw_const(t)) continue;
+    if (dw_const(t) || dw_tape(t)) continue;
     if (dw_hist(t)) {
       o.b[i] = bld4(rrec, d.h[i] + 64 * q, 0);
     } else {
       const int row = t == 0 ? REC_O : t < 15 ? REC_Z1 + 16 * (t - 10) : REC_Z2 + 16 * (t - 15);
       o.b[i] = bld4(rrec, loff + 64 * q, d.rs + 4 * (row * RB));
     }
+  }
+}
+
+// The tape tiles' B operands of slab q from the LDS window.
+template <int G>
+__device__ inline void dw_load_tape(DwOps<G>& o, const float* tw, const DwAddr<G>& d, int q) {
+#pragma unroll
+  for (int i = 0; i < dw_ntile(G); ++i)
+    if (dw_tape(dw_tile(G, i)))
+      o.b[i] = *reinterpret_cast<const f4*>(&tw[d.h[i] + 16 * q]);
+}
+
+// Copies tape slots [w0, w0 + DW_CH + NH) of 64-env block `chunk` (those
+// below NH + n) into the window tw, every thread of the 512 issuing its six
+// 16-byte loads before its first store.
+constexpr int DW_TLD = DW_TW * (RB / 4) / 512;
+static_assert(DW_TW * (RB / 4) % 512 == 0, "the window splits evenly over the workgroup");
+__device__ inline void dw_stage_tape(float* tw, __amdgpu_buffer_rsrc_t rrec, int chunk, int n,
+                                     int N, int w0) {
+  const uint32_t rbp = (uint32_t)rb_pad(N);
+  // the block's tape, in bytes from the record's start
+  const uint32_t base =
+      4u * ((uint32_t)n * REC_F * rbp + (uint32_t)chunk * (uint32_t)((NH + n) * NA * RB));
+  const int rows = min(DW_TW, (NH + n - w0) * NA);
+  f4 v[DW_TLD];
+#pragma unroll
+  for (int j = 0; j < DW_TLD; ++j) {
+    const int k = (int)threadIdx.x + 512 * j, r = k >> 4, c = 4 * (k & 15);
+    const int rr = r < rows ? r : rows - 1;
+    v[j] = bld4(rrec, 4u * (uint32_t)((w0 * NA + rr) * RB + c), base);
+  }
+#pragma unroll
+  for (int j = 0; j < DW_TLD; ++j) {
+    const int k = (int)threadIdx.x + 512 * j, r = k >> 4, c = 4 * (k & 15);
+    if (r < rows) *reinterpret_cast<f4*>(&tw[r * DW_AP + c]) = v[j];
   }
 }
 
@@ -605,7 +660,7 @@ __device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, const DwA& A, float b
 template <int G, bool BF16>
 __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
                                      const float* __restrict__ dz, int N, int chunk, int t_lo,
-                                     int t_hi, int n, int half, float* sA) {
+                                     int t_hi, int n, int half, float* sA, float* tw) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   const int iters = (t_hi - t_lo + 1) / 2;  // half 0's steps, the same in every wave
   if (iters <= 0) return;
@@ -619,6 +674,8 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
     const int t = t_lo + half + 2 * i;
     return t < t_hi ? t : t_hi - 1;
   };
+  int w0 = t_lo;  // first slot of the tape window
+  dw_stage_tape(tw, rrec, chunk, n, N, w0);
   f4 an[DW_AL];
   dw_a_load(an, rdz, step(0), chunk, N, G, lane);
   dw_a_store(an, sA, G, lane);
@@ -626,8 +683,9 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
   DwOps<G> ob0, ob1;
   DwA A;
   DwAddr<G> d;
-  dw_addr<G>(d, step(0), n, chunk, N, li, lg);
+  dw_addr<G>(d, step(0), n, chunk, N, li, lg, w0);
   dw_load_slab<G>(ob0, rrec, d, loff, 0);
+  dw_load_tape<G>(ob0, tw, d, 0);
   // scheduling barriers keep each slab's loads ahead of the previous slab's
   // matrix work (left alone, the scheduler interleaves a slab's products
   // with its own loads and the waits then cover the loads just issued)
@@ -638,24 +696,30 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
     // a branch would leave the waits below counting it conservatively
     dw_a_load(an, rdz, step(more ? i + 1 : i), chunk, N, G, lane);
     dw_load_slab<G>(ob1, rrec, d, loff, 1);
+    dw_load_tape<G>(ob1, tw, d, 1);
     __builtin_amdgcn_sched_barrier(0);
     dw_read_a<G>(A, sA, 0, li, lg);
     dw_prepare<G, BF16>(ob0, li);
     if (live) dw_mfma<G>(acc, ob0, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
     dw_load_slab<G>(ob0, rrec, d, loff, 2);
+    dw_load_tape<G>(ob0, tw, d, 2);
     __builtin_amdgcn_sched_barrier(0);
     dw_read_a<G>(A, sA, 1, li, lg);
     dw_prepare<G, BF16>(ob1, li);
     if (live) dw_mfma<G>(acc, ob1, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
     dw_load_slab<G>(ob1, rrec, d, loff, 3);
+    dw_load_tape<G>(ob1, tw, d, 3);
     __builtin_amdgcn_sched_barrier(0);
     dw_read_a<G>(A, sA, 2, li, lg);
     dw_prepare<G, BF16>(ob0, li);
     if (live) dw_mfma<G>(acc, ob0, A, bias1);
     __builtin_amdgcn_sched_barrier(0);
-    dw_addr<G>(d, step(more ? i + 1 : i), n, chunk, N, li, lg);
+    // the next step's window (refilled below when the next step opens one)
+    const bool refill = more && (i + 1) % (DW_CH / 2) == 0;
+    const int w0n = refill ? w0 + DW_CH : w0;
+    dw_addr<G>(d, step(more ? i + 1 : i), n, chunk, N, li, lg, w0n);
     dw_load_slab<G>(ob0, rrec, d, loff, 0);
     __builtin_amdgcn_sched_barrier(0);
     dw_read_a<G>(A, sA, 3, li, lg);
@@ -665,8 +729,28 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
     if (more) {
       __syncthreads();  // every wave is done with this step's staged rows
       dw_a_store(an, sA, G, lane);
+      if (refill) {
+        w0 = w0n;
+        dw_stage_tape(tw, rrec, chunk, n, N, w0);
+      }
       __syncthreads();
     }
+    // after the barrier: the window holds the next step's slots
+    dw_load_tape<G>(ob0, tw, d, 0);
+  }
+}
+
+// The workgroup's 64-env chunks x, x + gx, ... in turn; the barrier before
+// each chunk but the first lets every wave finish reading the previous
+// chunk's last staged step (its iteration ends without one).
+template <int G, bool BF16>
+__device__ inline void dw_chunks(f4* acc, const float* __restrict__ rec,
+                                 const float* __restrict__ dz, int N, int t_lo, int t_hi, int n,
+                                 int half, float* sA, float* tw) {
+  const int n_chunks = (N + RB - 1) / RB;
+  for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    if (chunk != (int)blockIdx.x) __syncthreads();
+    dw_accumulate<G, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA, tw);
   }
 }
 
@@ -718,18 +802,20 @@ __device__ inline int dw_slot(int idx) {
   return dw_place(19, idx - OFF_B3, 0);
 }
 
-// grid (64-env blocks, S step groups), 512 threads; group sg takes steps
-// [sg * per, min(n, (sg + 1) * per)), per = ceil(n / S), and accumulates
-// into its own partial slot (chunk * S + sg) across segments.
+// grid (gx, S step groups), 512 threads; workgroup x takes the 64-env
+// chunks x, x + gx, ... in turn, step group sg the steps [sg * per, min(n,
+// (sg + 1) * per)), per = ceil(n / S); it accumulates into its own partial
+// slot (x * S + sg) across segments.
 template <bool BF16>
 __global__ void __launch_bounds__(512)
 k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int n, int S,
          float* __restrict__ gpart) {
   // dz staging of the two halves during the loop, then the exchange of sums
-  __shared__ __attribute__((aligned(16))) float smem[2 * DW_ABUF];
+  __shared__ __attribute__((aligned(16))) float smem[2 * DW_ABUF + DW_TBUF];
+  float* tw = smem + 2 * DW_ABUF;  // the action-tape window
   static_assert(2 * DW_ABUF * 4 >= 4 * DW_MAXT * 64 * 16, "exchange fits the staging space");
   f4(*xacc)[DW_MAXT][64] = reinterpret_cast<f4(*)[DW_MAXT][64]>(smem);
-  const int chunk = blockIdx.x, sg = blockIdx.y;
+  const int sg = blockIdx.y;
   // the wave index is uniform across the wave: keep it (and every offset
   // derived from it) in scalar registers
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -740,11 +826,14 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
 #pragma unroll
   for (int i = 0; i < DW_MAXT; ++i) acc[i] = const4(0.0f);
   float* sA = smem + half * DW_ABUF;
+  // one loop over the workgroup's chunks inside each group's instantiation
+  // (a loop around the switch would keep every group's operands live and
+  // spill)
   switch (g) {
-    case 0: dw_accumulate<0, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
-    case 1: dw_accumulate<1, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
-    case 2: dw_accumulate<2, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
-    default: dw_accumulate<3, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA); break;
+    case 0: dw_chunks<0, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    case 1: dw_chunks<1, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    case 2: dw_chunks<2, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    default: dw_chunks<3, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
   }
   __syncthreads();  // the staging space becomes the exchange buffer
   // half 1 hands its sums to half 0 (fixed order: half 0 + half 1)
@@ -760,7 +849,7 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
     for (int r = 0; r < 4; ++r) acc[i][r] += o[r];
   }
   // add into this group's part of the slot: all loads, then all stores
-  f4* gp = reinterpret_cast<f4*>(gpart + ((size_t)chunk * S + sg) * DW_SLOT) + g * DW_MAXT * 64;
+  f4* gp = reinterpret_cast<f4*>(gpart + ((size_t)blockIdx.x * S + sg) * DW_SLOT) + g * DW_MAXT * 64;
   f4 old[DW_MAXT];
 #pragma unroll
   for (int i = 0; i < DW_MAXT; ++i) old[i] = gp[i * 64 + lane];
@@ -810,8 +899,11 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   bw.N = N;
   bw.K = K;
   bw.H = H;
-  // Step groups of the weight-gradient pass: one workgroup per CU (the
-  // double-buffered staging takes most of the LDS), so about n_cu workgroups.
+  // Weight-gradient pass: one workgroup per CU (the double-buffered staging
+  // takes most of the LDS), so about n_cu workgroups: up to n_cu 64-env
+  // chunks, each split into step groups to fill the CUs; beyond n_cu chunks,
+  // n_cu workgroups that each take every n_cu-th chunk in turn (one partial
+  // slot per workgroup, whose sums stay in registers across its chunks).
   const int chunks = (int)nb(N, 64);
   int n_cu = 256;
   {
@@ -822,8 +914,9 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   int S = n_cu / chunks;
   if (S > K / 2) S = K / 2;  // at least two steps per group: one per half
   if (S < 1) S = 1;
+  bw.dw_gx = chunks < n_cu ? chunks : n_cu;
   bw.dw_groups = S;
-  bw.n_parts = chunks * S;
+  bw.n_parts = bw.dw_gx * S;
   hipError_t e;
   for (int i = 0; i < BWD_NBUF; ++i) {
     // zeroed once: the quarter-lane and split kernels never write the slots
@@ -948,7 +1041,7 @@ static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const Bwd
       BWD_TRY(hipStreamWaitEvent(s_dw, bw.e_rev[buf], 0));
     }
     hipLaunchKernelGGL((c.flags & F_ACTOR_BF16) ? k_bwd_dw<true> : k_bwd_dw<false>,
-                       dim3(nb(N, 64), bw.dw_groups), dim3(512), 0, s_dw, N, bw.seg[buf],
+                       dim3(bw.dw_gx, bw.dw_groups), dim3(512), 0, s_dw, N, bw.seg[buf],
                        bw.dz[buf], n, bw.dw_groups, bw.gpart);
     BWD_TRY(hipGetLastError());
     if (overlap) BWD_TRY(hipEventRecord(bw.e_dw[buf], s_dw));
