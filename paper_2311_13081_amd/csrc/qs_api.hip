@@ -103,7 +103,8 @@ struct sim_handle {
   float* tape = nullptr;     // [max_tape_horizon/K + 1][145][N]
   int tape_ckpts = 0;
   int tape_T = 0;            // horizon of the recorded tape (0 = none)
-  bool last_seg_recorded = false;  // bw.seg[0] holds the tape's last segment's record
+  // segment of the current tape whose record segment buffer b holds (-1: none)
+  int seg_held[BWD_NBUF] = {-1, -1, -1};
   BwdBufs bw{};
   int variant = SIM_V_AUTO, spl = 0, use_graph = 1;
   int tuned_variant = SIM_V_FUSED_MFMA, tuned_spl = 0;
@@ -283,10 +284,21 @@ void drop_graph(sim_handle* h) {
   h->gkey = GraphKey{};
 }
 
+// Segments of a taped T-step rollout whose backward records the rollout
+// writes itself: the last ones, one per segment buffer, as many as the
+// one-env-per-lane kernel's record span takes; the last one for the others.
+static_assert(REC_SEGS == BWD_NBUF, "one record segment per segment buffer");
+static int recorded_segments(const sim_handle* h, int variant, int T) {
+  const int J = (T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
+  const int m = variant == SIM_V_FUSED_MFMA ? REC_SEGS : 1;
+  return J < m ? J : m;
+}
+
 // Queues the launches of a T-step rollout on st.
 // With tape != NULL the launches also write the backward's record of the
-// tape's last segment (steps from (J - 1) K on, J = ceil(T / K)) into the
-// first segment buffer, so the backward need not recompute that segment.
+// tape's last m = recorded_segments() segments (steps from (J - m) K on,
+// J = ceil(T / K)) into the segment buffers (the last segment into the
+// first), so the backward need not recompute those segments.
 int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, float* rew,
                     uint8_t* done, float* states, float* tape, hipStream_t st, int* launches) {
   const int N = h->N;
@@ -304,8 +316,10 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
     const bool mfma = variant == SIM_V_FUSED_MFMA;
     const int chunk = (spl <= 0 || spl > T) ? T : spl;
     float* rec = tape ? h->bw.seg[0] : nullptr;
-    const int rec_from = tape ? ((T + K - 1) / K - 1) * K : 0;
+    const int J = (T + K - 1) / K;
+    const int rec_from = tape ? (J - recorded_segments(h, variant, T)) * K : 0;
     const int rec_n = T - rec_from;
+    const RecSpan rs{{rec, h->bw.seg[1], h->bw.seg[2]}, rec_from, K, rec_n};
     for (int t0 = 0; t0 < T; t0 += chunk) {
       const int n = (T - t0) < chunk ? (T - t0) : chunk;
       if (variant == SIM_V_FUSED_MFMA4)
@@ -315,8 +329,8 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
         HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
                              rec_from, rec_n, st));
       else if (tape && mfma)
-        HIP_TRY(launch_fused_taped(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr,
-                                   rec, rec_from, rec_n, st));
+        HIP_TRY(launch_fused_taped(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rs,
+                                   st));
       else
         HIP_TRY(launch_fused(mfma, h->dc, h->b, W, nullptr, n, t0, rew, done, states, st));
       ++nl;
@@ -587,7 +601,9 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   h->timing_valid = true;
   if (record_tape) {
     h->tape_T = T;
-    h->last_seg_recorded = true;
+    const int J = (T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
+    const int m = recorded_segments(h, v, T);
+    for (int i = 0; i < BWD_NBUF; ++i) h->seg_held[i] = i < m ? J - 1 - i : -1;
   }
   return SIM_OK;
 }
@@ -643,12 +659,9 @@ int sim_backward(sim_handle* h, const float* actor, const float* d_rewards, cons
   DeviceGuard g(h->device);
   int rc = sticky_error();
   if (rc) return rc;
+  // seg_held is brought up to date with the buffers the recomputes reuse
   HIP_TRY(run_backward(h->dc, h->b, h->bw, actor, h->tape, h->cfg.ckpt_every, h->tape_T, d_rewards,
-                       d_states, grad_actor, grad_params, h->last_seg_recorded,
-                       (hipStream_t)stream));
-  // with more segments than buffers, the first buffer was reused
-  const int J = (h->tape_T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
-  if (J > BWD_NBUF) h->last_seg_recorded = false;
+                       d_states, grad_actor, grad_params, h->seg_held, (hipStream_t)stream));
   return SIM_OK;
 }
 

@@ -36,12 +36,14 @@ hipError_t launch_reverse1(const DevCfg& c, const float* theta, const float* W, 
                            const float* d_states, float* lam, float* gth, float* dz,
                            hipStream_t st);
 void bwd_free(BwdBufs& bw);
-// last_recorded: bw.seg[0] already holds the record of the last segment
-// (written by the taped rollout), so its recompute is skipped.
+// held[i]: the segment whose record bw.seg[i] holds already (written by the
+// taped rollout or a recompute of an earlier backward on the same tape), or
+// -1; those segments are not recomputed.  Updated to what the buffers hold
+// afterwards.
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
-                        bool last_recorded, hipStream_t st);
+                        int held[BWD_NBUF], hipStream_t st);
 
 // The same backward with every buffer of bw's shape carved out of `scratch`
 // (bwd_scratch_floats(bw) floats, device memory the caller owns) instead of

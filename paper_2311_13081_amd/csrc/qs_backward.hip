@@ -994,7 +994,7 @@ void bwd_free(BwdBufs& bw) {
 static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const BwdBufs& bw, int nbuf,
                                     const float* W, const float* tape, int K, int T,
                                     const float* d_rewards, const float* d_states,
-                                    float* grad_actor, float* grad_params, bool last_recorded,
+                                    float* grad_actor, float* grad_params, int* held,
                                     hipStream_t st) {
   const int N = c.n_envs;
   const size_t np = (size_t)bw.n_parts * DW_SLOT;
@@ -1014,9 +1014,13 @@ static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const Bwd
     const int t0 = j * K;
     const int n = (T - t0) < K ? (T - t0) : K;
     const int buf = idx % nbuf;
-    // the last segment's record may come from the taped rollout itself
-    // (written on the caller's stream, ahead of this call)
-    if (!(idx == 0 && last_recorded)) {
+    // the record may be in the buffer already: written by the taped rollout
+    // (on the caller's stream, ahead of this call) or by a recompute of an
+    // earlier backward on the same tape
+    if (held && held[buf] == j) {
+      // nothing to recompute
+    } else {
+      if (held) held[buf] = j;
       if (overlap && idx >= BWD_NBUF) BWD_TRY(hipStreamWaitEvent(s_rec, bw.e_dw[buf], 0));
       BWD_TRY(launch_recompute(c, b, W, n, tape + (size_t)j * CK_F * N, bw.seg[buf], s_rec));
       if (overlap) {
@@ -1060,9 +1064,9 @@ static hipError_t backward_segments(const DevCfg& c, const SimBufs& b, const Bwd
 hipError_t run_backward(const DevCfg& c, const SimBufs& b, BwdBufs& bw, const float* W,
                         const float* tape, int K, int T, const float* d_rewards,
                         const float* d_states, float* grad_actor, float* grad_params,
-                        bool last_recorded, hipStream_t st) {
+                        int held[BWD_NBUF], hipStream_t st) {
   return backward_segments(c, b, bw, BWD_NBUF, W, tape, K, T, d_rewards, d_states, grad_actor,
-                           grad_params, last_recorded, st);
+                           grad_params, held, st);
 }
 
 // Layout of the scratch array in floats, every part starting on a 256-byte
@@ -1106,7 +1110,7 @@ hipError_t run_backward_in(const DevCfg& c, const SimBufs& b, const BwdBufs& bw,
   hipLaunchKernelGGL(k_fill, dim3(nb((int)f_dz, 256)), dim3(256), 0, st, sb.dz[0], f_dz, 0.0f);
   BWD_TRY(hipGetLastError());
   return backward_segments(c, b, sb, 1, W, tape, K, T, d_rewards, d_states, grad_actor,
-                           grad_params, false, st);
+                           grad_params, nullptr, st);
 }
 
 }  // namespace qs

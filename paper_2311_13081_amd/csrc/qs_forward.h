@@ -122,11 +122,21 @@ inline TapedKernel taped_kernel(const DevCfg& c) {
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
                         float* states, hipStream_t st);
-// The same kernel (fp32 matrix-core actor) with the tape and record modes of
-// launch_fused4.
+// Where a launch writes the backward's record: the steps [from, from +
+// total) cut into segments of len steps (the last one may be shorter), the
+// last segment into buf[0], the one before it into buf[1], ... (at most
+// REC_SEGS segments, each in its own record buffer).
+constexpr int REC_SEGS = 3;
+struct RecSpan {
+  float* buf[REC_SEGS];
+  int from, len, total;
+};
+// The same kernel (fp32 matrix-core actor) with the tape mode of
+// launch_fused4 and the record mode for one or more segments (rs.buf[0] ==
+// NULL: no record).
 hipError_t launch_fused_taped(const DevCfg& c, const SimBufs& b, const float* W, int T,
                               int t_base, float* rewards, uint8_t* dones, float* states,
-                              float* tape, int ckpt_every, const float* ck_in, float* rec,
-                              int rec_from, int rec_n, hipStream_t st);
+                              float* tape, int ckpt_every, const float* ck_in, const RecSpan& rs,
+                              hipStream_t st);
 
 }  // namespace qs

@@ -408,8 +408,8 @@ hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, i
       return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T,
                           st);
     case TAPED_LANE:
-      return launch_fused_taped(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec,
-                                0, T, st);
+      return launch_fused_taped(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in,
+                                RecSpan{{rec, nullptr, nullptr}, 0, T, T}, st);
     default:
       return launch_fused4(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, rec, 0, T,
                            st);

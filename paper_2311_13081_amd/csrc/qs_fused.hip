@@ -26,9 +26,11 @@ namespace qs {
 // quarter-lane kernel.  With tape != NULL a CK_F-row checkpoint every
 // ckpt_every steps; with ck_in != NULL the launch starts from that
 // checkpoint and leaves the env state alone (the backward's recompute); with
-// rec != NULL the backward's record (blocked by 64 envs) of the steps
-// t_base + t >= rec_from, a segment of rec_n steps.  The taped forward and
-// the recompute run this same code, so they agree bit for bit.
+// rs.buf[0] != NULL the backward's record (blocked by 64 envs) of the steps
+// [rs.from, rs.from + rs.total), segment by segment (RecSpan): the taped
+// forward records up to the last REC_SEGS segments, a recompute its one
+// segment.  The taped forward and the recompute run this same code, so they
+// agree bit for bit.
 //
 // EXT: the actions come from ext_act and the kernel holds no actor; without
 // it the loop issues no vector-memory load at all.  (Vector loads and stores
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(256)
 k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restrict__ ext_act,
         int T, int t_base, float* __restrict__ rewards, uint8_t* __restrict__ dones,
         float* __restrict__ states, float* __restrict__ tape, int ckpt_every,
-        const float* __restrict__ ck_in, float* __restrict__ rec, int rec_from, int rec_n) {
+        const float* __restrict__ ck_in, RecSpan rs) {
   __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
   const int N = c.n_envs;
   if constexpr (!EXT) {
@@ -93,18 +95,16 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
     acc.load(b, N, e);
   }
   // record (TAPE): byte offsets of the wave's 64-env block within a step's
-  // record and within the segment's action tape (wave uniform), of the
-  // lane's own column, and of its place in a matrix-core tile row.  Lanes of
-  // envs past the batch write their slots too (copies of the first env's
-  // values): the backward's cotangents there are zero.
+  // record (wave uniform), of the lane's own column, and of its place in a
+  // matrix-core tile row.  Lanes of envs past the batch write their slots
+  // too (copies of the first env's values): the backward's cotangents there
+  // are zero.
   const int lane = threadIdx.x & 63;
   const uint32_t blk = __builtin_amdgcn_readfirstlane((uint32_t)(first / RB));
   const uint32_t rstride = 4u * REC_F * (uint32_t)rb_pad(N);  // bytes per recorded step
   const uint32_t s_rblk = 4u * blk * (REC_F * RB);
-  const uint32_t s_act = (uint32_t)rec_n * rstride + 4u * blk * (uint32_t)((NH + rec_n) * NA * RB);
   const uint32_t v_own = 4u * (uint32_t)lane, v_tile = 4u * (uint32_t)(4 * (lane >> 4) * RB + (lane & 15));
-  const __amdgpu_buffer_rsrc_t rrec =
-      span_rsrc(rec, TAPE && rec ? 4u * (uint32_t)rec_floats(rec_n, N) : 0u);
+  const int rec_segs = TAPE && rs.buf[0] ? (rs.total + rs.len - 1) / rs.len : 0;
   SetPoint sp;
   if (EXTRAS) sp.load(c, N, e);
   if (EXTRAS) {
@@ -140,10 +140,20 @@ k_fused(DevCfg c, SimBufs b, const float* __restrict__ W, const float* __restric
       ck[(size_t)CK_TEP * N + eo] = __int_as_float(t_ep);
       ck[(size_t)CK_EP * N + eo] = __int_as_float(ep);
     }
-    const int rt_step = gt - rec_from;
     // wave uniform: the record branches below are scalar branches around one
-    // copy of the actor
-    const bool rec_on = TAPE && rec != nullptr && rt_step >= 0;
+    // copy of the actor.  Recorded step gt: segment k of the span, its step
+    // rt_step, its buffer (the span's last segment in buf[0]) and length;
+    // the segment's action tape follows its n_k step records.
+    const int rt = gt - rs.from;
+    const bool rec_on = TAPE && rec_segs > 0 && rt >= 0 && rt < rs.total;
+    const int rk = rec_on ? rt / rs.len : 0;
+    const int rt_step = rt - rk * rs.len;
+    const int n_k = rk == rec_segs - 1 ? rs.total - rk * rs.len : rs.len;
+    const __amdgpu_buffer_rsrc_t rrec =
+        span_rsrc(rs.buf[rec_on ? rec_segs - 1 - rk : 0],
+                  rec_on ? 4u * (uint32_t)rec_floats(n_k, N) : 0u);
+    const uint32_t s_act = __builtin_amdgcn_readfirstlane(
+        (uint32_t)n_k * rstride + 4u * blk * (uint32_t)((NH + n_k) * NA * RB));
     float a[NA];
     if constexpr (EXT) {
 #pragma unroll
@@ -285,19 +295,21 @@ hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const floa
            : mfma ? (ex ? k_fused<true, true, false, false> : k_fused<true, false, false, false>)
                   : (ex ? k_fused<false, true, false, false> : k_fused<false, false, false, false>);
   hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, ext_act, T, t_base, rewards, dones, states,
-                     nullptr, 1, nullptr, nullptr, 0, 0);
+                     nullptr, 1, nullptr, RecSpan{});
   return hipGetLastError();
 }
 
 hipError_t launch_fused_taped(const DevCfg& c, const SimBufs& b, const float* W, int T,
                               int t_base, float* rewards, uint8_t* dones, float* states,
-                              float* tape, int ckpt_every, const float* ck_in, float* rec,
-                              int rec_from, int rec_n, hipStream_t st) {
+                              float* tape, int ckpt_every, const float* ck_in, const RecSpan& rs,
+                              hipStream_t st) {
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
+  if (rs.buf[0] && (rs.len < 1 || rs.total < 1 || (rs.total + rs.len - 1) / rs.len > REC_SEGS))
+    return hipErrorInvalidValue;
   auto k = ex ? k_fused<true, true, false, true> : k_fused<true, false, false, true>;
   hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, nullptr, T, t_base, rewards, dones, states, tape,
-                     ckpt_every, ck_in, rec, rec_from, rec_n);
+                     ckpt_every, ck_in, rs);
   return hipGetLastError();
 }
 
