@@ -285,12 +285,15 @@ void drop_graph(sim_handle* h) {
 }
 
 // Segments of a taped T-step rollout whose backward records the rollout
-// writes itself: the last ones, one per segment buffer, as many as the
-// one-env-per-lane kernel's record span takes; the last one for the others.
+// writes itself: the last ones, one per segment buffer.  Small batches (the
+// split-actor kernel) record only the last: their backward runs the other
+// recomputes beside the sweeps on a stream of their own, so recording more
+// in the forward, which nothing overlaps, measured slower (1024 x 64: 0.86
+// against 0.84 ms).
 static_assert(REC_SEGS == BWD_NBUF, "one record segment per segment buffer");
-static int recorded_segments(const sim_handle* h, int variant, int T) {
+static int recorded_segments(const sim_handle* h, int T) {
   const int J = (T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
-  const int m = variant == SIM_V_FUSED_MFMA ? REC_SEGS : 1;
+  const int m = taped_kernel(h->dc) == TAPED_SPLIT ? 1 : REC_SEGS;
   return J < m ? J : m;
 }
 
@@ -317,17 +320,15 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
     const int chunk = (spl <= 0 || spl > T) ? T : spl;
     float* rec = tape ? h->bw.seg[0] : nullptr;
     const int J = (T + K - 1) / K;
-    const int rec_from = tape ? (J - recorded_segments(h, variant, T)) * K : 0;
+    const int rec_from = tape ? (J - recorded_segments(h, T)) * K : 0;
     const int rec_n = T - rec_from;
     const RecSpan rs{{rec, h->bw.seg[1], h->bw.seg[2]}, rec_from, K, rec_n};
     for (int t0 = 0; t0 < T; t0 += chunk) {
       const int n = (T - t0) < chunk ? (T - t0) : chunk;
       if (variant == SIM_V_FUSED_MFMA4)
-        HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
-                              rec_from, rec_n, st));
+        HIP_TRY(launch_fused4(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rs, st));
       else if (variant == SIM_V_FUSED_SPLIT)
-        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rec,
-                             rec_from, rec_n, st));
+        HIP_TRY(launch_split(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rs, st));
       else if (tape && mfma)
         HIP_TRY(launch_fused_taped(h->dc, h->b, W, n, t0, rew, done, states, tape, K, nullptr, rs,
                                    st));
@@ -506,10 +507,10 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
                               nullptr, st));
   } else if (v == SIM_V_FUSED_MFMA4 && actor) {
     HIP_TRY(launch_fused4(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr,
-                          h->cfg.ckpt_every, nullptr, nullptr, 0, 0, st));
+                          h->cfg.ckpt_every, nullptr, RecSpan{}, st));
   } else if (v == SIM_V_FUSED_SPLIT && actor) {
     HIP_TRY(launch_split(h->dc, h->b, actor, 1, 0, reward, done, nullptr, nullptr, 1, nullptr,
-                         nullptr, 0, 0, st));
+                         RecSpan{}, st));
   } else {
     // external actions run on the one-env-per-lane kernel (it has the
     // action-input path); both kernels share the state layout
@@ -602,7 +603,7 @@ int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, ui
   if (record_tape) {
     h->tape_T = T;
     const int J = (T + h->cfg.ckpt_every - 1) / h->cfg.ckpt_every;
-    const int m = recorded_segments(h, v, T);
+    const int m = recorded_segments(h, T);
     for (int i = 0; i < BWD_NBUF; ++i) h->seg_held[i] = i < m ? J - 1 - i : -1;
   }
   return SIM_OK;

@@ -85,26 +85,54 @@ __host__ __device__ inline size_t rec_floats(int K, int N) {
   return ((size_t)K * REC_F + (size_t)(NH + K) * NA) * rb_pad(N);
 }
 
+// Where a launch writes the backward's record: the steps [from, from +
+// total) cut into segments of len steps (the last one may be shorter), the
+// last segment into buf[0], the one before it into buf[1], ... (at most
+// REC_SEGS segments, each in its own record buffer).
+constexpr int REC_SEGS = 3;
+struct RecSpan {
+  float* buf[REC_SEGS];
+  int from, len, total;
+};
+// Where global step gt is recorded: the segment's buffer, the step within
+// the segment and the segment's length (false: gt is not recorded).
+struct RecAt {
+  float* base;
+  int step, n;
+};
+__device__ inline bool rec_at(const RecSpan& rs, int gt, RecAt& r) {
+  const int rt = gt - rs.from;
+  r.base = rs.buf[0];
+  r.step = 0;
+  r.n = 1;
+  if (!rs.buf[0] || rt < 0 || rt >= rs.total) return false;
+  const int segs = (rs.total + rs.len - 1) / rs.len, k = rt / rs.len;
+  r.step = rt - k * rs.len;
+  r.n = k == segs - 1 ? rs.total - k * rs.len : rs.len;
+  r.base = rs.buf[segs - 1 - k];
+  return true;
+}
+// the recorded segments of a span (at most REC_SEGS)
+inline bool rec_span_ok(const RecSpan& rs) {
+  return !rs.buf[0] || (rs.len >= 1 && rs.total >= 1 && (rs.total + rs.len - 1) / rs.len <= REC_SEGS);
+}
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st);
 // Quarter-lane fused kernel (qs_fused4.hip): 16 envs per wave, 4 lanes per
 // env; the kernel of taped rollouts (tape: CK_F-row checkpoints every
 // ckpt_every steps).  With ck_in != NULL it starts from that checkpoint and
-// leaves the env state alone (the backward's recompute).  With rec != NULL
-// it writes the backward's record of the steps t_base + t >= rec_from, a
-// segment of rec_n steps (the recompute: rec_from 0, rec_n T; a taped
-// rollout: its last segment).
+// leaves the env state alone (the backward's recompute).  With rs.buf[0] !=
+// NULL it writes the backward's record of the span rs (the recompute: its
+// one segment; a taped rollout: its last segments).
 hipError_t launch_fused4(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                          float* rewards, uint8_t* dones, float* states, float* tape,
-                         int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
-                         hipStream_t st);
+                         int ckpt_every, const float* ck_in, const RecSpan& rs, hipStream_t st);
 // Split-actor fused kernel (qs_split.hip): 16 envs per workgroup of 4 waves,
 // wave w evaluating neuron tile w of layers 1 and 2; tape and record modes as
 // the quarter-lane kernel, whose results it reproduces bit for bit.
 hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                         float* rewards, uint8_t* dones, float* states, float* tape,
-                        int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
-                        hipStream_t st);
+                        int ckpt_every, const float* ck_in, const RecSpan& rs, hipStream_t st);
 // The kernel of taped rollouts and of their backward recompute (the two must
 // agree bit for bit): with the fp32 actor the split-actor kernel below 16384
 // envs (the quarter-lane kernel leaves SIMDs idle there), the one-env-per-lane
@@ -122,15 +150,6 @@ inline TapedKernel taped_kernel(const DevCfg& c) {
 hipError_t launch_fused(bool mfma, const DevCfg& c, const SimBufs& b, const float* W,
                         const float* ext_act, int T, int t_base, float* rewards, uint8_t* dones,
                         float* states, hipStream_t st);
-// Where a launch writes the backward's record: the steps [from, from +
-// total) cut into segments of len steps (the last one may be shorter), the
-// last segment into buf[0], the one before it into buf[1], ... (at most
-// REC_SEGS segments, each in its own record buffer).
-constexpr int REC_SEGS = 3;
-struct RecSpan {
-  float* buf[REC_SEGS];
-  int from, len, total;
-};
 // The same kernel (fp32 matrix-core actor) with the tape mode of
 // launch_fused4 and the record mode for one or more segments (rs.buf[0] ==
 // NULL: no record).

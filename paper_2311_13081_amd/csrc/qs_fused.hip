@@ -305,8 +305,7 @@ hipError_t launch_fused_taped(const DevCfg& c, const SimBufs& b, const float* W,
                               hipStream_t st) {
   const dim3 g(nblk(c.n_envs, 256)), blk(256);
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
-  if (rs.buf[0] && (rs.len < 1 || rs.total < 1 || (rs.total + rs.len - 1) / rs.len > REC_SEGS))
-    return hipErrorInvalidValue;
+  if (!rec_span_ok(rs)) return hipErrorInvalidValue;
   auto k = ex ? k_fused<true, true, false, true> : k_fused<true, false, false, true>;
   hipLaunchKernelGGL(k, g, blk, 0, st, c, b, W, nullptr, T, t_base, rewards, dones, states, tape,
                      ckpt_every, ck_in, rs);

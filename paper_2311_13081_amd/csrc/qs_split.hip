@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256)
 k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
         float* __restrict__ rewards, uint8_t* __restrict__ dones, float* __restrict__ states,
         float* __restrict__ tape, int ckpt_every, const float* __restrict__ ck_in,
-        float* __restrict__ rec, int rec_from, int rec_n) {
+        RecSpan rs) {
   __shared__ __attribute__((aligned(16))) float lds[Q_TOTAL];
   __shared__ f4q xz1[4 * 64], xz2[4 * 64];
   const int N = c.n_envs;
@@ -101,8 +101,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
   const bool active = env < N;
   const int e = active ? env : env0;
   // from a checkpoint (the backward's recompute): no write-back of the env
-  // state; records of steps t_base + t >= rec_from go to rec (segment of
-  // rec_n steps)
+  // state; the steps of the span rs are recorded (rec_at)
   const bool REC = ck_in != nullptr;
 
   float th[NP];
@@ -164,8 +163,9 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     __asm__ volatile("" ::: "memory");
     const uint32_t eo = opaque((uint32_t)e);
     const int gt = t_base + t;
-    const int rt_step = gt - rec_from;
-    const bool rec_on = opaque((rec && rt_step >= 0) ? 1u : 0u) != 0u;
+    RecAt ra;
+    const bool rec_on = rec_at(rs, gt, ra);  // wave uniform
+    const int rt_step = ra.step;
     if (tape && (gt % ckpt_every) == 0 && active && writer) {
       float* ck = tape + (size_t)(gt / ckpt_every) * CK_F * N;
 #pragma unroll
@@ -180,7 +180,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       }
     }
     quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F, sp);
-    float* rt = rec_on ? rec + rec_step(rt_step, N) : nullptr;
+    float* rt = rec_on ? ra.base + rec_step(rt_step, N) : nullptr;
     const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
     float z3[NA];
     actor_split(lds, F, xz1, xz2, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
@@ -194,8 +194,8 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
 #pragma unroll
       for (int cc = 0; cc < 5; ++cc)
         if (q_phi(cc, k) >= 0) rt[(size_t)(REC_O + 4 * cc) * RB + koff] = F[cc];
-      float* act = rec + rec_act(rec_n, N);
-      const uint32_t aoff = opaque((uint32_t)(rb_at(e, (NH + rec_n) * NA) + k * RB));
+      float* act = ra.base + rec_act(ra.n, N);
+      const uint32_t aoff = opaque((uint32_t)(rb_at(e, (NH + ra.n) * NA) + k * RB));
       if (rt_step == 0) {
 #pragma unroll
         for (int s = 0; s < NH; ++s) act[(size_t)(s * NA) * RB + aoff] = F[5 + s];
@@ -266,13 +266,13 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
 
 hipError_t launch_split(const DevCfg& c, const SimBufs& b, const float* W, int T, int t_base,
                         float* rewards, uint8_t* dones, float* states, float* tape,
-                        int ckpt_every, const float* ck_in, float* rec, int rec_from, int rec_n,
-                        hipStream_t st) {
+                        int ckpt_every, const float* ck_in, const RecSpan& rs, hipStream_t st) {
+  if (!rec_span_ok(rs)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((c.n_envs + 15) / 16);
   const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
   auto k = ex ? k_split<true> : k_split<false>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, c, b, W, T, t_base, rewards, dones, states,
-                     tape, ckpt_every, ck_in, rec, rec_from, rec_n);
+                     tape, ckpt_every, ck_in, rs);
   return hipGetLastError();
 }
 
