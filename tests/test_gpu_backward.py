@@ -227,15 +227,18 @@ def test_split_kernels_match_quarter_lane_bitwise(pkg, oracle_lib):
     assert np.array_equal(gps[0], gps[1])
 
 
-@pytest.mark.parametrize("n,T,K", [(300, 24, 8), (300, 40, 8), (65573, 40, 8)])
+@pytest.mark.parametrize("n,T,K", [(300, 24, 8), (300, 40, 8), (16500, 40, 8), (65573, 40, 8)])
 def test_backward_twice_on_one_tape(pkg, oracle_lib, n, T, K):
-    """The taped rollout writes the backward's record of its last segment, so
-    the first backward skips that recompute.  With more segments than record
-    buffers (40 / 8 = 5 > 3) the backward reuses that buffer and a second
-    backward on the same tape recomputes the segment; with 3 segments it
-    still holds it.  Either way the gradients repeat bit for bit: the
-    recompute reproduces the taped forward's record exactly.  65573 envs
-    (a ragged last wave) run the one-env-per-lane taped kernel and sweep."""
+    """The taped rollout writes the backward's record of its last segment
+    (split-actor kernel, 300 envs) or of its last three (quarter-lane kernel,
+    16500 envs; one-env-per-lane kernel, 65573 envs with a ragged last wave),
+    one per record buffer, so the first backward skips those recomputes.
+    With more segments than record buffers (40 / 8 = 5 > 3) the backward
+    reuses buffers and a second backward on the same tape recomputes some of
+    the segments the forward had recorded and reuses the others; with 3
+    segments the buffers still hold them.  Either way the gradients repeat
+    bit for bit: the recompute reproduces the taped forward's record
+    exactly."""
     cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
     a = sim.actor_tensor(wl.sysid_actor(0) if n > 16384 else wl.xavier_actor(0))
     sim.rollout(a, T, rewards=False, dones=False, states=False, record_tape=True)
