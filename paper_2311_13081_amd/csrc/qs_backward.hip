@@ -372,60 +372,60 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 
 // Weight gradients of one segment: for every (step, env) row,
 //   dW1 += dz1 o^T, dW2 += dz2 relu(z1)^T, dW3 += dz3 relu(z2)^T, db += dz,
-// on fp32 MFMA (v_mfma_f32_16x16x4f32) with the rows as the K dimension:
-// A[i][k] (lane i + 16 k) = dz of neuron 16 n + i at env e0 + k, B[k][j] =
-// input column 16 t + j at the same env; result register r of a tile holds
-// neuron 16 n + 4 lg + r, column 16 t + li.  Biases come from a constant-one
-// input column (generated, not stored).
+// the rows being the contraction dimension.  Most of the work runs on fp32
+// MFMA (v_mfma_f32_16x16x4f32): A[i][k] (lane i + 16 k) = dz of neuron
+// 16 n + i at env e0 + k, B[k][j] = input column 16 t + j at the same env;
+// result register r of a tile holds neuron 16 n + 4 lg + r, column 16 t + li.
 //
-// One workgroup of 8 waves per (64-env block, step group).  The output tiles
-// are split by input column.  Column tiles 0..9 are layer 1's (147 columns
-// with the bias), 10..14 layer 2's and 15..19 layer 3's (65 each); tiles 14
-// and 19 hold only the bias column and are generated, not loaded.  A layer-1
-// or -2 tile carries its 4 neuron tiles, a layer-3 tile 1 (4 outputs).  The
-// groups: 0 {0 4 8 12}, 1 {1 5 9 13}, 2 {2 6 10 11}, 3 {3 7 14 15..19}: 16,
-// 16, 16 and 17 output tiles, and every input value is read by one group
-// only (the dz rows, a third of the bytes, by all four, through L2).  Waves
-// g and g + 4 run column group g on alternate steps -- two waves per SIMD, so
-// one's loads overlap the other's matrix work -- and add their sums through
-// LDS at the end, half 0 first.  The dz rows (A operands, the same for the
-// four groups of a half) are loaded once per step by the half's four waves
-// together, whole 256-byte rows per lane group, and staged in LDS; each wave
-// loads its own input columns (B operands) straight from the record, one
-// 16-env slab ahead.  The kernel is bound by the number of vector-memory
-// instructions (the address unit's queue fills), which the shared dz staging
-// halves.  The history features of o_t are the actions of the 32 previous
-// steps, read from the segment's action tape (one contiguous span per 64-env
-// block).
-constexpr int DW_MAXT = 17;  // output tiles of a column group
+// One workgroup of 8 waves per (64-env block, step group).  The input
+// columns fall in column tiles of 16: layer 1's 146 columns make the full
+// tiles 0..8 and the 2 columns 144, 145; layer 2's 64 columns the tiles
+// 10..13.  Waves g and g + 4 run column group g on alternate steps (two
+// waves per SIMD, so one's loads overlap the other's matrix work) and add
+// their sums through LDS at the end, half 0 first.  A group owns three full
+// tiles with their 4 neuron tiles -- {g, g + 4} of layer 1 and 10 + g of
+// layer 2 -- and neuron tile g of the shared tile 8, so each group issues the
+// same 52 products per 16-env slab and no product multiplies padding.  The
+// rest is small: group 0 takes layer 1's last two columns and its bias
+// (16-block v_mfma_f32_4x4x1f32, block b = neurons 4 b .. 4 b + 3, one
+// product per env: D[i][j] in lane 4 b + j, register i, is neuron 4 b + i,
+// column 144 + j, with column 146 the constant one), group 2 layer 3 (the
+// same shape with block b = columns 4 b .. 4 b + 3: lane l, register o holds
+// output o, column l) and layer 3's bias, every group layer 2's bias of its
+// neuron tile (vector adds of the A operands it already holds).  The dz rows
+// (A operands, the same for the four groups of a half) are loaded once per
+// step by the half's four waves together, whole 256-byte rows per lane
+// group, and staged in LDS; each wave loads its own input columns (B
+// operands) from the record or the LDS copy of the action tape, one 16-env
+// slab ahead.  The history features of o_t are the actions of the 32
+// previous steps, read from the segment's action tape (one contiguous span
+// per 64-env block).
+constexpr int DW_SPLIT = 8;  // the column tile shared by the four groups
+constexpr int DW_NB = 4;     // B operands of a slab: three full tiles, the shared one
+// accumulators (f4) of a wave: full tile i, neuron tile n at 4 i + n, then
+// the shared tile, layer 2's bias, the small products and layer 3's bias
+constexpr int DW_A_SHARED = 12, DW_A_B2 = 13, DW_A_SMALL = 14, DW_A_B3 = 15, DW_NACC = 16;
+constexpr int DW_COL_SMALL = 16 * (DW_SPLIT + 1);  // first layer-1 column of the small products
 
+// column tile of B slot i of group G
 __host__ __device__ constexpr int dw_tile(int G, int i) {
-  return G == 0   ? (i < 4 ? 4 * i : -1)
-         : G == 1 ? (i < 4 ? 1 + 4 * i : -1)
-         : G == 2 ? (i < 2 ? 2 + 4 * i : i < 4 ? 8 + i : -1)
-                  : (i < 2 ? 3 + 4 * i : i < 8 ? 12 + i : -1);
+  return i < 2 ? G + 4 * i : i == 2 ? 10 + G : DW_SPLIT;
 }
-__host__ __device__ constexpr int dw_ntile(int G) { return G == 3 ? 8 : 4; }
-__host__ __device__ constexpr int dw_nacc(int t) { return t < 15 ? 4 : 1; }
-__host__ __device__ constexpr bool dw_const(int t) { return t == 14 || t == 19; }
-// first accumulator of column tile i of group G (only group 3's tiles 3..7
-// are layer-3 tiles, one accumulator each)
-__host__ __device__ constexpr int dw_acc0(int G, int i) {
-  return G < 3 || i < 3 ? 4 * i : 12 + (i - 3);
-}
-static_assert(dw_acc0(3, 8) == DW_MAXT && dw_acc0(0, 4) == 16 && dw_acc0(2, 4) == 16 &&
-                  dw_acc0(3, 3) == dw_acc0(3, 2) + dw_nacc(dw_tile(3, 2)),
-              "column-group tile counts");
+static_assert(dw_tile(3, 1) == 7 && dw_tile(0, 2) == 10 && dw_tile(3, 2) == 13 &&
+                  DW_COL_SMALL + 2 == NO,
+              "column groups");
 
-// B operands of one 16-env slab for column group G (slot i of column tile
-// i; the bias-only tiles use no slot), and the A operands: the dz1 and dz2
-// tiles of the four neuron tiles and dz3 (group 3).
-template <int G>
+// B operands of a slab; group 2's small products take z2 row l of the
+// lane for the slab's env quads 0..3 from the record
 struct DwOps {
-  f4 b[dw_ntile(G)];
+  f4 b[DW_NB];
+  f4 z[4];
 };
+// A operands of a slab and the small products' A (env quads 0..3 of the
+// slab), with group 0's small B (its tape columns), all read from LDS
 struct DwA {
-  f4 a1[4], a2[4], a3;
+  f4 a1[4], a2[4];
+  f4 sa[4], sb[4];
 };
 
 // LDS staging of one step's dz rows for a half: DZ_F rows of 64 envs, pitch
@@ -448,36 +448,33 @@ __device__ inline f4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// A column tile whose rows depend on the lane only through li (state
-// features, z rows) is addressed as a uniform row offset plus the lane's
-// offset li * RB + 4 lg; a tile with history columns needs a per-lane offset
-// (the source step depends on the column).
-__host__ __device__ constexpr bool dw_hist(int t) { return t >= 1 && t < 10; }
-
-// Tiles 2..9 hold action-tape values only.  Their B operands come from an
-// LDS copy of the block's tape window: the DW_CH steps [w0, w0 + DW_CH)
-// observe slots w0 .. w0 + DW_CH + NH - 2, which the workgroup copies in
-// (rows (slot - w0) * NA + a, pitch DW_AP) and refills every DW_CH steps, so
-// each tape value is read from memory once per window instead of once for
-// each of the 32 steps that observe it.  Tile 1 mixes the last two state
-// features with history and stays on the record.
+// Tiles 1..8 hold history columns: tile 1 mixes the last two state features
+// with history and is read from the record with a per-lane offset (the
+// source step depends on the column); tiles 2..8 hold action-tape values
+// only and read an LDS copy of the block's tape window: the DW_CH steps [w0,
+// w0 + DW_CH) observe slots w0 .. w0 + DW_CH + NH - 2, which the workgroup
+// copies in (rows (slot - w0) * NA + a, pitch DW_AP) and refills every
+// DW_CH steps, so each tape value is read from memory once per window
+// instead of once for each of the 32 steps that observe it.
 constexpr int DW_CH = 16, DW_TW = (DW_CH + NH) * NA, DW_TBUF = DW_TW * DW_AP;
 static_assert(DW_CH % 2 == 0, "a window holds whole iterations (one step per half)");
-__host__ __device__ constexpr bool dw_tape(int t) { return t >= 2 && t < 10; }
+__host__ __device__ constexpr bool dw_tape(int t) { return t >= 2 && t <= DW_SPLIT; }
 
 // Addressing of one step, in bytes from the dz and record buffers: uniform
-// offsets of this step's block, and the per-lane offsets of the history
-// tiles (in floats from the LDS tape window for tiles 2..9, w0 its first
-// slot).
-template <int G>
+// offsets of this step's block, the per-lane offset of tile 1 (group 1), and
+// in floats from the LDS tape window (w0 its first slot) those of the tape
+// tiles and of group 0's small B operands (tape rows of columns 144, 145).
+// Group 2's small B operands (relu(z2) row l of the lane) need no per-step
+// lane offset.
 struct DwAddr {
   uint32_t dzs, rs;
-  uint32_t h[dw_ntile(G)];
+  uint32_t h[DW_NB];
+  uint32_t hs;
 };
 
 template <int G>
-__device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, int li, int lg,
-                               int w0) {
+__device__ inline void dw_addr(DwAddr& d, int tl, int n, int chunk, int N, int lane, int w0) {
+  const int li = lane & 15, lg = lane >> 4;
   const uint32_t rbp = (uint32_t)rb_pad(N), rstep = (uint32_t)REC_F * rbp;
   d.dzs = 4u * ((uint32_t)tl * (DZ_F * rbp) + (uint32_t)chunk * (DZ_F * RB));
   d.rs = 4u * ((uint32_t)tl * rstep + (uint32_t)chunk * (REC_F * RB));
@@ -486,51 +483,57 @@ __device__ inline void dw_addr(DwAddr<G>& d, int tl, int n, int chunk, int N, in
   // this block's action tape; history slot sl of step tl is tape slot tl + sl
   const uint32_t tape = (uint32_t)n * rstep + (uint32_t)chunk * ((NH + n) * NA * RB) + c4;
 #pragma unroll
-  for (int i = 0; i < dw_ntile(G); ++i) {
-    const int t = dw_tile(G, i);
-    if (!dw_hist(t)) continue;
-    const int col = 16 * t + li;
+  for (int i = 0; i < DW_NB; ++i) {
+    const int t = dw_tile(G, i), col = 16 * t + li;
     if (dw_tape(t)) {
-      // columns past the features (bias, padding) read a valid row; their
-      // values are replaced before use
-      const int hc = col < NO ? col - 18 : NH * NA - 1;
-      d.h[i] = (uint32_t)(((tl - w0) * NA + hc) * DW_AP + 4 * lg);
-      continue;
+      // window row of history column hc: (tl + hc / NA - w0) NA + hc % NA
+      d.h[i] = (uint32_t)(((tl - w0) * NA + col - 18) * DW_AP + 4 * lg);
+    } else if (t == 1) {
+      const int hc = col < 18 ? 0 : col - 18;
+      const uint32_t o_hist = tape + (uint32_t)((tl + (hc >> 2)) * NA + (hc & 3)) * RB;
+      d.h[i] = 4u * (col < 18 ? rbo + (REC_O + col) * RB : o_hist);
+    } else {
+      d.h[i] = 0;
     }
-    const int hc = col < 18 ? 0 : col < NO ? col - 18 : 0;
-    const uint32_t o_hist = tape + (uint32_t)((tl + (hc >> 2)) * NA + (hc & 3)) * RB;
-    d.h[i] = 4u * (col < 18 ? rbo + (REC_O + col) * RB : col < NO ? o_hist : rbo);
   }
+  // group 0: lane 4 b + j takes column 144 + j (j = 2, 3: constants, any
+  // valid row)
+  const int j = lane & 3;
+  d.hs = G == 0 ? (uint32_t)(((tl - w0) * NA + DW_COL_SMALL - 18 + (j < 2 ? j : 0)) * DW_AP) : 0u;
 }
 
-// Issues the B loads of slab q of a step; dw_prepare finishes the operands
-// when they are used, so the loads stay in flight during the previous slab's
-// matrix work.  Every lane of a loaded tile loads (lanes of constant columns
-// from a valid address, replaced later), so no load sits under a branch.
-// loff: the lane's byte offset 4 (li * RB + 4 lg).
+// Issues the record B loads of slab q of a step; dw_prepare finishes the
+// operands when they are used, so the loads stay in flight during the
+// previous slab's matrix work.  loff: the lane's byte offset 4 (li * RB +
+// 4 lg).
 template <int G>
-__device__ inline void dw_load_slab(DwOps<G>& o, __amdgpu_buffer_rsrc_t rrec, const DwAddr<G>& d,
+__device__ inline void dw_load_slab(DwOps& o, __amdgpu_buffer_rsrc_t rrec, const DwAddr& d,
                                     uint32_t loff, int q) {
+  if (G == 2) {
+    // z2 row l, envs 16 q + 4 k .. + 3 (64 rows of 16 bytes per load)
+    const uint32_t lo = 4u * (uint32_t)((threadIdx.x & 63) * RB);
 #pragma unroll
-  for (int i = 0; i < dw_ntile(G); ++i) {
+    for (int k = 0; k < 4; ++k) o.z[k] = bld4(rrec, lo + 64 * q + 16 * k, d.rs + 4 * (REC_Z2 * RB));
+  }
+#pragma unroll
+  for (int i = 0; i < DW_NB; ++i) {
     const int t = dw_tile(G, i);
-    if (dw_const(t) || dw_tape(t)) continue;
-    if (dw_hist(t)) {
+    if (dw_tape(t)) continue;
+    if (t == 1) {
       o.b[i] = bld4(rrec, d.h[i] + 64 * q, 0);
     } else {
-      const int row = t == 0 ? REC_O : t < 15 ? REC_Z1 + 16 * (t - 10) : REC_Z2 + 16 * (t - 15);
+      const int row = t == 0 ? REC_O : REC_Z1 + 16 * (t - 10);
       o.b[i] = bld4(rrec, loff + 64 * q, d.rs + 4 * (row * RB));
     }
   }
 }
 
-// The tape tiles' B operands of slab q from the LDS window.
+// The tape B operands of slab q from the LDS window.
 template <int G>
-__device__ inline void dw_load_tape(DwOps<G>& o, const float* tw, const DwAddr<G>& d, int q) {
+__device__ inline void dw_load_tape(DwOps& o, const float* tw, const DwAddr& d, int q) {
 #pragma unroll
-  for (int i = 0; i < dw_ntile(G); ++i)
-    if (dw_tape(dw_tile(G, i)))
-      o.b[i] = *reinterpret_cast<const f4*>(&tw[d.h[i] + 16 * q]);
+  for (int i = 0; i < DW_NB; ++i)
+    if (dw_tape(dw_tile(G, i))) o.b[i] = *reinterpret_cast<const f4*>(&tw[d.h[i] + 16 * q]);
 }
 
 // Copies tape slots [w0, w0 + DW_CH + NH) of 64-env block `chunk` (those
@@ -580,66 +583,96 @@ __device__ inline void dw_a_store(const f4 an[DW_AL], float* sA, int g, int lane
     if (jr < DW_AW && r < DZ_F) *reinterpret_cast<f4*>(&sA[r * DW_AP + 4 * (lane & 15)]) = an[j];
   }
 }
-// A operands of slab q from the staged rows (dz3 rows only for the 4
-// outputs).
+// A operands of slab q from the staged rows, and the small products'
+// operands of envs 16 q + 4 k .. + 3 held in LDS: group 0 A = dz1 row l, B =
+// the tape rows of columns 144 + (l & 3) at window offset hs (lanes with
+// l & 3 >= 2 take constants, set by dw_prepare); group 2 A = dz3 row l & 3.
 template <int G>
-__device__ inline void dw_read_a(DwA& a, const float* sA, int q, int li, int lg) {
-  const int c = 16 * q + 4 * lg;
+__device__ inline void dw_read_a(DwA& a, const float* sA, const float* tw, uint32_t hs, int q,
+                                 int lane) {
+  const int li = lane & 15, c = 16 * q + 4 * (lane >> 4);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     a.a1[nt] = *reinterpret_cast<const f4*>(&sA[(16 * nt + li) * DW_AP + c]);
     a.a2[nt] = *reinterpret_cast<const f4*>(&sA[(NHID + 16 * nt + li) * DW_AP + c]);
   }
-  if (G == 3) {
-    a.a3 = *reinterpret_cast<const f4*>(&sA[(2 * NHID + (li & 3)) * DW_AP + c]);
+  if (G == 0 || G == 2) {
+    const int row = G == 0 ? lane : 2 * NHID + (lane & 3);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a.a3[m] = li < NA ? a.a3[m] : 0.0f;
+    for (int k = 0; k < 4; ++k) {
+      a.sa[k] = *reinterpret_cast<const f4*>(&sA[row * DW_AP + 16 * q + 4 * k]);
+      if (G == 0) a.sb[k] = *reinterpret_cast<const f4*>(&tw[hs + 16 * q + 4 * k]);
+    }
   }
 }
 
-// ReLU of the pre-activation columns, the constant columns (ones at the bias
-// column, zeros beyond) and the forward's bf16 rounding of its inputs.  Envs
-// >= N of the last block need nothing: their dz slots are zero (cleared at
-// allocation; the one-env-per-lane sweep writes zeros there) and their
-// record slots are zero or finite copies of a batch env's values (the
-// one-env-per-lane forward writes those), so they add nothing.
+// ReLU of the pre-activation columns, the constant columns of group 0's
+// small products (one at the bias column 146, zero at 147) and the
+// forward's bf16 rounding of its inputs.  Envs >= N of the last block need
+// nothing: their dz slots are zero (cleared at allocation; the
+// one-env-per-lane sweep writes zeros there) and their record slots are
+// zero or finite copies of a batch env's values (the one-env-per-lane
+// forward writes those), so they add nothing.
 template <int G, bool BF16>
-__device__ inline void dw_prepare(DwOps<G>& o, int li) {
+__device__ inline void dw_prepare(DwOps& o, DwA& a, int lane) {
 #pragma unroll
-  for (int i = 0; i < dw_ntile(G); ++i) {
+  for (int i = 0; i < DW_NB; ++i) {
     const int t = dw_tile(G, i);
-    if (dw_const(t)) continue;
-    const int n_in = t < 10 ? NO : NHID;
-    const int col0 = t < 10 ? 16 * t : 16 * (t < 15 ? t - 10 : t - 15);
-    const int col = col0 + li;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       float v = t < 10 ? o.b[i][m] : relu_bits(o.b[i][m]);
       if (BF16) v = (float)(__bf16)v;
-      // only a tile that reaches the bias column has constant lanes
-      o.b[i][m] = col0 + 15 < n_in ? v : col < n_in ? v : col == n_in ? 1.0f : 0.0f;
+      o.b[i][m] = v;
     }
+  }
+  if (G == 0 || G == 2) {
+    const int j = lane & 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        float v = G == 2 ? relu_bits(o.z[k][m]) : a.sb[k][m];
+        if (BF16) v = (float)(__bf16)v;
+        if (G == 2)
+          o.z[k][m] = v;
+        else
+          a.sb[k][m] = j < 2 ? v : j == 2 ? 1.0f : 0.0f;
+      }
   }
 }
 
-// bias1: B of a bias-only tile (column 64 = lane li 0).
+// The products of one slab: m walks the four envs a lane group holds
+// (16x16x4: K = the four lane groups), k and m the 16 envs one at a time
+// (4x4x1: K = one env).
 template <int G>
-__device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, const DwA& A, float bias1) {
+__device__ inline void dw_mfma(f4* acc, float* bs, const DwOps& o, const DwA& A) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m) {
 #pragma unroll
-    for (int i = 0; i < dw_ntile(G); ++i) {
-      const int t = dw_tile(G, i), a0 = dw_acc0(G, i);
-      const float bv = dw_const(t) ? bias1 : o.b[i][m];
-      if (t < 15) {
+    for (int i = 0; i < 3; ++i) {
+      const int t = dw_tile(G, i);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-          acc[a0 + nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(t < 10 ? A.a1[nt][m] : A.a2[nt][m],
-                                                              bv, acc[a0 + nt], 0, 0, 0);
-      } else {
-        acc[a0] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a3[m], bv, acc[a0], 0, 0, 0);
-      }
+      for (int nt = 0; nt < 4; ++nt)
+        acc[4 * i + nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            t < 10 ? A.a1[nt][m] : A.a2[nt][m], o.b[i][m], acc[4 * i + nt], 0, 0, 0);
     }
+    acc[DW_A_SHARED] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a1[G][m], o.b[3][m],
+                                                            acc[DW_A_SHARED], 0, 0, 0);
+  }
+  if (G == 0 || G == 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        acc[DW_A_SMALL] = __builtin_amdgcn_mfma_f32_4x4x1f32(
+            A.sa[k][m], G == 2 ? o.z[k][m] : A.sb[k][m], acc[DW_A_SMALL], 0, 0, 0);
+  }
+  // biases: layer 2's of neuron tile G (bs[0]), layer 3's (group 2, bs[1])
+  bs[0] += (A.a2[G][0] + A.a2[G][1]) + (A.a2[G][2] + A.a2[G][3]);
+  if (G == 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bs[1] += (A.sa[k][0] + A.sa[k][1]) + (A.sa[k][2] + A.sa[k][3]);
+  }
 }
 
 // This half's steps t_lo + half, t_lo + half + 2, ... of the group, the four
@@ -658,7 +691,7 @@ __device__ inline void dw_mfma(f4* acc, const DwOps<G>& o, const DwA& A, float b
 // barriers in uniform code, but it keeps every group's operand slots live
 // across the switch and spills.
 template <int G, bool BF16>
-__device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
+__device__ inline void dw_accumulate(f4* acc, float* bs, const float* __restrict__ rec,
                                      const float* __restrict__ dz, int N, int chunk, int t_lo,
                                      int t_hi, int n, int half, float* sA, float* tw) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
@@ -669,7 +702,6 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
       buf_rsrc(rec, 4u * ((uint32_t)n * REC_F * rbp + (uint32_t)(NH + n) * NA * rbp));
   const __amdgpu_buffer_rsrc_t rdz = buf_rsrc(dz, 4u * ((uint32_t)n * DZ_F * rbp));
   const uint32_t loff = 4u * (uint32_t)(li * RB + 4 * lg);
-  const float bias1 = li == 0 ? 1.0f : 0.0f;
   auto step = [&](int i) {
     const int t = t_lo + half + 2 * i;
     return t < t_hi ? t : t_hi - 1;
@@ -680,10 +712,10 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
   dw_a_load(an, rdz, step(0), chunk, N, G, lane);
   dw_a_store(an, sA, G, lane);
   __syncthreads();
-  DwOps<G> ob0, ob1;
+  DwOps ob0, ob1;
   DwA A;
-  DwAddr<G> d;
-  dw_addr<G>(d, step(0), n, chunk, N, li, lg, w0);
+  DwAddr d;
+  dw_addr<G>(d, step(0), n, chunk, N, lane, w0);
   dw_load_slab<G>(ob0, rrec, d, loff, 0);
   dw_load_tape<G>(ob0, tw, d, 0);
   // scheduling barriers keep each slab's loads ahead of the previous slab's
@@ -698,33 +730,35 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
     dw_load_slab<G>(ob1, rrec, d, loff, 1);
     dw_load_tape<G>(ob1, tw, d, 1);
     __builtin_amdgcn_sched_barrier(0);
-    dw_read_a<G>(A, sA, 0, li, lg);
-    dw_prepare<G, BF16>(ob0, li);
-    if (live) dw_mfma<G>(acc, ob0, A, bias1);
+    dw_read_a<G>(A, sA, tw, d.hs, 0, lane);
+    dw_prepare<G, BF16>(ob0, A, lane);
+    if (live) dw_mfma<G>(acc, bs, ob0, A);
     __builtin_amdgcn_sched_barrier(0);
     dw_load_slab<G>(ob0, rrec, d, loff, 2);
     dw_load_tape<G>(ob0, tw, d, 2);
     __builtin_amdgcn_sched_barrier(0);
-    dw_read_a<G>(A, sA, 1, li, lg);
-    dw_prepare<G, BF16>(ob1, li);
-    if (live) dw_mfma<G>(acc, ob1, A, bias1);
+    dw_read_a<G>(A, sA, tw, d.hs, 1, lane);
+    dw_prepare<G, BF16>(ob1, A, lane);
+    if (live) dw_mfma<G>(acc, bs, ob1, A);
     __builtin_amdgcn_sched_barrier(0);
     dw_load_slab<G>(ob1, rrec, d, loff, 3);
     dw_load_tape<G>(ob1, tw, d, 3);
     __builtin_amdgcn_sched_barrier(0);
-    dw_read_a<G>(A, sA, 2, li, lg);
-    dw_prepare<G, BF16>(ob0, li);
-    if (live) dw_mfma<G>(acc, ob0, A, bias1);
+    dw_read_a<G>(A, sA, tw, d.hs, 2, lane);
+    dw_prepare<G, BF16>(ob0, A, lane);
+    if (live) dw_mfma<G>(acc, bs, ob0, A);
     __builtin_amdgcn_sched_barrier(0);
+    // slab 3's small-product tape rows are this step's (d moves on below)
+    const uint32_t hs = d.hs;
     // the next step's window (refilled below when the next step opens one)
     const bool refill = more && (i + 1) % (DW_CH / 2) == 0;
     const int w0n = refill ? w0 + DW_CH : w0;
-    dw_addr<G>(d, step(more ? i + 1 : i), n, chunk, N, li, lg, w0n);
+    dw_addr<G>(d, step(more ? i + 1 : i), n, chunk, N, lane, w0n);
     dw_load_slab<G>(ob0, rrec, d, loff, 0);
     __builtin_amdgcn_sched_barrier(0);
-    dw_read_a<G>(A, sA, 3, li, lg);
-    dw_prepare<G, BF16>(ob1, li);
-    if (live) dw_mfma<G>(acc, ob1, A, bias1);
+    dw_read_a<G>(A, sA, tw, hs, 3, lane);
+    dw_prepare<G, BF16>(ob1, A, lane);
+    if (live) dw_mfma<G>(acc, bs, ob1, A);
     __builtin_amdgcn_sched_barrier(0);
     if (more) {
       __syncthreads();  // every wave is done with this step's staged rows
@@ -744,62 +778,59 @@ __device__ inline void dw_accumulate(f4* acc, const float* __restrict__ rec,
 // each chunk but the first lets every wave finish reading the previous
 // chunk's last staged step (its iteration ends without one).
 template <int G, bool BF16>
-__device__ inline void dw_chunks(f4* acc, const float* __restrict__ rec,
+__device__ inline void dw_chunks(f4* acc, float* bs, const float* __restrict__ rec,
                                  const float* __restrict__ dz, int N, int t_lo, int t_hi, int n,
                                  int half, float* sA, float* tw) {
   const int n_chunks = (N + RB - 1) / RB;
   for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
     if (chunk != (int)blockIdx.x) __syncthreads();
-    dw_accumulate<G, BF16>(acc, rec, dz, N, chunk, t_lo, t_hi, n, half, sA, tw);
+    dw_accumulate<G, BF16>(acc, bs, rec, dz, N, chunk, t_lo, t_hi, n, half, sA, tw);
   }
 }
 
-// A partial slot holds the sums in the tiles' own register layout:
-// [group 4][output tile 17][lane 64][register 4] floats, so a wave adds its
-// tiles with whole-wave vector loads and stores; dw_slot maps a flat
+// A partial slot holds the sums in the accumulators' own register layout:
+// [group 4][accumulator DW_NACC][lane 64][register 4] floats, so a wave adds
+// its sums with whole-wave vector loads and stores; dw_slot maps a flat
 // gradient index to its place in a slot (k_bwd_reduce gathers with it).
-constexpr int DW_SLOT = 4 * DW_MAXT * 64 * 4;
+// The bias sums are reduced within the wave first: layer 2's bias of neuron
+// 16 g + i sits in lane i, register 0 of accumulator DW_A_B2 of group g,
+// layer 3's bias of output o in lane o, register 0 of DW_A_B3 of group 2.
+constexpr int DW_SLOT = 4 * DW_NACC * 64 * 4;
 
-// owner (group, tile slot i) of column tile t: the inverse of dw_tile
-__host__ __device__ constexpr int dw_owner_g(int t) {
-  return t < 10 ? t % 4 : t == 10 || t == 11 ? 2 : t == 12 ? 0 : t == 13 ? 1 : 3;
+__host__ __device__ constexpr int dw_pos(int g, int a, int lane, int r) {
+  return ((g * DW_NACC + a) * 64 + lane) * 4 + r;
 }
-__host__ __device__ constexpr int dw_owner_i(int t) {
-  return t < 10 ? t / 4 : t == 10 ? 2 : t == 11 ? 3 : t == 12 || t == 13 ? 3 : t == 14 ? 2 : t - 12;
-}
-static_assert(dw_tile(dw_owner_g(11), dw_owner_i(11)) == 11 &&
-                  dw_tile(dw_owner_g(14), dw_owner_i(14)) == 14 &&
-                  dw_tile(dw_owner_g(17), dw_owner_i(17)) == 17 &&
-                  dw_tile(dw_owner_g(9), dw_owner_i(9)) == 9,
-              "tile owners");
-
-// Place in a slot of the sum for (neuron or output row, column) of column
-// tile t (column within the tile c = 0..15).
-__host__ __device__ constexpr int dw_place(int t, int row, int c) {
-  const int g = dw_owner_g(t), i = dw_owner_i(t);
-  const int acc = t < 15 ? dw_acc0(g, i) + row / 16 : dw_acc0(g, i);
-  const int r = t < 15 ? row % 16 : row;  // row within the 16-row tile
-  const int lane = c + 16 * (r / 4);
-  return ((g * DW_MAXT + acc) * 64 + lane) * 4 + r % 4;
+// a 16x16 product tile: row rr (neuron within the tile), column c
+__host__ __device__ constexpr int dw_tile_pos(int g, int a, int rr, int c) {
+  return dw_pos(g, a, c + 16 * (rr / 4), rr % 4);
 }
 
 // flat gradient index (torch Linear layout) -> place in a slot
 __device__ inline int dw_slot(int idx) {
   if (idx < OFF_B1) {
     const int nrn = idx / NO, col = idx % NO;
-    return dw_place(col / 16, nrn, col % 16);
+    if (col >= DW_COL_SMALL) return dw_pos(0, DW_A_SMALL, 4 * (nrn / 4) + col - DW_COL_SMALL, nrn % 4);
+    const int t = col / 16, c = col % 16;
+    if (t == DW_SPLIT) return dw_tile_pos(nrn / 16, DW_A_SHARED, nrn % 16, c);
+    return dw_tile_pos(t % 4, 4 * (t / 4) + nrn / 16, nrn % 16, c);
   }
-  if (idx < OFF_W2) return dw_place(NO / 16, idx - OFF_B1, NO % 16);
+  if (idx < OFF_W2) {
+    const int nrn = idx - OFF_B1;  // the constant column 146
+    return dw_pos(0, DW_A_SMALL, 4 * (nrn / 4) + NO - DW_COL_SMALL, nrn % 4);
+  }
   if (idx < OFF_B2) {
     const int nrn = (idx - OFF_W2) / NHID, col = (idx - OFF_W2) % NHID;
-    return dw_place(10 + col / 16, nrn, col % 16);
+    return dw_tile_pos(col / 16, 8 + nrn / 16, nrn % 16, col % 16);
   }
-  if (idx < OFF_W3) return dw_place(14, idx - OFF_B2, 0);
+  if (idx < OFF_W3) {
+    const int nrn = idx - OFF_B2;
+    return dw_pos(nrn / 16, DW_A_B2, nrn % 16, 0);
+  }
   if (idx < OFF_B3) {
     const int o = (idx - OFF_W3) / NHID, col = (idx - OFF_W3) % NHID;
-    return dw_place(15 + col / 16, o, col % 16);
+    return dw_pos(2, DW_A_SMALL, col, o);
   }
-  return dw_place(19, idx - OFF_B3, 0);
+  return dw_pos(2, DW_A_B3, idx - OFF_B3, 0);
 }
 
 // grid (gx, S step groups), 512 threads; workgroup x takes the 64-env
@@ -813,8 +844,8 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
   // dz staging of the two halves during the loop, then the exchange of sums
   __shared__ __attribute__((aligned(16))) float smem[2 * DW_ABUF + DW_TBUF];
   float* tw = smem + 2 * DW_ABUF;  // the action-tape window
-  static_assert(2 * DW_ABUF * 4 >= 4 * DW_MAXT * 64 * 16, "exchange fits the staging space");
-  f4(*xacc)[DW_MAXT][64] = reinterpret_cast<f4(*)[DW_MAXT][64]>(smem);
+  static_assert(2 * DW_ABUF * 4 >= 4 * DW_NACC * 64 * 16, "exchange fits the staging space");
+  f4(*xacc)[DW_NACC][64] = reinterpret_cast<f4(*)[DW_NACC][64]>(smem);
   const int sg = blockIdx.y;
   // the wave index is uniform across the wave: keep it (and every offset
   // derived from it) in scalar registers
@@ -822,39 +853,52 @@ k_bwd_dw(int N, const float* __restrict__ rec, const float* __restrict__ dz, int
   const int g = wv & 3, half = wv >> 2;
   const int per = (n + S - 1) / S;
   const int t_lo = sg * per, t_hi = (t_lo + per) < n ? (t_lo + per) : n;
-  f4 acc[DW_MAXT];
+  // the bias sums accumulate in bs (layer 2's, layer 3's) and enter their
+  // slots DW_A_B2 and DW_A_B3 after the loop
+  f4 acc[DW_NACC];
+  float bs[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int i = 0; i < DW_MAXT; ++i) acc[i] = const4(0.0f);
+  for (int i = 0; i < DW_NACC; ++i) acc[i] = const4(0.0f);
   float* sA = smem + half * DW_ABUF;
   // one loop over the workgroup's chunks inside each group's instantiation
-  // (a loop around the switch would keep every group's operands live and
-  // spill)
+  // (a loop around the switch would keep every group's operand slots live
+  // and spill)
   switch (g) {
-    case 0: dw_chunks<0, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
-    case 1: dw_chunks<1, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
-    case 2: dw_chunks<2, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
-    default: dw_chunks<3, BF16>(acc, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    case 0: dw_chunks<0, BF16>(acc, bs, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    case 1: dw_chunks<1, BF16>(acc, bs, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    case 2: dw_chunks<2, BF16>(acc, bs, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
+    default: dw_chunks<3, BF16>(acc, bs, rec, dz, N, t_lo, t_hi, n, half, sA, tw); break;
   }
+  acc[DW_A_B2] = f4{bs[0], 0.0f, 0.0f, 0.0f};
+  acc[DW_A_B3] = f4{bs[1], 0.0f, 0.0f, 0.0f};
   __syncthreads();  // the staging space becomes the exchange buffer
   // half 1 hands its sums to half 0 (fixed order: half 0 + half 1)
   if (half == 1)
 #pragma unroll
-    for (int i = 0; i < DW_MAXT; ++i) xacc[g][i][lane] = acc[i];
+    for (int i = 0; i < DW_NACC; ++i) xacc[g][i][lane] = acc[i];
   __syncthreads();
   if (half == 1) return;
 #pragma unroll
-  for (int i = 0; i < DW_MAXT; ++i) {
+  for (int i = 0; i < DW_NACC; ++i) {
     const f4 o = xacc[g][i][lane];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[i][r] += o[r];
   }
+  // layer 2's bias sums over the four lane groups (lanes i, i ^ 32, then
+  // i ^ 16); every lane of layer 3's output o already holds the whole sum
+  {
+    float s = acc[DW_A_B2][0];
+    s += __shfl_xor(s, 32);
+    s += __shfl_xor(s, 16);
+    acc[DW_A_B2][0] = s;
+  }
   // add into this group's part of the slot: all loads, then all stores
-  f4* gp = reinterpret_cast<f4*>(gpart + ((size_t)blockIdx.x * S + sg) * DW_SLOT) + g * DW_MAXT * 64;
-  f4 old[DW_MAXT];
+  f4* gp = reinterpret_cast<f4*>(gpart + ((size_t)blockIdx.x * S + sg) * DW_SLOT) + g * DW_NACC * 64;
+  f4 old[DW_NACC];
 #pragma unroll
-  for (int i = 0; i < DW_MAXT; ++i) old[i] = gp[i * 64 + lane];
+  for (int i = 0; i < DW_NACC; ++i) old[i] = gp[i * 64 + lane];
 #pragma unroll
-  for (int i = 0; i < DW_MAXT; ++i) {
+  for (int i = 0; i < DW_NACC; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) old[i][r] += acc[i][r];
     gp[i * 64 + lane] = old[i];
