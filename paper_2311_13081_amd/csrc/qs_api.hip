@@ -104,7 +104,7 @@ struct sim_handle {
   int tape_ckpts = 0;
   int tape_T = 0;            // horizon of the recorded tape (0 = none)
   // segment of the current tape whose record segment buffer b holds (-1: none)
-  int seg_held[BWD_NBUF] = {-1, -1, -1};
+  int seg_held[BWD_NBUF] = {-1, -1, -1, -1};
   BwdBufs bw{};
   int variant = SIM_V_AUTO, spl = 0, use_graph = 1;
   int tuned_variant = SIM_V_FUSED_MFMA, tuned_spl = 0;
@@ -322,7 +322,7 @@ int enqueue_rollout(sim_handle* h, int variant, int spl, const float* W, int T, 
     const int J = (T + K - 1) / K;
     const int rec_from = tape ? (J - recorded_segments(h, T)) * K : 0;
     const int rec_n = T - rec_from;
-    const RecSpan rs{{rec, h->bw.seg[1], h->bw.seg[2]}, rec_from, K, rec_n};
+    const RecSpan rs{{rec, h->bw.seg[1], h->bw.seg[2], h->bw.seg[3]}, rec_from, K, rec_n};
     for (int t0 = 0; t0 < T; t0 += chunk) {
       const int n = (T - t0) < chunk ? (T - t0) : chunk;
       if (variant == SIM_V_FUSED_MFMA4)

@@ -7,7 +7,7 @@ namespace qs {
 // Scratch owned by the handle for the backward pass (allocated at create).
 // Segments are pipelined over three streams (recompute, reverse sweep on the
 // caller's stream, weight gradients) with NBUF rotating segment buffers.
-constexpr int BWD_NBUF = 3;
+constexpr int BWD_NBUF = 4;
 struct BwdBufs {
   int N = 0, K = 0, H = 0;
   int n_parts = 0;                    // partial slots of the weight gradients (dw_gx x groups)

@@ -962,7 +962,13 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
   bw.dw_groups = S;
   bw.n_parts = bw.dw_gx * S;
   hipError_t e;
+  // a horizon of J segments uses min(J, BWD_NBUF) of the rotating buffers
+  const int nseg = (H + K - 1) / K < BWD_NBUF ? (H + K - 1) / K : BWD_NBUF;
   for (int i = 0; i < BWD_NBUF; ++i) {
+    if ((e = hipEventCreateWithFlags(&bw.e_rec[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&bw.e_rev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&bw.e_dw[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if (i >= nseg) continue;
     // zeroed once: the quarter-lane and split kernels never write the slots
     // of envs >= N in the last 64-env block, which must then read as finite
     // (record) and zero (cotangents) in the weight-gradient pass
@@ -970,9 +976,6 @@ hipError_t bwd_alloc(BwdBufs& bw, int N, int K, int H) {
     if ((e = hipMemset(bw.seg[i], 0, rec_floats(K, N) * 4)) != hipSuccess) return e;
     if ((e = hipMalloc(&bw.dz[i], (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
     if ((e = hipMemset(bw.dz[i], 0, (size_t)K * DZ_F * rb_pad(N) * 4)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&bw.e_rec[i], hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&bw.e_rev[i], hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&bw.e_dw[i], hipEventDisableTiming)) != hipSuccess) return e;
   }
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;

@@ -89,7 +89,7 @@ __host__ __device__ inline size_t rec_floats(int K, int N) {
 // total) cut into segments of len steps (the last one may be shorter), the
 // last segment into buf[0], the one before it into buf[1], ... (at most
 // REC_SEGS segments, each in its own record buffer).
-constexpr int REC_SEGS = 3;
+constexpr int REC_SEGS = 4;
 struct RecSpan {
   float* buf[REC_SEGS];
   int from, len, total;

@@ -403,7 +403,7 @@ hipError_t launch_copy_state(const SimBufs& b, int N, float* out, hipStream_t st
 hipError_t launch_recompute(const DevCfg& c, const SimBufs& b, const float* W, int T,
                             const float* ck_in, float* rec, hipStream_t st) {
   // the kernel of taped rollouts, in record mode: one segment of T steps
-  const RecSpan one{{rec, nullptr, nullptr}, 0, T, T};
+  const RecSpan one{{rec, nullptr, nullptr, nullptr}, 0, T, T};
   switch (taped_kernel(c)) {
     case TAPED_SPLIT:
       return launch_split(c, b, W, T, 0, nullptr, nullptr, nullptr, nullptr, 1, ck_in, one, st);

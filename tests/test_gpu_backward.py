@@ -230,10 +230,10 @@ def test_split_kernels_match_quarter_lane_bitwise(pkg, oracle_lib):
 @pytest.mark.parametrize("n,T,K", [(300, 24, 8), (300, 40, 8), (16500, 40, 8), (65573, 40, 8)])
 def test_backward_twice_on_one_tape(pkg, oracle_lib, n, T, K):
     """The taped rollout writes the backward's record of its last segment
-    (split-actor kernel, 300 envs) or of its last three (quarter-lane kernel,
+    (split-actor kernel, 300 envs) or of its last four (quarter-lane kernel,
     16500 envs; one-env-per-lane kernel, 65573 envs with a ragged last wave),
     one per record buffer, so the first backward skips those recomputes.
-    With more segments than record buffers (40 / 8 = 5 > 3) the backward
+    With more segments than record buffers (40 / 8 = 5 > 4) the backward
     reuses buffers and a second backward on the same tape recomputes some of
     the segments the forward had recorded and reuses the others; with 3
     segments the buffers still hold them.  Either way the gradients repeat
