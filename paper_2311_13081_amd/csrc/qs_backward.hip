@@ -83,35 +83,27 @@ __device__ inline void stage_reverse(const float* __restrict__ W, float* lds, bo
 }
 
 // Inputs of one reverse step: the recorded state and action, this lane's
-// layer-1 and layer-2 pre-activations (ZT tiles: all four, rows 16 q + 4 k
-// + r at index 4 q + r, or, for the split sweep, tile w only, at index r),
-// the reward and state cotangents.
-template <int ZT>
+// ReLU mask word (quarter_mask: the signs of its 16 layer-1 and 16 layer-2
+// pre-activations, neurons 16 q + 4 k + r), the reward and state cotangents.
 struct StepIn {
-  float x[NS], a[NA], z1[4 * ZT], z2[4 * ZT], dS[NS], dR;
+  float x[NS], a[NA], dS[NS], dR;
+  uint32_t zm;
 };
 
-template <int ZT>
-__device__ inline void load_step(StepIn<ZT>& in, const float* __restrict__ rec,
+__device__ inline void load_step(StepIn& in, const float* __restrict__ rec,
                                  const float* __restrict__ d_rewards,
                                  const float* __restrict__ d_states, int tl, int t0, int N, int e,
-                                 int k, int w) {
+                                 int k) {
   const uint32_t eo = opaque((uint32_t)e);
   const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
-  const uint32_t zoff = opaque((uint32_t)(rb_at(e, REC_F) + 4 * k * RB + (ZT == 1 ? 16 * w * RB : 0)));
+  const uint32_t koff = opaque((uint32_t)(rb_at(e, REC_F) + k * RB));
   const int t = t0 + tl;
   const float* rt = rec + rec_step(tl, N);
 #pragma unroll
   for (int i = 0; i < NS; ++i) in.x[i] = rt[(size_t)(REC_X + i) * RB + roff];
 #pragma unroll
   for (int i = 0; i < NA; ++i) in.a[i] = rt[(size_t)(REC_A + i) * RB + roff];
-#pragma unroll
-  for (int q = 0; q < ZT; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      in.z1[4 * q + r] = rt[(size_t)(REC_Z1 + 16 * q + r) * RB + zoff];
-      in.z2[4 * q + r] = rt[(size_t)(REC_Z2 + 16 * q + r) * RB + zoff];
-    }
+  in.zm = __float_as_uint(rt[(size_t)REC_M * RB + koff]);
   in.dR = d_rewards ? d_rewards[(size_t)t * N + eo] : 1.0f;
 #pragma unroll
   for (int i = 0; i < NS; ++i)
@@ -217,12 +209,11 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
 
   // The per-step inputs (record rows and cotangents) of step tl - 1 are
   // loaded while step tl is processed, so their latency hides behind it.
-  constexpr int ZT = SPLIT ? 1 : 4;
-  StepIn<ZT> cur, nxt;
-  load_step<ZT>(cur, rec, d_rewards, d_states, n - 1, t0, N, e, k, w);
+  StepIn cur, nxt;
+  load_step(cur, rec, d_rewards, d_states, n - 1, t0, N, e, k);
   for (int tl = n - 1; tl >= 0; --tl) {
     __asm__ volatile("" ::: "memory");
-    load_step<ZT>(nxt, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k, w);
+    load_step(nxt, rec, d_rewards, d_states, tl > 0 ? tl - 1 : 0, t0, N, e, k);
     // blocked cotangent rows of this env: row k and row 4k
     const uint32_t koff = opaque((uint32_t)(rb_at(e, DZ_F) + k * RB));
     const uint32_t zoff = opaque((uint32_t)(rb_at(e, DZ_F) + 4 * k * RB));
@@ -255,8 +246,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
                                                       f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float z2 = cur.z2[(4 * q + r) % (4 * ZT)];
-          dz2[q][r] = z2 > 0.0f ? dz2[q][r] : 0.0f;
+          dz2[q][r] = (cur.zm >> (8 * q + 4 + r)) & 1u ? dz2[q][r] : 0.0f;
           if (active) dzt[(size_t)(NHID + 16 * q + r) * RB + zoff] = dz2[q][r];
         }
       }
@@ -275,8 +265,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float z1 = cur.z1[(4 * mt + r) % (4 * ZT)];
-          dz1[mt][r] = z1 > 0.0f ? accm[r] : 0.0f;
+          dz1[mt][r] = (cur.zm >> (8 * mt + r)) & 1u ? accm[r] : 0.0f;
           if (active) dzt[(size_t)(16 * mt + r) * RB + zoff] = dz1[mt][r];
         }
       }
@@ -300,7 +289,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
                                                    f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        d2[r] = cur.z2[r] > 0.0f ? d2[r] : 0.0f;
+        d2[r] = (cur.zm >> (8 * w + 4 + r)) & 1u ? d2[r] : 0.0f;
         if (active) dzt[(size_t)(NHID + 16 * w + r) * RB + zoff] = d2[r];
       }
       xd2[w * 64 + lane] = d2;
@@ -321,7 +310,7 @@ k_bwd_reverse(DevCfg c, const float* __restrict__ theta, const float* __restrict
       f4 d1;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        d1[r] = cur.z1[r] > 0.0f ? accm[r] : 0.0f;
+        d1[r] = (cur.zm >> (8 * w + r)) & 1u ? accm[r] : 0.0f;
         if (active) dzt[(size_t)(16 * w + r) * RB + zoff] = d1[r];
       }
       xd1[w * 64 + lane] = d1;

@@ -46,11 +46,16 @@ hipError_t launch_dyn_rollout(const DevCfg& c, const SimBufs& b, const float* ac
 // Per-step record of the backward recompute, REC_F rows per env: x_t (17),
 // a_t (4), layer-1 and layer-2 pre-activations (64 + 64), the 18 state
 // features of the observation o_t (as the actor saw them, noise included)
-// and 4 rows of ReLU masks written by the one-env-per-lane kernel only: in
-// that kernel's matrix-core tile layout, lane l of a 64-env block keeps bit
-// 16 n + 4 bb + v of word w = n / 2 (layer 1, words 0-1; layer 2, words 2-3)
-// set when neuron 16 n + 4 (l / 16) + v of env 16 bb + l % 16 of the block
-// has a positive pre-activation; the word sits in row REC_M + w, column l.
+// and 4 rows of ReLU masks, in the layout of the kernel family that writes
+// them (the reverse sweep of the same family reads them).  The
+// one-env-per-lane kernel uses its matrix-core tile layout: lane l of a
+// 64-env block keeps bit 16 n + 4 bb + v of word w = n / 2 (layer 1, words
+// 0-1; layer 2, words 2-3) set when neuron 16 n + 4 (l / 16) + v of env 16 bb
+// + l % 16 of the block has a positive pre-activation; the word sits in row
+// REC_M + w, column l.  The quarter-lane and split-actor kernels write one
+// word per env and quarter k, in row REC_M + k of the env's column: bit
+// 8 n + r for layer-1 neuron 16 n + 4 k + r, bit 8 n + 4 + r for layer 2
+// (quarter_mask).
 // The 128 history features of o_t are not stored per step: they are the
 // actions of the 32 previous steps.  After the n step records of a segment
 // comes its action tape: per 64-env block, (NH + n) slots of NA rows, slot s

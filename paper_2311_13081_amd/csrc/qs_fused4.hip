@@ -35,10 +35,11 @@ typedef __bf16 bf8q __attribute__((ext_vector_type(8)));
 // Actor for the wave's 16 envs.  F: this lane's 37 layer-1 operands.  Returns
 // z3 (pre-tanh) of this lane's env in every lane.  When rz1/rz2 are given,
 // writes the layer pre-activations (64 rows of the blocked record; the lane
-// offset rec_lane_off addresses row 4 lg of this lane's env).
+// offset rec_lane_off addresses row 4 lg of this lane's env) and returns the
+// lane's ReLU mask word (quarter_mask) in zmask.
 __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA],
                                float* __restrict__ rz1, float* __restrict__ rz2, int N,
-                               int env0, uint32_t rec_lane_off) {
+                               int env0, uint32_t rec_lane_off, uint32_t& zmask) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   // bias tiles enter as the accumulator input of each chain's first product
   f4q acc1[4];
@@ -95,6 +96,7 @@ __device__ inline void actor_q(const float* lds, const float F[Q_C], float z3[NA
   for (int n2 = 0; n2 < 4; ++n2)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc2[n2][r] = relu_bits(acc2[n2][r]);
+  zmask = rz1 ? quarter_mask(acc1, acc2) : 0u;
   layer3_q(lds, acc2, z3);
 }
 
@@ -161,10 +163,11 @@ __device__ inline bf8q relu_pack(const f4q& lo, const f4q& hi) {
   return v;
 }
 
-// Same contract as actor_q, bf16 operands.
+// Same contract as actor_q, bf16 operands (the mask from the fp32
+// accumulators).
 __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[NA],
                                 float* __restrict__ rz1, float* __restrict__ rz2, int N,
-                                int env0, uint32_t rec_lane_off) {
+                                int env0, uint32_t rec_lane_off, uint32_t& zmask) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   const __bf16* h = reinterpret_cast<const __bf16*>(lds);
   f4q acc1[4];
@@ -212,6 +215,7 @@ __device__ inline void actor_qb(const float* lds, const float F[Q_C], float z3[N
 #pragma unroll
       for (int r = 0; r < 4; ++r) rz2[(size_t)(16 * n2 + r) * RB + rec_lane_off] = acc2[n2][r];
   }
+  zmask = rz1 ? quarter_mask(acc1, acc2) : 0u;
   f4q acc3;
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc3[r] = lg == 0 ? lds[QB_B3 + r] : 0.0f;
@@ -333,16 +337,17 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     quarter_state_features<EXTRAS>(c, (uint32_t)e, (uint32_t)ep, t_ep, k, x, F, sp);
     float* rt = rec_on ? ra.base + rec_step(rt_step, N) : nullptr;
     float z3[NA];
+    uint32_t zmask;
     // per-lane part of record addresses, recomputed every step (see opaque())
     const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
     const uint32_t koff = opaque((uint32_t)(rb_at(e, REC_F) + k * RB));
     const uint32_t roff = opaque((uint32_t)rb_at(e, REC_F));
     if (BF16)
       actor_qb(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
-               rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff);
+               rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff, zmask);
     else
       actor_q(lds, F, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
-              rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff);
+              rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, N, env0, zoff, zmask);
     float a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
@@ -364,6 +369,7 @@ k_fused4(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       for (int i = 0; i < NS; ++i)
         if ((i & 3) == k) rt[(size_t)(REC_X + i) * RB + roff] = x[i];
       rt[(size_t)REC_A * RB + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+      rt[(size_t)REC_M * RB + koff] = __uint_as_float(zmask);
     }
     float u[NA];
 #pragma unroll

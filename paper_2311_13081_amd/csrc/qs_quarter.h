@@ -64,6 +64,23 @@ __device__ inline void quarter_state_features(const DevCfg& c, uint32_t e, uint3
                                                                     : sf[4 * cc + 3];
 }
 
+// ReLU mask word of a quarter-lane record (row REC_M + k of the lane's env,
+// k its quarter): bit 8 n + r is set when layer-1 neuron 16 n + 4 k + r of
+// the env has a positive pre-activation, bit 8 n + 4 + r the same for layer
+// 2.  z1, z2: the lane's result tiles, before or after the ReLU (z > 0 and
+// relu(z) > 0 agree, NaN included).
+__device__ inline uint32_t quarter_mask(const f4q z1[4], const f4q z2[4]) {
+  uint32_t m = 0u;
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      m |= (z1[n][r] > 0.0f ? 1u : 0u) << (8 * n + r);
+      m |= (z2[n][r] > 0.0f ? 1u : 0u) << (8 * n + 4 + r);
+    }
+  return m;
+}
+
 // Layer 3 from the four layer-2 result tiles acc2[n2] (ReLU applied): returns
 // z3 (pre-tanh) of the lane's env in all 4 of its lanes.
 __device__ inline void layer3_q(const float* lds, const f4q acc2[4], float z3[NA]) {

@@ -20,11 +20,13 @@ namespace qs {
 // Layers 1 and 2 for tile w of the workgroup's 16 envs, exchange through
 // xz1/xz2 ([tile][lane]), layer 3 in every wave.  When rz1/rz2 are given,
 // writes this wave's tile of the layer pre-activations to the record (rows
-// 16 w + 4 lg + r; rec_lane_off addresses row 4 lg of this lane's env).
+// 16 w + 4 lg + r; rec_lane_off addresses row 4 lg of this lane's env) and
+// returns the lane's ReLU mask word (quarter_mask, from the exchanged tiles,
+// the same in every wave) in zmask.
 __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz1, f4q* xz2,
                                    float z3[NA], float* __restrict__ rz1,
                                    float* __restrict__ rz2, bool rec_lane,
-                                   uint32_t rec_lane_off) {
+                                   uint32_t rec_lane_off, uint32_t& zmask) {
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   const int w = threadIdx.x >> 6;
   f4q acc1;
@@ -71,6 +73,7 @@ __device__ inline void actor_split(const float* lds, const float F[Q_C], f4q* xz
   f4q z2[4];
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) z2[n2] = xz2[n2 * 64 + lane];
+  zmask = rz1 ? quarter_mask(z1, z2) : 0u;
   layer3_q(lds, z2, z3);
 }
 
@@ -183,8 +186,9 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
     float* rt = rec_on ? ra.base + rec_step(rt_step, N) : nullptr;
     const uint32_t zoff = opaque((uint32_t)(rb_at(env0 + j, REC_F) + 4 * k * RB));
     float z3[NA];
+    uint32_t zmask;
     actor_split(lds, F, xz1, xz2, z3, rec_on ? rt + (size_t)REC_Z1 * RB : nullptr,
-                rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, active, zoff);
+                rec_on ? rt + (size_t)REC_Z2 * RB : nullptr, active, zoff, zmask);
     float a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = tanh_act(z3[i]);
@@ -205,6 +209,7 @@ k_split(DevCfg c, SimBufs b, const float* __restrict__ W, int T, int t_base,
       for (int i = 0; i < NS; ++i)
         if ((i & 3) == k) rt[(size_t)(REC_X + i) * RB + roff] = x[i];
       rt[(size_t)REC_A * RB + koff] = k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+      rt[(size_t)REC_M * RB + koff] = __uint_as_float(zmask);
     }
     float u[NA];
 #pragma unroll
