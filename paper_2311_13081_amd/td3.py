@@ -55,6 +55,10 @@ class TD3Config:
     expl_factor: float = 0.8
     expl_target: float = 0.1
     recalc_rewards: bool = True
+    # the learner's update replayed from two captured HIP graphs (critic
+    # only; critic, actor and targets); the same arithmetic as the eager
+    # update, whose random draws stay outside the graphs
+    graph_updates: bool = True
     eval_every: int = 10_000
     eval_envs: int = 256
     eval_steps: int = 500
@@ -206,6 +210,110 @@ def evaluate(ev: QuadSim, flat: torch.Tensor, steps: int, seed: int):
     return length.float(), ret
 
 
+class Learner:
+    """One TD3 update (Fujimoto et al.): twin critics regressed on the
+    clipped double-Q target with target-policy smoothing, and every
+    `policy_delay`-th update the actor step and the Polyak update of the
+    targets.  The batch indices and the smoothing noise are drawn outside
+    the update (idx, eps), so the same update runs eagerly or replayed from
+    a captured graph with identical random streams.  With graphs, the
+    update's kernels are captured once per variant (critic only; critic,
+    actor and targets) after two eager warm-up updates whose effect on the
+    parameters and optimiser states is undone before the capture."""
+
+    def __init__(self, cfg, actor, critics, actor_t, critics_t, buf, dev):
+        self.cfg, self.buf = cfg, buf
+        self.actor, self.critics, self.actor_t, self.critics_t = actor, critics, actor_t, critics_t
+        self.opt_a = torch.optim.Adam(actor.parameters(), lr=cfg.lr_actor, capturable=True)
+        self.opt_c = torch.optim.Adam(critics.parameters(), lr=cfg.lr_critic, capturable=True)
+        self.online = list(actor.parameters()) + list(critics.parameters())
+        self.target = list(actor_t.parameters()) + list(critics_t.parameters())
+        self.idx = torch.zeros(cfg.batch, dtype=torch.long, device=dev)
+        self.eps = torch.zeros(cfg.batch, 4, device=dev)
+        self.graphs = None
+
+    def draw(self, gen):
+        """The batch indices and the target-policy noise of one update."""
+        torch.randint(0, self.buf.size, (self.cfg.batch,), device=self.idx.device, generator=gen,
+                      out=self.idx)
+        torch.randn(self.eps.shape, device=self.eps.device, generator=gen, out=self.eps)
+
+    def _update(self, do_actor):
+        cfg, b = self.cfg, self.buf
+        i = self.idx
+        boa, boc, ba, br, bnoa, bnoc, bterm = (b.oa[i], b.oc[i], b.a[i], b.r[i], b.noa[i],
+                                               b.noc[i], b.term[i])
+        with torch.no_grad():
+            eps = (self.eps * cfg.target_noise).clamp(-cfg.target_noise_clip,
+                                                     cfg.target_noise_clip)
+            na = (self.actor_t(bnoa) + eps).clamp(-1.0, 1.0)
+            q1t, q2t = self.critics_t(bnoc, na)
+            y = br + cfg.gamma * (1.0 - bterm) * torch.minimum(q1t, q2t)
+        q1, q2 = self.critics(boc, ba)
+        loss_c = ((q1 - y) ** 2).mean() + ((q2 - y) ** 2).mean()
+        self.opt_c.zero_grad(set_to_none=True)
+        loss_c.backward()
+        self.opt_c.step()
+        if do_actor:
+            q, _ = self.critics(boc, self.actor(boa))
+            loss_a = -q.mean()
+            self.opt_a.zero_grad(set_to_none=True)
+            loss_a.backward()
+            self.opt_a.step()
+            with torch.no_grad():
+                torch._foreach_lerp_(self.target, self.online, cfg.tau)
+
+    def _state(self):
+        ts = self.online + self.target
+        for opt in (self.opt_a, self.opt_c):
+            for st in opt.state.values():
+                ts += [v for v in st.values() if torch.is_tensor(v)]
+        return ts
+
+    def _capture(self):
+        state = self._state()
+        saved = [t.detach().clone() for t in state]
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for do_actor in (False, True, False, True):
+                self._update(do_actor)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.no_grad():
+            for t, v in zip(state, saved):
+                t.copy_(v)
+            # optimiser states the warm-up created (the actor's, when the
+            # first update was a critic update) go back to Adam's initial
+            # state: zero moments, zero steps
+            known = {id(t) for t in state}
+            for t in self._state():
+                if id(t) not in known:
+                    t.zero_()
+        self.graphs = {}
+        for do_actor in (False, True):
+            g = torch.cuda.CUDAGraph()
+            self.opt_a.zero_grad(set_to_none=True)
+            self.opt_c.zero_grad(set_to_none=True)
+            with torch.cuda.graph(g):
+                self._update(do_actor)
+            self.graphs[do_actor] = g
+        torch.cuda.synchronize()
+
+    def update(self, gen, do_actor):
+        self.draw(gen)
+        if not self.cfg.graph_updates:
+            self._update(do_actor)
+            return
+        if self.graphs is None:
+            # the first update runs eagerly (it creates the optimiser
+            # states), the later ones replay the graphs
+            self._update(do_actor)
+            self._capture()
+            return
+        self.graphs[do_actor].replay()
+
+
 def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
     """Runs TD3 with the curriculum.  log: callable receiving each evaluation
     record (dict) as it is made; stop_after(record) -> True ends the run.
@@ -227,11 +335,8 @@ def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
     critics_t.load_state_dict(critics.state_dict())
     for p in list(actor_t.parameters()) + list(critics_t.parameters()):
         p.requires_grad_(False)
-    opt_a = torch.optim.Adam(actor.parameters(), lr=cfg.lr_actor, fused=True)
-    opt_c = torch.optim.Adam(critics.parameters(), lr=cfg.lr_critic, fused=True)
-    online = list(actor.parameters()) + list(critics.parameters())
-    target = list(actor_t.parameters()) + list(critics_t.parameters())
     buf = Replay(cfg.total_steps, dev)
+    learner = Learner(cfg, actor, critics, actor_t, critics_t, buf, dev)
     flat = torch.empty(13828, dtype=torch.float32, device=dev)
     records = []
     N = cfg.n_envs
@@ -279,26 +384,7 @@ def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
             while update_credit >= 1.0:
                 update_credit -= 1.0
                 n_updates += 1
-                boa, boc, ba, br, bnoa, bnoc, bterm = buf.sample(cfg.batch, gen)
-                with torch.no_grad():
-                    eps = (torch.randn(ba.shape, device=dev, generator=gen) * cfg.target_noise
-                           ).clamp(-cfg.target_noise_clip, cfg.target_noise_clip)
-                    na = (actor_t(bnoa) + eps).clamp(-1.0, 1.0)
-                    q1t, q2t = critics_t(bnoc, na)
-                    y = br + cfg.gamma * (1.0 - bterm) * torch.minimum(q1t, q2t)
-                q1, q2 = critics(boc, ba)
-                loss_c = ((q1 - y) ** 2).mean() + ((q2 - y) ** 2).mean()
-                opt_c.zero_grad(set_to_none=True)
-                loss_c.backward()
-                opt_c.step()
-                if n_updates % cfg.policy_delay == 0:
-                    q, _ = critics(boc, actor(boa))
-                    loss_a = -q.mean()
-                    opt_a.zero_grad(set_to_none=True)
-                    loss_a.backward()
-                    opt_a.step()
-                    with torch.no_grad():
-                        torch._foreach_lerp_(target, online, cfg.tau)
+                learner.update(gen, n_updates % cfg.policy_delay == 0)
         if step % cfg.eval_every < N or step >= cfg.total_steps:
             length, ret = evaluate(ev, actor.flat(flat), cfg.eval_steps, seed=7)
             rec = dict(step=step, eval_len_mean=float(length.mean()),

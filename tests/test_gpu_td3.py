@@ -73,3 +73,49 @@ def test_td3_without_recalculation_keeps_old_rewards(td3, oracle_lib):
     late = ids >= 2000   # added under the final constants
     assert err[late].max() < 1e-5
     assert (err[~late] > 1e-4).mean() > 0.5
+
+
+def test_graph_updates_match_eager_updates(td3):
+    """The learner's update replayed from the captured graphs (critic only;
+    critic, actor and targets) against the same update run eagerly, from the
+    same networks, replay contents and random streams: eight updates in
+    turn, every replay checked against the eager result, with the other
+    learner's eager work between the replays."""
+    import copy
+    import dataclasses
+    t = td3
+    dev = torch.device("cuda")
+    torch.manual_seed(0)
+    cfg = t.TD3Config(total_steps=4096)
+    buf = t.Replay(4096, dev)
+    g = torch.Generator(device=dev).manual_seed(1)
+    n = 4096
+    buf.add(torch.randn(n, 146, device=dev, generator=g), torch.randn(n, 28, device=dev, generator=g),
+            torch.rand(n, 4, device=dev, generator=g) * 2 - 1, torch.randn(n, device=dev, generator=g),
+            torch.randn(n, 146, device=dev, generator=g), torch.randn(n, 28, device=dev, generator=g),
+            (torch.rand(n, device=dev, generator=g) < 0.05).float(),
+            torch.randn(17, n, device=dev, generator=g))
+    nets = (t.Actor().to(dev), t.Critics(cfg.critic_hidden).to(dev))
+    learners, gens = [], []
+    for graph in (False, True):
+        a, c = copy.deepcopy(nets[0]), copy.deepcopy(nets[1])
+        at, ct = copy.deepcopy(a), copy.deepcopy(c)
+        for p in list(at.parameters()) + list(ct.parameters()):
+            p.requires_grad_(False)
+        learners.append(t.Learner(dataclasses.replace(cfg, graph_updates=graph), a, c, at, ct,
+                                  buf, dev))
+        gens.append(torch.Generator(device=dev).manual_seed(7))
+    worst = 0.0
+    for u in range(1, 9):
+        do_actor = u % cfg.policy_delay == 0
+        for lr, gen in zip(learners, gens):
+            lr.update(gen, do_actor)
+        torch.cuda.synchronize()
+        pe = [p.detach() for p in learners[0].online + learners[0].target]
+        pg = [p.detach() for p in learners[1].online + learners[1].target]
+        for x, y in zip(pe, pg):
+            d = float((x - y).abs().max()) / max(float(x.abs().max()), 1e-30)
+            worst = max(worst, d)
+            assert d <= 1e-6, (u, d)
+    assert learners[1].graphs is not None
+    print(f"graph vs eager updates: worst relative parameter difference {worst:.1e}")
