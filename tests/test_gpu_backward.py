@@ -56,7 +56,14 @@ def gpu_grad(sim, W, T, dR=None, dS=None):
     return np_(ga).astype(np.float64), np_(gp).astype(np.float64).T
 
 
-@pytest.mark.parametrize("n,T,K", [(64, 20, 8), (100, 16, 16), (257, 33, 5)])
+# 64, 100, 257 envs: split-actor forward and split reverse sweep; 5000 envs:
+# split-actor forward records read by the quarter-lane reverse sweep.  Every
+# env meets max(1e-3, 4 x its own FP64 envelope) (grad_envelope): among 5000
+# randomised bodies a few spin fast enough under this policy that the FP64
+# parameter gradient itself moves by up to about 1e-3 under a float32-sized
+# change of the start state (measured: the worst env's error 9.9e-4 against
+# its envelope 9.9e-4; median error 4e-7).
+@pytest.mark.parametrize("n,T,K", [(64, 20, 8), (100, 16, 16), (257, 33, 5), (5000, 24, 8)])
 def test_backward_matches_oracle_adjoint(pkg, oracle_lib, n, T, K):
     cfg, sim, ref, th = setup(pkg, oracle_lib, n, T, K, dr=1)
     W = wl.random_actor(4)
@@ -65,13 +72,19 @@ def test_backward_matches_oracle_adjoint(pkg, oracle_lib, n, T, K):
     dS = rng.normal(size=(T + 1, 17, n)) * 1e-2
     dS[:, 13:17] *= 1e-4
     ga, gp = gpu_grad(sim, W, T, dR, dS)
-    J, gW, gth = ref.grad(W, T, dR=dR, dS=np.transpose(dS, (0, 2, 1)), nthreads=4)
+    dSo = np.transpose(dS, (0, 2, 1))
+    env_a, env_p, (J, gW, gth) = grad_envelope(ref, W, T, dR=dR, dS=dSo, nthreads=8)
     ea = np.linalg.norm(ga - gW) / np.linalg.norm(gW)
     sc = param_scale(cfg, th.T.astype(np.float64))
     ep = param_grad_err(gp, gth, sc)
-    print(f"n={n} T={T} K={K}: actor rel err {ea:.2e}, params max rel err {ep.max():.2e}")
+    bar = np.maximum(GRAD_TOL, GRAD_ENVELOPE_FACTOR * env_p)
+    w = int(np.argmax(ep / bar))
+    print(f"n={n} T={T} K={K}: actor rel err {ea:.2e} (FP64 envelope {env_a:.2e}), params "
+          f"max rel err {ep.max():.2e} (env {int(np.argmax(ep))}, FP64 envelope there "
+          f"{env_p[int(np.argmax(ep))]:.2e}), median {np.median(ep):.2e}; worst err/bar "
+          f"{float(ep[w] / bar[w]):.2f}")
     assert ea < GRAD_TOL
-    assert ep.max() < GRAD_TOL
+    assert np.all(ep <= bar), np.nonzero(ep > bar)[0]
     sim.close()
 
 
