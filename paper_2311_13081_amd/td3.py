@@ -56,9 +56,12 @@ class TD3Config:
     expl_target: float = 0.1
     recalc_rewards: bool = True
     # the learner's update replayed from two captured HIP graphs (critic
-    # only; critic, actor and targets); the same arithmetic as the eager
-    # update, whose random draws stay outside the graphs
+    # only; critic, actor and targets), and the environment step with its
+    # bookkeeping from two more (the policy's action; the step, replay
+    # insert, restarts and next observation); the same arithmetic as the
+    # eager loop, whose random draws stay outside the graphs
     graph_updates: bool = True
+    graph_env: bool = True
     eval_every: int = 10_000
     eval_envs: int = 256
     eval_steps: int = 500
@@ -172,6 +175,22 @@ class Replay:
         self.a[idx], self.r[idx], self.term[idx] = a, r, term
         self.s_next[:, idx] = s_next
         self.a_soa[:, idx] = a.T
+        self.pos = (self.pos + n) % self.cap
+        self.size = min(self.size + n, self.cap)
+
+    def add_at(self, pos, ar, oa, oc, a, r, noa, noc, term, s_next):
+        """add() with the insert position in a device scalar (pos, advanced
+        here) instead of on the host, so the insert can be replayed from a
+        graph; ar: arange(n) on the device.  The host's size and pos are
+        brought up to date by advance()."""
+        idx = (ar + pos) % self.cap
+        self.oa[idx], self.oc[idx], self.noa[idx], self.noc[idx] = oa, oc, noa, noc
+        self.a[idx], self.r[idx], self.term[idx] = a, r, term
+        self.s_next[:, idx] = s_next
+        self.a_soa[:, idx] = a.T
+        pos.add_(ar.shape[0]).remainder_(self.cap)
+
+    def advance(self, n):
         self.pos = (self.pos + n) % self.cap
         self.size = min(self.size + n, self.cap)
 
@@ -314,6 +333,87 @@ class Learner:
         self.graphs[do_actor].replay()
 
 
+class EnvLoop:
+    """The training env's side of one TD3 step: the action (uniform during
+    the warm-up, else the policy plus Gaussian exploration noise, clipped),
+    the step, the post-step observations and state into the replay buffer,
+    the restart of finished envs, the episode statistics and the next
+    observation.  With graphs, the policy's action and the rest are replayed
+    from two captured graphs (the noise drawn outside them); the step's
+    graph is captured again after each change of the reward constants, which
+    the step launches take by value."""
+
+    def __init__(self, sim, buf, actor, N, dev, graph):
+        self.sim, self.buf, self.actor, self.N, self.graph = sim, buf, actor, N, graph
+        self.a = torch.zeros(N, 4, device=dev)
+        self.u = torch.zeros(N, 4, device=dev)
+        self.sigma = torch.zeros((), device=dev)
+        o = sim.observe()
+        self.oa, self.oc = o["actor"].T.contiguous(), o["critic"].T.contiguous()
+        self.ep_len_sum = torch.zeros((), device=dev)
+        self.ep_count = torch.zeros((), device=dev)
+        self.pos = torch.zeros((), dtype=torch.long, device=dev)
+        self.ar = torch.arange(N, device=dev)
+        self.g_act = self.g_step = None
+        self.steps = self.act_steps = 0
+
+    def _act(self):
+        with torch.no_grad():
+            self.a.copy_((self.actor(self.oa) + self.sigma * self.u).clamp(-1.0, 1.0))
+
+    def _step(self):
+        sim, buf = self.sim, self.buf
+        r, d = sim.step(actions=self.a.T.contiguous())
+        no = sim.observe()
+        s_next = sim.get_state(parts=("state",))["state"]
+        term = (d & 1).float()
+        buf.add_at(self.pos, self.ar, self.oa, self.oc, self.a, r, no["actor"].T,
+                   no["critic"].T, term, s_next)
+        done = d != 0
+        sim.reset_envs(done)
+        st = sim.get_state(parts=("last_len",))
+        self.ep_len_sum += (st["last_len"].float() * done).sum()
+        self.ep_count += done.sum()
+        o = sim.observe()
+        self.oa.copy_(o["actor"].T)
+        self.oc.copy_(o["critic"].T)
+
+    def constants_changed(self):
+        self.g_step = None
+
+    def _capture(self, fn):
+        # the loop's own eager steps before the first capture initialise
+        # every library the captured work uses
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    def run(self, gen, warm, sigma):
+        """One step: warm = uniform actions; sigma = exploration noise."""
+        if warm:
+            torch.rand(self.a.shape, device=self.a.device, generator=gen, out=self.u)
+            torch.sub(self.u * 2, 1, out=self.a)
+        else:
+            torch.randn(self.u.shape, device=self.u.device, generator=gen, out=self.u)
+            self.sigma.fill_(sigma)
+            if self.graph and self.act_steps >= 2:
+                if self.g_act is None:
+                    self.g_act = self._capture(self._act)
+                self.g_act.replay()
+            else:
+                self._act()
+            self.act_steps += 1
+        if self.graph and self.steps >= 2:
+            if self.g_step is None:
+                self.g_step = self._capture(self._step)
+            self.g_step.replay()
+        else:
+            self._step()
+        self.buf.advance(self.N)
+        self.steps += 1
+
+
 def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
     """Runs TD3 with the curriculum.  log: callable receiving each evaluation
     record (dict) as it is made; stop_after(record) -> True ends the run.
@@ -340,14 +440,11 @@ def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
     flat = torch.empty(13828, dtype=torch.float32, device=dev)
     records = []
     N = cfg.n_envs
-    o = sim.observe()
-    oa, oc = o["actor"].T.contiguous(), o["critic"].T.contiguous()
+    env = EnvLoop(sim, buf, actor, N, dev, cfg.graph_env)
     stage = 0
     sigma = cfg.expl_noise
     n_updates = 0
     update_credit = 0.0
-    ep_len_sum = torch.zeros((), device=dev)
-    ep_count = torch.zeros((), device=dev)
     t0 = time.perf_counter()
     step = 0
     while step < cfg.total_steps:
@@ -357,26 +454,10 @@ def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
             stage = k
             sim.set_reward(**C)
             ev.set_reward(**C)
+            env.constants_changed()
             if cfg.recalc_rewards and buf.size:
                 sim.reward(buf.s_next, buf.a_soa, out=buf.r)
-        with torch.no_grad():
-            if step < cfg.warmup:
-                a = torch.rand(N, 4, device=dev, generator=gen) * 2 - 1
-            else:
-                a = actor(oa) + sigma * torch.randn(N, 4, device=dev, generator=gen)
-                a = a.clamp(-1.0, 1.0)
-        r, d = sim.step(actions=a.T.contiguous())
-        no = sim.observe()
-        s_next = sim.get_state(parts=("state",))["state"]
-        term = (d & 1).float()
-        buf.add(oa, oc, a, r, no["actor"].T, no["critic"].T, term, s_next)
-        done = d != 0
-        sim.reset_envs(done)
-        st = sim.get_state(parts=("last_len",))
-        ep_len_sum += (st["last_len"].float() * done).sum()
-        ep_count += done.sum()
-        o = sim.observe()
-        oa, oc = o["actor"].T.contiguous(), o["critic"].T.contiguous()
+        env.run(gen, step < cfg.warmup, sigma)
         step += N
         # TD3 updates
         if step >= cfg.warmup:
@@ -390,12 +471,12 @@ def train(cfg: TD3Config, log=None, env_overrides=None, stop_after=None):
             rec = dict(step=step, eval_len_mean=float(length.mean()),
                        eval_len_std=float(length.std()), eval_ret_mean=float(ret.mean()),
                        eval_fly_frac=float((length >= cfg.eval_steps).float().mean()),
-                       train_episodes=int(ep_count), train_len_mean=float(ep_len_sum /
-                                                                         ep_count.clamp(min=1)),
+                       train_episodes=int(env.ep_count),
+                       train_len_mean=float(env.ep_len_sum / env.ep_count.clamp(min=1)),
                        updates=n_updates, sigma=sigma, stage=stage,
                        C={kk: C[kk] for kk in cfg.C_factor}, wall_s=time.perf_counter() - t0)
-            ep_len_sum.zero_()
-            ep_count.zero_()
+            env.ep_len_sum.zero_()
+            env.ep_count.zero_()
             records.append(rec)
             if log:
                 log(rec)
