@@ -179,7 +179,10 @@ int sim_step(sim_handle* h, const float* actor, const float* actions, float* rew
  * T <= max_tape_horizon and flags without TERMINATE and AUTORESET, else
  * SIM_E_STATE / SIM_E_INVAL.  A taped rollout runs on the kernel its
  * backward recomputes with (split-actor below 16384 envs with the fp32
- * actor, else quarter-lane), whatever variant is set or tuned. */
+ * actor, one env per lane from 65536 envs with the fp32 actor, else
+ * quarter-lane), whatever variant is set or tuned, and also writes the
+ * backward's records of its last segments (the last one on the split-actor
+ * kernel, else up to four), whose recomputes the next sim_backward skips. */
 int sim_rollout(sim_handle* h, const float* actor, int32_t T, float* rewards, uint8_t* dones,
                 float* states, int32_t record_tape, void* stream);
 
