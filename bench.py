@@ -429,8 +429,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the environment batch is one GPU's share and "
-              "this build has no multi-GPU path (see DESIGN.md for how it would shard).",
-              file=sys.stderr)
+              "the library has no multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2311_13081_amd as pkg

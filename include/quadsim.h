@@ -62,7 +62,7 @@ typedef enum sim_status {
   SIM_E_NOMEM = -2,       /* device allocation failed                            */
   SIM_E_DEVICE = -3,      /* HIP error, no device, or a launch failed            */
   SIM_E_STATE = -4,       /* call not valid in the handle's current state        */
-  SIM_E_UNSUPPORTED = -5  /* option not available in this build                  */
+  SIM_E_UNSUPPORTED = -5  /* option not available for this handle or library    */
 } sim_status;
 
 enum {
