@@ -4,7 +4,7 @@
 //
 // Layout: one env per lane, struct-of-arrays in HBM ([K][N]) so every global
 // access of a wave is a contiguous 256-byte segment.
-#include "qs_device.h"
+#include "qs_actor.h"
 #include "qs_forward.h"
 
 namespace qs {
@@ -148,36 +148,163 @@ __global__ void __launch_bounds__(256) k_plain_obs(DevCfg c, SimBufs b, float* _
   }
 }
 
-// out[NOUT][N] = act(Wl in[NIN][N] + bl), act = ReLU or tanh.  Weights are
-// staged transposed in LDS so every lane reads the same address (broadcast).
-template <int NIN, int NOUT, bool TANH>
-__global__ void __launch_bounds__(256) k_plain_dense(int N, const float* __restrict__ Wl,
-                                                     const float* __restrict__ bl,
-                                                     const float* __restrict__ in,
-                                                     float* __restrict__ out) {
-  __shared__ float sW[NIN * NOUT];
-  __shared__ float sb[NOUT];
-  for (int i = threadIdx.x; i < NIN * NOUT; i += blockDim.x) {
-    const int k = i / NOUT, n = i % NOUT;
-    sW[i] = Wl[n * NIN + k];
-  }
-  for (int i = threadIdx.x; i < NOUT; i += blockDim.x) sb[i] = bl[i];
+// The three actor layers of the plain path on fp32 matrix cores, one 64-env
+// block per wave, in the product order and lane layout of the fused kernel's
+// actor; only the layer outputs go through HBM ([64][N], [64][N], [4][N]).
+// Lanes of envs past the batch load the last env and store nothing.
+//
+// Layer 1, h1[64][N] = ReLU(W1 obs + b1): 147 rank-1 updates per 16-neuron
+// tile with the 4-block 16x16x1 product, the bias first (a constant input 1);
+// B = input k of the lane's env, A = the weights of 16 neurons for all four
+// 16-env blocks.  Result register 4 bb + v of tile n holds neuron 16 n + 4 g
+// + v of env 16 bb + i (lane 16 g + i).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_plain_l1_mfma(int N, const float* __restrict__ W, const float* __restrict__ in,
+                float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float sW[NHID * M_W1_LD];
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int first = blockIdx.x * blockDim.x + threadIdx.x - lane;
+  // every input load in flight before the weights are staged
+  const int e = min(first + lane, N - 1);
+  float xin[NO];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) xin[k] = in[(size_t)k * N + e];
+  __builtin_amdgcn_sched_barrier(0);
+  stage_lds(sW, NHID * M_W1_LD, W, [](int i) {
+    const int r = i / M_W1_LD, k = i % M_W1_LD;
+    return k == 0 ? OFF_B1 + r : k <= NO ? OFF_W1 + r * NO + k - 1 : -1;
+  });
   __syncthreads();
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N) return;
-  float acc[NOUT];
+  if (first >= N) return;
+  const f16 zero16 = {};
+  f16 acc[4];
 #pragma unroll
-  for (int n = 0; n < NOUT; ++n) acc[n] = sb[n];
-  for (int k = 0; k < NIN; ++k) {
-    const float x = in[(size_t)k * N + e];
+  for (int kc = 0; kc < M_W1_LD / 4; ++kc) {
+    f4 w[4];
 #pragma unroll
-    for (int n = 0; n < NOUT; ++n) acc[n] = fmaf(sW[k * NOUT + n], x, acc[n]);
+    for (int n = 0; n < 4; ++n)
+      w[n] = *reinterpret_cast<const f4*>(&sW[(16 * n + li) * M_W1_LD + 4 * kc]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int col = 4 * kc + kk;  // 0: bias, k + 1: input k
+      if (col == 0) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][0], 1.0f, zero16, 0, 0, 0);
+      } else if (col <= NO) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], xin[col - 1], acc[n], 0, 0, 0);
+      }
+    }
   }
 #pragma unroll
-  for (int n = 0; n < NOUT; ++n) out[n * N + e] = TANH ? tanh_act(acc[n]) : fmaxf(acc[n], 0.0f);
+  for (int bb = 0; bb < 4; ++bb) {
+    const int oe = first + 16 * bb + li;
+    if (oe < N)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(16 * n + 4 * lg + v) * N + oe] = relu_bits(acc[n][4 * bb + v]);
+  }
 }
 
-// Dynamics, reward, history push, episode bookkeeping and reset.
+// Layer 2, h2[64][N] = ReLU(W2 h1 + b2): 16x16x4 products, chain (n2, bb)
+// for neurons 16 n2.. and envs 16 bb..; the K-chunk of product (n, v) is
+// the inputs {16 n + 4 g + v} (lane 16 g + i holds input 16 n + 4 g + v of
+// env 16 bb + i), the bias tile the accumulator input of the first product.
+// Result register v of chain (n2, bb): neuron 16 n2 + 4 g + v of env 16 bb + i.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_plain_l2_mfma(int N, const float* __restrict__ W, const float* __restrict__ in,
+                float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float sW[NHID * M_W2_LD];
+  __shared__ __attribute__((aligned(16))) float sb[NHID];
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int first = blockIdx.x * blockDim.x + threadIdx.x - lane;
+  // every input load in flight before the weights are staged: x[n][v][bb]
+  float x[4][4][4];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    const int e = min(first + 16 * bb + li, N - 1);
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[n][v][bb] = in[(size_t)(16 * n + 4 * lg + v) * N + e];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  stage_lds(sW, NHID * M_W2_LD, W, [](int i) {
+    const int r = i / M_W2_LD, k = i % M_W2_LD;
+    return k < NHID ? OFF_W2 + r * NHID + k : -1;
+  });
+  stage_lds(sb, NHID, W, [](int i) { return OFF_B2 + i; });
+  __syncthreads();
+  if (first >= N) return;
+  f4 acc[4][4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const f4 w = *reinterpret_cast<const f4*>(&sW[(16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
+      const f4 b2 = *reinterpret_cast<const f4*>(&sb[16 * n2 + 4 * lg]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          acc[n2][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              w[v], x[n][v][bb], (n == 0 && v == 0) ? b2 : acc[n2][bb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    const int oe = first + 16 * bb + li;
+    if (oe < N)
+#pragma unroll
+      for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(16 * n2 + 4 * lg + v) * N + oe] = relu_bits(acc[n2][bb][v]);
+  }
+}
+
+// Layer 3, act[4][N] = tanh(W3 h2 + b3): the input registers of the fused
+// kernel's layer 3 (register v of (n2, bb) in lane 16 g + i: input 16 n2 + 4 g
+// + v of env 16 bb + i) loaded from h2, then the same 4x4x1 products and
+// cross-lane sums (layer3_one_lane).
+__global__ void __launch_bounds__(256) k_plain_l3_mfma(int N, const float* __restrict__ W,
+                                                       const float* __restrict__ in,
+                                                       float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float sW[NA * M_W2_LD + NA];  // W3 rows, then b3
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int first = blockIdx.x * blockDim.x + threadIdx.x - lane;
+  f4 h[4][4];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    const int e = min(first + 16 * bb + li, N - 1);
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) h[n2][bb][v] = in[(size_t)(16 * n2 + 4 * lg + v) * N + e];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  stage_lds(sW, NA * M_W2_LD, W, [](int i) {
+    const int r = i / M_W2_LD, k = i % M_W2_LD;
+    return k < NHID ? OFF_W3 + r * NHID + k : -1;
+  });
+  stage_lds(sW + NA * M_W2_LD, NA, W, [](int i) { return OFF_B3 + i; });
+  __syncthreads();
+  if (first >= N) return;
+  float z3[NA];
+  layer3_one_lane(sW, 0, NA * M_W2_LD, h, z3);
+  if (first + lane < N)
+#pragma unroll
+    for (int o = 0; o < NA; ++o) out[(size_t)o * N + first + lane] = tanh_act(z3[o]);
+}
+
+// Dynamics, reward, history push, episode bookkeeping and reset.  DIST: the
+// dynamics carry the episode disturbance terms (instantiated as the fused
+// kernel instantiates its dynamics: with the training extras or a set point).
+template <bool DIST>
 __global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
                                                    const float* __restrict__ act,
                                                    float* __restrict__ reward_out,
@@ -197,10 +324,12 @@ __global__ void __launch_bounds__(256) k_plain_dyn(DevCfg c, SimBufs b,
     u[i] = action_to_rpm(c, a[i]);
   }
   Body<float> B = make_body<float>(th);
-  float dist[6];
-  disturbance(c, (uint32_t)e, (uint32_t)b.ep[e], dist);
-  set_disturbance(B, dist);
-  rk4_step<float>(B, c.arm, c.km, c.g, c.dt, (c.flags & F_RENORM_Q) != 0, x, u);
+  if (DIST) {
+    float dist[6];
+    disturbance(c, (uint32_t)e, (uint32_t)b.ep[e], dist);
+    set_disturbance(B, dist);
+  }
+  rk4_step<float, DIST>(B, c.arm, c.km, c.g, c.dt, (c.flags & F_RENORM_Q) != 0, x, u);
   const float r = reward(c, x, a);
   int h = b.head[e];
 #pragma unroll
@@ -362,15 +491,14 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
   const float* act = ext_act;
   if (!ext_act) {
     hipLaunchKernelGGL(k_plain_obs, g, blk, 0, st, c, b, p.obs);
-    hipLaunchKernelGGL((k_plain_dense<NO, NHID, false>), g, blk, 0, st, N, W + OFF_W1, W + OFF_B1,
-                       p.obs, p.h1);
-    hipLaunchKernelGGL((k_plain_dense<NHID, NHID, false>), g, blk, 0, st, N, W + OFF_W2,
-                       W + OFF_B2, p.h1, p.h2);
-    hipLaunchKernelGGL((k_plain_dense<NHID, NA, true>), g, blk, 0, st, N, W + OFF_W3, W + OFF_B3,
-                       p.h2, p.act);
+    hipLaunchKernelGGL(k_plain_l1_mfma, g, blk, 0, st, N, W, p.obs, p.h1);
+    hipLaunchKernelGGL(k_plain_l2_mfma, g, blk, 0, st, N, W, p.h1, p.h2);
+    hipLaunchKernelGGL(k_plain_l3_mfma, g, blk, 0, st, N, W, p.h2, p.act);
     act = p.act;
   }
-  hipLaunchKernelGGL(k_plain_dyn, g, blk, 0, st, c, b, act, reward, done, state_out);
+  const bool ex = (c.flags & (F_DISTURB | F_OBS_NOISE)) != 0 || c.target != nullptr;
+  hipLaunchKernelGGL(ex ? k_plain_dyn<true> : k_plain_dyn<false>, g, blk, 0, st, c, b, act,
+                     reward, done, state_out);
   return hipGetLastError();
 }
 

@@ -347,6 +347,47 @@ def test_plain_graph_equals_eager(pkg):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
+@pytest.mark.parametrize("n", [1000, 64, 17])
+def test_plain_path_matches_fused_mfma_kernel(pkg, n):
+    """The plain path (five kernels, the actor's layers on matrix cores in
+    the fused kernel's product order) against the fused kernel, one step at
+    a time from the same state (the fused kernel's own state after each
+    step), 40 steps with domain randomisation and resets, ragged batches (15
+    full waves and a 40-lane tail, one wave, a 17-lane wave).  Rewards, done
+    flags, counters and the history agree exactly; states and returns to
+    1e-6 relative.  (The two paths compile the shared dynamics into
+    differently contracted code: a few state values per thousand envs differ
+    in the last place, so a wrong neuron, lane or product order in a layer,
+    which moves the action by far more, cannot hide.)"""
+    T = 40
+    flags = wl.F_RENORM_Q | wl.F_TERMINATE | wl.F_AUTORESET
+    cfg = wl.crazyflie_config(n_envs=n, dr_enable=1, flags=flags, max_episode_steps=15)
+    W = wl.xavier_actor(3)
+    fused = make_sim(pkg, cfg, "mfma", 0, False)
+    plain = make_sim(pkg, cfg, "plain", 0, False)
+    af, ap = fused.actor_tensor(W), plain.actor_tensor(W)
+    resets, worst = 0, 0.0
+    for t in range(T):
+        plain.set_state(**fused.get_state())
+        rf, df = fused.step(actor=af)
+        rp, dp = plain.step(actor=ap)
+        rf, rp, df, dp = np_(rf), np_(rp), np_(df), np_(dp)
+        assert np.array_equal(df, dp), t
+        assert np.allclose(rf, rp, rtol=1e-6, atol=1e-7), t
+        sf, sp = fused.get_state(), plain.get_state()
+        for k in ("hist", "t_ep", "episode", "last_len"):
+            assert np.array_equal(np_(sf[k]), np_(sp[k])), (t, k)
+        for k in ("state", "returns"):
+            x, y = np_(sf[k]), np_(sp[k])
+            rel = np.abs(x - y) / np.maximum(np.abs(x), 1.0)
+            worst = max(worst, float(rel.max()))
+            assert rel.max() <= 1e-6, (t, k, float(rel.max()))
+        resets += int((df != 0).sum())
+    assert resets > 0
+    fused.close()
+    plain.close()
+
+
 def test_rollout_continuation_and_graph_replay(pkg):
     """rollout(200) == rollout(100) + rollout(100) bitwise, and a graph
     replayed after set_state sees the new state."""
