@@ -148,10 +148,13 @@ __global__ void __launch_bounds__(256) k_plain_obs(DevCfg c, SimBufs b, float* _
   }
 }
 
-// The three actor layers of the plain path on fp32 matrix cores, one 64-env
-// block per wave, in the product order and lane layout of the fused kernel's
-// actor; only the layer outputs go through HBM ([64][N], [64][N], [4][N]).
-// Lanes of envs past the batch load the last env and store nothing.
+// The three actor layers of the plain path on fp32 matrix cores, in the
+// product order and lane layout of the fused kernel's actor; only the layer
+// outputs go through HBM ([64][N], [64][N], [4][N]).  The hidden layers give
+// each 64-env block two waves, one per half of the neuron tiles (a
+// workgroup of four waves takes 128 envs), so two waves share a SIMD and one
+// wave's loads and stores overlap the other's products.  Lanes of envs past
+// the batch load the last env and store nothing.
 //
 // Layer 1, h1[64][N] = ReLU(W1 obs + b1): 147 rank-1 updates per 16-neuron
 // tile with the 4-block 16x16x1 product, the bias first (a constant input 1);
@@ -163,7 +166,8 @@ k_plain_l1_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
                 float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) float sW[NHID * M_W1_LD];
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int first = blockIdx.x * blockDim.x + threadIdx.x - lane;
+  const int wv = threadIdx.x >> 6, th = wv & 1;  // tiles 2 th, 2 th + 1
+  const int first = blockIdx.x * 128 + 64 * (wv >> 1);
   // every input load in flight before the weights are staged
   const int e = min(first + lane, N - 1);
   float xin[NO];
@@ -177,24 +181,24 @@ k_plain_l1_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
   __syncthreads();
   if (first >= N) return;
   const f16 zero16 = {};
-  f16 acc[4];
+  f16 acc[2];
 #pragma unroll
   for (int kc = 0; kc < M_W1_LD / 4; ++kc) {
-    f4 w[4];
+    f4 w[2];
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
-      w[n] = *reinterpret_cast<const f4*>(&sW[(16 * n + li) * M_W1_LD + 4 * kc]);
+    for (int j = 0; j < 2; ++j)
+      w[j] = *reinterpret_cast<const f4*>(&sW[(16 * (2 * th + j) + li) * M_W1_LD + 4 * kc]);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int col = 4 * kc + kk;  // 0: bias, k + 1: input k
       if (col == 0) {
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][0], 1.0f, zero16, 0, 0, 0);
+        for (int j = 0; j < 2; ++j)
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[j][0], 1.0f, zero16, 0, 0, 0);
       } else if (col <= NO) {
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[n][kk], xin[col - 1], acc[n], 0, 0, 0);
+        for (int j = 0; j < 2; ++j)
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x1f32(w[j][kk], xin[col - 1], acc[j], 0, 0, 0);
       }
     }
   }
@@ -203,10 +207,10 @@ k_plain_l1_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
     const int oe = first + 16 * bb + li;
     if (oe < N)
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          out[(size_t)(16 * n + 4 * lg + v) * N + oe] = relu_bits(acc[n][4 * bb + v]);
+          out[(size_t)(16 * (2 * th + j) + 4 * lg + v) * N + oe] = relu_bits(acc[j][4 * bb + v]);
   }
 }
 
@@ -221,7 +225,8 @@ k_plain_l2_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
   __shared__ __attribute__((aligned(16))) float sW[NHID * M_W2_LD];
   __shared__ __attribute__((aligned(16))) float sb[NHID];
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int first = blockIdx.x * blockDim.x + threadIdx.x - lane;
+  const int wv = threadIdx.x >> 6, th = wv & 1;  // tiles n2 = 2 th, 2 th + 1
+  const int first = blockIdx.x * 128 + 64 * (wv >> 1);
   // every input load in flight before the weights are staged: x[n][v][bb]
   float x[4][4][4];
 #pragma unroll
@@ -240,19 +245,20 @@ k_plain_l2_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
   stage_lds(sb, NHID, W, [](int i) { return OFF_B2 + i; });
   __syncthreads();
   if (first >= N) return;
-  f4 acc[4][4];
+  f4 acc[2][4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
 #pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
+    for (int j = 0; j < 2; ++j) {
+      const int n2 = 2 * th + j;
       const f4 w = *reinterpret_cast<const f4*>(&sW[(16 * n2 + li) * M_W2_LD + 16 * n + 4 * lg]);
       const f4 b2 = *reinterpret_cast<const f4*>(&sb[16 * n2 + 4 * lg]);
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb)
-          acc[n2][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-              w[v], x[n][v][bb], (n == 0 && v == 0) ? b2 : acc[n2][bb], 0, 0, 0);
+          acc[j][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              w[v], x[n][v][bb], (n == 0 && v == 0) ? b2 : acc[j][bb], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -260,10 +266,10 @@ k_plain_l2_mfma(int N, const float* __restrict__ W, const float* __restrict__ in
     const int oe = first + 16 * bb + li;
     if (oe < N)
 #pragma unroll
-      for (int n2 = 0; n2 < 4; ++n2)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          out[(size_t)(16 * n2 + 4 * lg + v) * N + oe] = relu_bits(acc[n2][bb][v]);
+          out[(size_t)(16 * (2 * th + j) + 4 * lg + v) * N + oe] = relu_bits(acc[j][bb][v]);
   }
 }
 
@@ -491,8 +497,9 @@ hipError_t launch_plain_step(const DevCfg& c, const SimBufs& b, const PlainBufs&
   const float* act = ext_act;
   if (!ext_act) {
     hipLaunchKernelGGL(k_plain_obs, g, blk, 0, st, c, b, p.obs);
-    hipLaunchKernelGGL(k_plain_l1_mfma, g, blk, 0, st, N, W, p.obs, p.h1);
-    hipLaunchKernelGGL(k_plain_l2_mfma, g, blk, 0, st, N, W, p.h1, p.h2);
+    const dim3 g2(nblk(N, 128));  // 128 envs per workgroup (two waves per 64-env block)
+    hipLaunchKernelGGL(k_plain_l1_mfma, g2, blk, 0, st, N, W, p.obs, p.h1);
+    hipLaunchKernelGGL(k_plain_l2_mfma, g2, blk, 0, st, N, W, p.h1, p.h2);
     hipLaunchKernelGGL(k_plain_l3_mfma, g, blk, 0, st, N, W, p.h2, p.act);
     act = p.act;
   }
