@@ -347,13 +347,15 @@ def test_plain_graph_equals_eager(pkg):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
-@pytest.mark.parametrize("n", [1000, 64, 17])
+@pytest.mark.parametrize("n", [1000, 64, 17, 1, 129])
 def test_plain_path_matches_fused_mfma_kernel(pkg, n):
     """The plain path (five kernels, the actor's layers on matrix cores in
     the fused kernel's product order) against the fused kernel, one step at
     a time from the same state (the fused kernel's own state after each
     step), 40 steps with domain randomisation and resets, ragged batches (15
-    full waves and a 40-lane tail, one wave, a 17-lane wave).  Rewards, done
+    full waves and a 40-lane tail, one wave, a 17-lane wave, one env, and
+    129 envs: a full 128-env workgroup of the hidden layers and one env in
+    the next, whose second 64-env block is empty).  Rewards, done
     flags, counters and the history agree exactly; states and returns to
     1e-6 relative.  (The two paths compile the shared dynamics into
     differently contracted code: a few state values per thousand envs differ
